@@ -1,0 +1,208 @@
+/*
+ * tdec.h -- C ABI of the MI355X (gfx950) LTE turbo decoder library, libtdec.
+ *
+ * The library decodes LTE turbo code blocks and transport blocks on the GPU.
+ * It implements the decoding function of the paper "Higher aggregation of
+ * gNodeBs in Cloud-RAN architectures via parallel computing" (Sec. IV-B,
+ * "Decoding function", Fig. 4): received data is de-multiplexed into the
+ * systematic and the two parity streams; decoder 1 computes extrinsic LLRs
+ * and passes them (interleaved) to decoder 2, which also takes the
+ * interleaved systematic LLRs and parity 2, and feeds its extrinsic LLRs back
+ * de-interleaved; the loop runs up to a maximum number of iterations and ends
+ * with a hard decision.  The constituent decoders are max-log-MAP (BCJR in
+ * the max-plus semiring) over the 8-state RSC trellis of TS 36.212 5.1.3.2;
+ * code blocks come from the segmentation of TS 36.212 5.1.2 (the paper's
+ * Algorithm 1 caps a block at 6120 payload bits) and carry CRC24B, the
+ * transport block CRC24A (TS 36.212 5.1.1).  A transport block succeeds only
+ * if it passes CRC24A (the paper's Algorithm 2: all code blocks must decode).
+ *
+ * Arithmetic contract (every result is exact; nothing is left to rounding):
+ *   - input LLRs are int16 in units of 1/8 nat, positive meaning bit 1 (the
+ *     paper defines the LLR as log P(1)/P(0)); values outside +-2047 are
+ *     clamped, not rejected;
+ *   - state metrics are int16 max-plus sums; extrinsic values are scaled by
+ *     0.75 with truncation toward zero and clamped to +-2047 before they
+ *     become a-priori values of the other decoder;
+ *   - hard decision: bit = 1 iff the decoder-2 a-posteriori value is > 0;
+ *   - windowed decoding: a code block of K bits is cut into n_windows
+ *     windows of W = K / n_windows trellis steps that run concurrently; a
+ *     window starts its forward (backward) recursion from all-zero metrics,
+ *     or, with win_init = 1 and from the second iteration on, from the metric
+ *     its left (right) neighbour computed at the shared boundary in the
+ *     previous iteration of the same constituent decoder; window 0 always
+ *     starts in state 0 and the last window always from the trellis
+ *     termination; n_windows = 1 is exact full-length max-log-MAP;
+ *   - the CRC of a code block is checked over bits F..K-1 (the filler bits are
+ *     known zeros) after each full iteration (CRC24B when the block belongs to
+ *     a transport block of several blocks, CRC24A when it is the only one).
+ *
+ * Memory: "d_" arguments are device pointers (HIP device memory of the
+ * context's device), every other pointer is host memory.  The caller owns
+ * all input and output buffers.  The context owns a workspace allocated by
+ * tdec_create; calls that fit in it allocate nothing.
+ *
+ * Asynchrony: calls validate their arguments on the host, enqueue work on
+ * `stream` and return; outputs are valid once the stream has synchronised.
+ * A context may be used by one host thread at a time and its calls must not
+ * overlap in time on different streams (they share the workspace).
+ *
+ * Errors: on a non-zero return nothing has been enqueued and no output is
+ * written.  A code block that fails its CRC is not an error: it is reported
+ * through crc_ok = 0.
+ */
+#ifndef TDEC_H
+#define TDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TDEC_OK = 0,
+    TDEC_EINVAL = -1,  /* bad pointer, size, K, window count or parameter */
+    TDEC_ERANGE = -2,  /* transport block size out of range */
+    TDEC_ENOMEM = -3,  /* the call does not fit in the context's workspace */
+    TDEC_EDEVICE = -4, /* a HIP runtime error (launch or copy failed) */
+    TDEC_EBUSY = -5    /* reserved */
+} tdec_status;
+
+enum { TDEC_CRC_NONE = 0, TDEC_CRC24A = 1, TDEC_CRC24B = 2 };
+
+/* Decoder parameters. */
+typedef struct {
+    int32_t max_iters;  /* 1..16 full iterations (decoder 1 + decoder 2) */
+    int32_t early_stop; /* 0: run exactly max_iters; 1: stop after the first
+                           iteration whose CRC passes (blocks without CRC never stop early) */
+    int32_t n_windows;  /* windows per code block: must divide K with K/n a multiple of 8;
+                           0 = the library's tuned choice for each K (tdec_pick_windows) */
+    int32_t win_init;   /* 0: windows start from zero metrics every iteration;
+                           1: from the neighbours' previous-iteration boundary metrics */
+} tdec_params;
+
+/* ---------------------------------------------------------------- host-only helpers */
+
+/* Segmentation of a transport block of `tbs` payload bits (TS 36.212 5.1.2):
+ * B = tbs + 24 (CRC24A), C code blocks, L = 24 CRC24B bits per block when
+ * C > 1, Cminus blocks of Kminus bits first, then Cplus blocks of Kplus bits,
+ * F filler bits at the start of block 0.  1 <= tbs <= 1<<20, else ERANGE. */
+typedef struct {
+    int32_t B, C, L, Kplus, Kminus, Cplus, Cminus, F;
+} tdec_seg;
+tdec_status tdec_segment(int32_t tbs, tdec_seg *out);
+
+/* Number of int16 LLRs of a transport block: 3 * sum_r (K_r + 4); -1 if tbs is out of range. */
+int64_t tdec_tb_llr_count(int32_t tbs);
+
+/* The 188 code block sizes (TS 36.212 Table 5.1.3-3), ascending; returns 188. */
+int32_t tdec_k_table(int32_t *out188);
+
+/* QPP interleaver of size K (TS 36.212 5.1.3.2.3): pi[i] = (f1*i + f2*i^2) mod K;
+ * writes K entries to pi (host memory) and the coefficients to f1/f2 (each may be NULL). */
+tdec_status tdec_qpp(int32_t K, int32_t *pi, int32_t *f1, int32_t *f2);
+
+/* ---------------------------------------------------------------- context */
+
+typedef struct tdec_ctx tdec_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * workspace the context allocates (0 = 1 GiB); calls that would need more
+ * return ENOMEM. */
+tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out);
+void tdec_destroy(tdec_ctx *ctx);
+
+/* Window count the library uses for code block size K when
+ * tdec_params.n_windows == 0 (always a valid count for K). */
+int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K);
+
+/* ---------------------------------------------------------------- decoding */
+
+/* One code block of a batch.
+ *   llr_off : element offset (int16 units) of the block's [3][K+4] LLR array
+ *             in d_llr: row 0 systematic d0, row 1 parity 1 d1, row 2 parity 2
+ *             d2, each with the trellis termination LLRs at indices K..K+3 in
+ *             the TS 36.212 5.1.3.2.2 order (d0: x_K z_K+1 x'_K z'_K+1,
+ *             d1: z_K x_K+2 z'_K x'_K+2, d2: x_K+1 z_K+2 x'_K+1 z'_K+2);
+ *             the first F entries of rows 0 and 1 (filler) are ignored;
+ *   bits_off: byte offset in d_bits where the block's K-F-L payload bits are
+ *             written packed MSB first (L = 24 when crc != NONE, else 0);
+ *   K       : code block size, one of the 188 table sizes;
+ *   F       : filler bits at the start of the block, 0 <= F < K;
+ *   crc     : TDEC_CRC_NONE / TDEC_CRC24A / TDEC_CRC24B (K - F >= 24 when not NONE). */
+typedef struct {
+    int64_t llr_off;
+    int64_t bits_off;
+    int32_t K;
+    int16_t F;
+    int8_t crc;
+    int8_t rsv;
+} tdec_cb_desc;
+
+/* Decode n_cb independent code blocks in one launch.
+ *   desc     : n_cb descriptors in HOST memory (the library plans the launch
+ *              from them; a repeated identical batch reuses its plan);
+ *   d_llr    : int16 LLRs (device);
+ *   d_bits   : packed payload output (device); may be NULL;
+ *   d_crc_ok : n_cb bytes, 1 if the block's CRC passed (1 for crc NONE);
+ *   d_iters  : n_cb bytes, iterations run (max_iters unless it stopped early).
+ * n_cb = 0 is a no-op.  EINVAL for a bad descriptor, bad parameters or a
+ * window count that does not suit some K; ENOMEM if the batch needs more
+ * workspace than the context holds. */
+tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                            const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                            uint8_t *d_crc_ok, uint8_t *d_iters, void *stream);
+
+/* Result of one transport block (device memory, written by the decoder). */
+typedef struct {
+    int32_t tb_ok;          /* 1 iff the reassembled payload passes CRC24A */
+    int32_t max_iters_used; /* largest iteration count over the code blocks */
+    int32_t C;              /* number of code blocks */
+    int32_t rsv;
+    uint8_t cb_ok[64];      /* per code block CRC flag */
+    uint8_t cb_iters[64];   /* per code block iteration count */
+} tdec_tb_result;
+
+/* Decode one transport block of `tbs` payload bits (C <= 64, i.e. tbs <= 391656).
+ *   d_llr  : the C blocks' [3][K_r+4] LLR arrays back to back (K- blocks first),
+ *            tdec_tb_llr_count(tbs) int16 values;
+ *   d_bits : ceil(tbs/8) bytes, the payload packed MSB first (CRC24A removed);
+ *   d_res  : one tdec_tb_result (device). */
+tdec_status tb_decode(tdec_ctx *ctx, const int16_t *d_llr, int32_t tbs, const tdec_params *params,
+                      uint8_t *d_bits, tdec_tb_result *d_res, void *stream);
+
+/* Decode n_tb transport blocks in one launch.
+ *   tbs, llr_off, bits_off : n_tb entries each, HOST memory: payload size,
+ *                            element offset of the TB's LLRs in d_llr, byte
+ *                            offset of its packed payload in d_bits;
+ *   d_res                  : n_tb results (device). */
+tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
+                            const int64_t *bits_off, const int16_t *d_llr,
+                            const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
+                            void *stream);
+
+/* ---------------------------------------------------------------- encoding */
+/* The rate-1/3 turbo encoder of the paper's encoding function (Sec. IV-B,
+ * Fig. 3): two RSC encoders separated by the QPP interleaver, output
+ * (systematic, parity 1, parity 2) with trellis termination. */
+
+/* Encode n_cb code blocks.  For block i, desc[i] (host memory) gives K, F and
+ * crc as for decoding; its K-F-L payload bits are read packed MSB first from
+ * d_payload + bits_off; the encoder puts F zero filler bits in front, appends
+ * the block CRC when crc != NONE (computed over the K-24 bits before it), and
+ * writes the coded bits as one byte per bit (0/1) to d_coded + llr_off in the
+ * same [3][K+4] layout the decoder reads (filler positions of rows 0/1 hold 0). */
+tdec_status cb_encode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                            const uint8_t *d_payload, uint8_t *d_coded, void *stream);
+
+/* Encode one transport block: CRC24A over the tbs payload bits (packed MSB
+ * first), segmentation, CRC24B per block when C > 1, filler, turbo encoding.
+ * d_coded receives tdec_tb_llr_count(tbs) bytes (0/1), blocks back to back. */
+tdec_status tb_encode(tdec_ctx *ctx, const uint8_t *d_payload, int32_t tbs, uint8_t *d_coded,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,41 @@
+"""Build libtdec.so (the gfx950 turbo decoder library) in the package directory.
+
+hipcc compiles the HIP kernels and the C-ABI host code into one shared
+library.  Packed-FP32 instruction selection is disabled for all device code.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libtdec.so")
+SOURCES = ["csrc/api.cpp", "csrc/tables.cpp", "csrc/dec_kernels.hip", "csrc/enc_kernels.hip"]
+ARCH = os.environ.get("TDEC_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    p = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    return p if os.path.exists(p) else "hipcc"
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Wall", "-Wno-unused-result",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include")]
+    cmd += [os.path.join(HERE, s) for s in SOURCES]
+    cmd += ["-o", tmp]
+    r = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr[-8000:])
+    if verbose and r.stderr:
+        print(r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

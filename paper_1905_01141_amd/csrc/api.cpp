@@ -1,0 +1,599 @@
+// api.cpp -- the C ABI of libtdec (include/tdec.h): argument checking,
+// launch planning, workspace management and kernel launches.
+//
+// A decode call becomes one persistent launch of the decode kernel over a
+// list of work items (code blocks of one size grouped so that their windows
+// fill the work group's lanes and their extrinsic arrays fit the LDS budget),
+// plus, for transport blocks, one launch of the assembly kernel.  Plans are
+// cached by the content of the request, so a repeated batch costs no host
+// planning and no upload.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tdec.h"
+#include "tdec_internal.h"
+
+using namespace tdec;
+
+namespace {
+
+constexpr int kPlanSlots = 8;
+constexpr size_t kPlanSlotBytes = 8u << 20;
+constexpr int kLdsPerCu = 160 * 1024;
+
+struct PlanSlot {
+    std::string key;
+    char *d_buf = nullptr;   // device copy of the plan
+    char *h_buf = nullptr;   // pinned staging
+    hipEvent_t ev = nullptr; // completion of the last upload from h_buf
+    uint64_t last_use = 0;
+    // decoded plan
+    int n_items = 0, grid = 0, wg = 0, lds = 0;
+    int64_t stride = 0;
+    int n_cb = 0, n_tb = 0;
+    size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
+};
+
+}  // namespace
+
+struct tdec_ctx {
+    int device = 0;
+    int num_cus = 0;
+    size_t budget = 0;
+    uint32_t *d_crc_tab = nullptr;
+    char *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    uint32_t *d_hard = nullptr;
+    size_t hard_words_cap = 0;
+    uint8_t *d_ok = nullptr, *d_it = nullptr;
+    size_t flags_cap = 0;
+    uint8_t *d_encbuf = nullptr;
+    size_t encbuf_bytes = 0;
+    PlanSlot slots[kPlanSlots];
+    uint64_t clock = 0;
+    int lds_budget = 27 * 1024;  // LDS bytes per work group the planner aims for
+    int grid_cap = 0;            // 0: occupancy-derived persistent grid
+};
+
+namespace {
+
+int slot_bytes_for(int32_t K)
+{
+    const int e = K + ((K - 1) >> 6);             // padded int16 entries
+    const int ewords = (e + 1) / 2;
+    const int bytes = (ewords + (int)hard_words(K)) * 4;
+    return (bytes + 15) & ~15;
+}
+
+bool params_ok(const tdec_params *p)
+{
+    return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
+           p->early_stop <= 1 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 1;
+}
+
+int32_t pick_windows(int32_t K)
+{
+    // Aim for windows of ~192 steps (the shape at which 32 windows of a
+    // 6144-bit block fill a wave): the largest window count with W a
+    // multiple of 8 and W >= 192, else full length.
+    int best = 1;
+    for (int nw = 1; nw <= 64; ++nw)
+        if (K % nw == 0 && (K / nw) % 8 == 0 && K / nw >= 192) best = nw;
+    return best;
+}
+
+bool windows_ok(int32_t K, int32_t nw)
+{
+    return nw >= 1 && nw <= kMaxWgThreads && K % nw == 0 && (K / nw) % 8 == 0;
+}
+
+struct CbReq {
+    int32_t K, nw;
+    DecCb cb;
+};
+
+// Build the decode plan (items + code block list) from a request.
+tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot &ps,
+                              std::vector<char> &blob, const std::vector<TbItem> *tbs)
+{
+    // group by (K, nw), biggest blocks first
+    std::vector<int> order(reqs.size());
+    for (size_t i = 0; i < reqs.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (reqs[a].K != reqs[b].K) return reqs[a].K > reqs[b].K;
+        return reqs[a].nw < reqs[b].nw;
+    });
+    int max_nw = 1;
+    for (auto &r : reqs) max_nw = std::max(max_nw, r.nw);
+    const int wg = std::min(kMaxWgThreads, ((max_nw + 63) / 64) * 64);
+    std::vector<DecItem> items;
+    std::vector<DecCb> cbl;
+    cbl.reserve(reqs.size());
+    int lds = 0;
+    int64_t stride = 0;
+    size_t i = 0;
+    while (i < order.size()) {
+        const CbReq &r0 = reqs[order[i]];
+        const int K = r0.K, nw = r0.nw, W = K / nw;
+        const int sb = slot_bytes_for(K);
+        int cap = std::min(wg / nw, kMaxSlotsPerWg);
+        cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
+        DecItem it;
+        it.K = K;
+        it.nw = nw;
+        it.W = W;
+        it.cb0 = (int)cbl.size();
+        int32_t f1, f2;
+        qpp_coeffs(k_index(K), &f1, &f2);
+        it.f1 = f1;
+        it.f2 = f2;
+        it.S = 8;
+        it.lds_slot = sb;
+        it.rsv = 0;
+        int n = 0;
+        while (i < order.size() && n < cap && reqs[order[i]].K == K && reqs[order[i]].nw == nw) {
+            cbl.push_back(reqs[order[i]].cb);
+            ++i;
+            ++n;
+        }
+        it.ncb = n;
+        items.push_back(it);
+        lds = std::max(lds, n * sb);
+        const int lanes = n * nw;
+        const int64_t need = (int64_t)n * K * 6 + (int64_t)(W / it.S) * lanes * 16 +
+                             (((int64_t)(W / it.S) * lanes * 8 + 15) & ~(int64_t)15) +
+                             (int64_t)4 * lanes * 16 + 256;
+        stride = std::max(stride, (need + 255) & ~(int64_t)255);
+    }
+    // persistent grid: as many work groups as can be resident
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(), wg, lds) !=
+            hipSuccess ||
+        occ < 1)
+        occ = std::max(1, kLdsPerCu / std::max(lds, 1));
+    int grid = std::min<int64_t>((int64_t)items.size(), (int64_t)occ * ctx->num_cus);
+    if (ctx->grid_cap > 0) grid = std::min(grid, ctx->grid_cap);
+    const int64_t fit = (int64_t)(ctx->scratch_bytes / (size_t)stride);
+    if (fit < 1) return TDEC_ENOMEM;
+    grid = (int)std::min<int64_t>(grid, fit);
+    grid = std::max(grid, 1);
+
+    // serialise: [items][cbs][tbs]
+    ps.off_items = 0;
+    ps.off_cbs = (items.size() * sizeof(DecItem) + 255) & ~(size_t)255;
+    ps.off_tbs = ps.off_cbs + ((cbl.size() * sizeof(DecCb) + 255) & ~(size_t)255);
+    const size_t ntb = tbs ? tbs->size() : 0;
+    const size_t total = ps.off_tbs + ntb * sizeof(TbItem);
+    if (total > kPlanSlotBytes) return TDEC_ENOMEM;
+    blob.assign(total, 0);
+    memcpy(blob.data() + ps.off_items, items.data(), items.size() * sizeof(DecItem));
+    memcpy(blob.data() + ps.off_cbs, cbl.data(), cbl.size() * sizeof(DecCb));
+    if (ntb) memcpy(blob.data() + ps.off_tbs, tbs->data(), ntb * sizeof(TbItem));
+    ps.n_items = (int)items.size();
+    ps.n_cb = (int)cbl.size();
+    ps.n_tb = (int)ntb;
+    ps.grid = grid;
+    ps.wg = wg;
+    ps.lds = lds;
+    ps.stride = stride;
+    return TDEC_OK;
+}
+
+// Find a cached plan for `key`, or claim the least recently used slot.
+PlanSlot *lookup(tdec_ctx *ctx, const std::string &key, bool *hit)
+{
+    ++ctx->clock;
+    for (auto &s : ctx->slots)
+        if (!s.key.empty() && s.key == key) {
+            s.last_use = ctx->clock;
+            *hit = true;
+            return &s;
+        }
+    PlanSlot *v = &ctx->slots[0];
+    for (auto &s : ctx->slots)
+        if (s.last_use < v->last_use) v = &s;
+    *hit = false;
+    return v;
+}
+
+tdec_status upload(tdec_ctx *ctx, PlanSlot *ps, const std::string &key, const std::vector<char> &blob,
+                   hipStream_t st)
+{
+    if (hipEventSynchronize(ps->ev) != hipSuccess) return TDEC_EDEVICE;
+    memcpy(ps->h_buf, blob.data(), blob.size());
+    if (hipMemcpyAsync(ps->d_buf, ps->h_buf, blob.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        return TDEC_EDEVICE;
+    if (hipEventRecord(ps->ev, st) != hipSuccess) return TDEC_EDEVICE;
+    ps->key = key;
+    ps->last_use = ctx->clock;
+    return TDEC_OK;
+}
+
+tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
+                        const tdec_params *p, uint8_t *d_bits, uint8_t *d_ok, uint8_t *d_it,
+                        bool hard, hipStream_t st)
+{
+    DecArgs a;
+    a.items = (const DecItem *)(ps->d_buf + ps->off_items);
+    a.n_items = ps->n_items;
+    a.cbs = (const DecCb *)(ps->d_buf + ps->off_cbs);
+    a.llr = d_llr;
+    a.bits = d_bits;
+    a.crc_ok = d_ok;
+    a.iters = d_it;
+    a.hard = hard ? ctx->d_hard : nullptr;
+    a.crc_tab = ctx->d_crc_tab;
+    a.scratch = ctx->d_scratch;
+    a.scratch_stride = ps->stride;
+    a.max_iters = p->max_iters;
+    a.early_stop = p->early_stop;
+    a.win_init = p->win_init;
+    if (launch_decode(a, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdec_status tdec_segment(int32_t tbs, tdec_seg *out)
+{
+    if (!out) return TDEC_EINVAL;
+    int32_t s[8];
+    if (segment(tbs, s)) return TDEC_ERANGE;
+    out->B = s[0];
+    out->C = s[1];
+    out->L = s[2];
+    out->Kplus = s[3];
+    out->Kminus = s[4];
+    out->Cplus = s[5];
+    out->Cminus = s[6];
+    out->F = s[7];
+    return TDEC_OK;
+}
+
+int64_t tdec_tb_llr_count(int32_t tbs)
+{
+    int32_t s[8];
+    if (segment(tbs, s)) return -1;
+    return 3 * ((int64_t)s[5] * (s[3] + 4) + (int64_t)s[6] * (s[4] + 4));
+}
+
+int32_t tdec_k_table(int32_t *out188)
+{
+    if (out188)
+        for (int i = 0; i < kNumK; ++i) out188[i] = k_of_index(i);
+    return kNumK;
+}
+
+tdec_status tdec_qpp(int32_t K, int32_t *pi, int32_t *f1, int32_t *f2)
+{
+    const int i = k_index(K);
+    if (i < 0) return TDEC_EINVAL;
+    int32_t a, b;
+    qpp_coeffs(i, &a, &b);
+    if (f1) *f1 = a;
+    if (f2) *f2 = b;
+    if (pi) {
+        // second-order recurrence: pi(i+1) = pi(i) + g(i), g(i+1) = g(i) + 2 f2
+        int64_t p = 0, g = (a + b) % K;
+        for (int32_t k = 0; k < K; ++k) {
+            pi[k] = (int32_t)p;
+            p = (p + g) % K;
+            g = (g + 2 * b) % K;
+        }
+    }
+    return TDEC_OK;
+}
+
+tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
+{
+    if (!out) return TDEC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TDEC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TDEC_EDEVICE;
+    tdec_ctx *c = new tdec_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)1 << 30);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return TDEC_EDEVICE;
+    }
+    c->num_cus = prop.multiProcessorCount;
+    const size_t tab_bytes = 2 * kCrcTabN * sizeof(uint32_t);
+    c->flags_cap = 1 << 20;
+    c->encbuf_bytes = 1 << 20;
+    const size_t plan_bytes = (size_t)kPlanSlots * kPlanSlotBytes;
+    const size_t fixed = tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes;
+    if (c->budget < fixed + (16u << 20)) {
+        delete c;
+        return TDEC_ENOMEM;
+    }
+    const size_t rest = c->budget - fixed;
+    c->hard_words_cap = std::min<size_t>(rest / 8, (size_t)128 << 20) / 4;
+    c->scratch_bytes = rest - c->hard_words_cap * 4;
+    bool ok = hipMalloc(&c->d_crc_tab, tab_bytes) == hipSuccess &&
+              hipMalloc(&c->d_scratch, c->scratch_bytes) == hipSuccess &&
+              hipMalloc(&c->d_hard, c->hard_words_cap * 4) == hipSuccess &&
+              hipMalloc(&c->d_ok, c->flags_cap) == hipSuccess &&
+              hipMalloc(&c->d_it, c->flags_cap) == hipSuccess &&
+              hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess;
+    for (auto &s : c->slots) {
+        ok = ok && hipMalloc(&s.d_buf, kPlanSlotBytes) == hipSuccess &&
+             hipHostMalloc(&s.h_buf, kPlanSlotBytes, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
+    }
+    if (ok) {
+        std::vector<uint32_t> tab(2 * kCrcTabN);
+        crc_shift_table(kPoly24A, tab.data(), kCrcTabN);
+        crc_shift_table(kPoly24B, tab.data() + kCrcTabN, kCrcTabN);
+        ok = hipMemcpy(c->d_crc_tab, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        tdec_destroy(c);
+        return TDEC_ENOMEM;
+    }
+    *out = c;
+    return TDEC_OK;
+}
+
+void tdec_destroy(tdec_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->d_crc_tab);
+    (void)hipFree(c->d_scratch);
+    (void)hipFree(c->d_hard);
+    (void)hipFree(c->d_ok);
+    (void)hipFree(c->d_it);
+    (void)hipFree(c->d_encbuf);
+    for (auto &s : c->slots) {
+        if (s.d_buf) (void)hipFree(s.d_buf);
+        if (s.h_buf) (void)hipHostFree(s.h_buf);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    delete c;
+}
+
+int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K)
+{
+    (void)ctx;
+    if (k_index(K) < 0) return 0;
+    return pick_windows(K);
+}
+
+tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                            const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                            uint8_t *d_crc_ok, uint8_t *d_iters, void *stream)
+{
+    if (!ctx || n_cb < 0 || !params_ok(params)) return TDEC_EINVAL;
+    if (n_cb == 0) return TDEC_OK;
+    if (!desc || !d_llr || !d_crc_ok || !d_iters) return TDEC_EINVAL;
+    std::vector<CbReq> reqs((size_t)n_cb);
+    for (int32_t i = 0; i < n_cb; ++i) {
+        const tdec_cb_desc &d = desc[i];
+        if (k_index(d.K) < 0 || d.F < 0 || d.F >= d.K || d.crc < 0 || d.crc > 2 || d.llr_off < 0)
+            return TDEC_EINVAL;
+        if (d.crc && d.K - d.F < 24) return TDEC_EINVAL;
+        if (d_bits && d.bits_off < 0) return TDEC_EINVAL;
+        const int32_t nw = params->n_windows ? params->n_windows : pick_windows(d.K);
+        if (!windows_ok(d.K, nw)) return TDEC_EINVAL;
+        CbReq &r = reqs[i];
+        r.K = d.K;
+        r.nw = nw;
+        r.cb.llr_off = d.llr_off;
+        r.cb.bits_off = d_bits ? d.bits_off : -1;
+        r.cb.hard_off = -1;
+        r.cb.out_idx = i;
+        r.cb.F = d.F;
+        r.cb.crc = d.crc;
+        r.cb.rsv = 0;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::string key(1, 'C');
+    key.append((const char *)&params->n_windows, sizeof(int32_t));
+    key.push_back(d_bits ? 1 : 0);
+    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (!hit) {
+        std::vector<char> blob;
+        tdec_status s = build_decode_plan(ctx, reqs, *ps, blob, nullptr);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+        s = upload(ctx, ps, key, blob, st);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+    }
+    return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st);
+}
+
+tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
+                            const int64_t *bits_off, const int16_t *d_llr,
+                            const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
+                            void *stream)
+{
+    if (!ctx || n_tb < 0 || !params_ok(params)) return TDEC_EINVAL;
+    if (n_tb == 0) return TDEC_OK;
+    if (!tbs || !llr_off || !d_llr || !d_res) return TDEC_EINVAL;
+    if (d_bits && !bits_off) return TDEC_EINVAL;
+    std::vector<CbReq> reqs;
+    std::vector<TbItem> tbl((size_t)n_tb);
+    int64_t hard = 0;
+    int32_t cbi = 0;
+    for (int32_t t = 0; t < n_tb; ++t) {
+        int32_t s[8];
+        if (segment(tbs[t], s)) return TDEC_ERANGE;
+        if (s[1] > 64) return TDEC_ERANGE;
+        if (llr_off[t] < 0 || (d_bits && bits_off[t] < 0)) return TDEC_EINVAL;
+        TbItem &ti = tbl[t];
+        ti.tbs = tbs[t];
+        ti.B = s[0];
+        ti.C = s[1];
+        ti.L = s[2];
+        ti.Kplus = s[3];
+        ti.Kminus = s[4];
+        ti.Cminus = s[6];
+        ti.F = s[7];
+        ti.hard_off = hard;
+        ti.bits_off = d_bits ? bits_off[t] : -1;
+        ti.cb_idx0 = cbi;
+        ti.res_idx = t;
+        int64_t off = llr_off[t];
+        for (int r = 0; r < s[1]; ++r) {
+            const int32_t K = r < s[6] ? s[4] : s[3];
+            const int32_t nw = params->n_windows ? params->n_windows : pick_windows(K);
+            if (!windows_ok(K, nw)) return TDEC_EINVAL;
+            CbReq q;
+            q.K = K;
+            q.nw = nw;
+            q.cb.llr_off = off;
+            q.cb.bits_off = -1;
+            q.cb.hard_off = hard;
+            q.cb.out_idx = cbi;
+            q.cb.F = (int16_t)(r == 0 ? s[7] : 0);
+            q.cb.crc = (int8_t)(s[1] > 1 ? TDEC_CRC24B : TDEC_CRC24A);
+            q.cb.rsv = 0;
+            reqs.push_back(q);
+            off += 3 * (int64_t)(K + 4);
+            hard += hard_words(K);
+            ++cbi;
+        }
+    }
+    if ((size_t)hard > ctx->hard_words_cap || (size_t)cbi > ctx->flags_cap) return TDEC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::string key(1, 'T');
+    key.append((const char *)&params->n_windows, sizeof(int32_t));
+    key.push_back(d_bits ? 1 : 0);
+    key.append((const char *)tbs, sizeof(int32_t) * (size_t)n_tb);
+    key.append((const char *)llr_off, sizeof(int64_t) * (size_t)n_tb);
+    if (d_bits) key.append((const char *)bits_off, sizeof(int64_t) * (size_t)n_tb);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (!hit) {
+        std::vector<char> blob;
+        tdec_status s = build_decode_plan(ctx, reqs, *ps, blob, &tbl);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+        s = upload(ctx, ps, key, blob, st);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+    }
+    tdec_status s = launch_plan(ctx, ps, d_llr, params, nullptr, ctx->d_ok, ctx->d_it, true, st);
+    if (s != TDEC_OK) return s;
+    if (launch_tb_assemble((const TbItem *)(ps->d_buf + ps->off_tbs), ps->n_tb, ctx->d_hard,
+                           ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
+        return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+tdec_status tb_decode(tdec_ctx *ctx, const int16_t *d_llr, int32_t tbs, const tdec_params *params,
+                      uint8_t *d_bits, tdec_tb_result *d_res, void *stream)
+{
+    const int64_t lo = 0, bo = 0;
+    return tb_decode_batch(ctx, 1, &tbs, &lo, &bo, d_llr, params, d_bits, d_res, stream);
+}
+
+static tdec_status encode_list(tdec_ctx *ctx, std::vector<EncCb> &list, const std::string &key,
+                               const uint8_t *src, uint8_t *d_coded, hipStream_t st)
+{
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (!hit) {
+        const size_t bytes = list.size() * sizeof(EncCb);
+        if (bytes > kPlanSlotBytes) return TDEC_ENOMEM;
+        std::vector<char> blob(bytes);
+        memcpy(blob.data(), list.data(), bytes);
+        ps->off_enc = 0;
+        ps->n_cb = (int)list.size();
+        tdec_status s = upload(ctx, ps, key, blob, st);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+    }
+    if (launch_encode((const EncCb *)(ps->d_buf + ps->off_enc), ps->n_cb, src, d_coded,
+                      ctx->d_crc_tab, st))
+        return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+tdec_status cb_encode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                            const uint8_t *d_payload, uint8_t *d_coded, void *stream)
+{
+    if (!ctx || n_cb < 0) return TDEC_EINVAL;
+    if (n_cb == 0) return TDEC_OK;
+    if (!desc || !d_payload || !d_coded) return TDEC_EINVAL;
+    std::vector<EncCb> list((size_t)n_cb);
+    for (int32_t i = 0; i < n_cb; ++i) {
+        const tdec_cb_desc &d = desc[i];
+        const int ki = k_index(d.K);
+        if (ki < 0 || d.F < 0 || d.F >= d.K || d.crc < 0 || d.crc > 2 || d.llr_off < 0 ||
+            d.bits_off < 0)
+            return TDEC_EINVAL;
+        if (d.crc && d.K - d.F < 24) return TDEC_EINVAL;
+        EncCb &e = list[i];
+        e.src_bit = 8 * d.bits_off;
+        e.out_off = d.llr_off;
+        e.K = d.K;
+        qpp_coeffs(ki, &e.f1, &e.f2);
+        e.F = d.F;
+        e.crc = d.crc;
+        e.rsv = 0;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::string key(1, 'E');
+    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
+    return encode_list(ctx, list, key, d_payload, d_coded, (hipStream_t)stream);
+}
+
+tdec_status tb_encode(tdec_ctx *ctx, const uint8_t *d_payload, int32_t tbs, uint8_t *d_coded,
+                      void *stream)
+{
+    if (!ctx || !d_payload || !d_coded) return TDEC_EINVAL;
+    int32_t s[8];
+    if (segment(tbs, s)) return TDEC_ERANGE;
+    if ((size_t)(s[0] + 7) / 8 > ctx->encbuf_bytes) return TDEC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::vector<EncCb> list((size_t)s[1]);
+    int64_t bit = 0, out = 0;
+    for (int r = 0; r < s[1]; ++r) {
+        const int32_t K = r < s[6] ? s[4] : s[3];
+        const int32_t F = r == 0 ? s[7] : 0;
+        EncCb &e = list[r];
+        e.src_bit = bit;
+        e.out_off = out;
+        e.K = K;
+        qpp_coeffs(k_index(K), &e.f1, &e.f2);
+        e.F = (int16_t)F;
+        e.crc = (int8_t)(s[1] > 1 ? TDEC_CRC24B : TDEC_CRC_NONE);
+        e.rsv = 0;
+        bit += K - F - s[2];
+        out += 3 * (int64_t)(K + 4);
+    }
+    if (launch_tb_crc_attach(d_payload, tbs, ctx->d_encbuf, ctx->d_crc_tab, st)) return TDEC_EDEVICE;
+    std::string key(1, 'B');
+    key.append((const char *)&tbs, sizeof tbs);
+    return encode_list(ctx, list, key, ctx->d_encbuf, d_coded, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// tdec_internal.h -- structures shared by the host planner and the kernels of
+// libtdec.  Nothing here is part of the public C ABI (include/tdec.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdec {
+
+constexpr int kNumK = 188;
+constexpr int kKmax = 6144;
+constexpr int kLlrMax = 2047;
+// x^n mod g for n = 0 .. kCrcTabN-1 (covers every shift a code block needs)
+constexpr int kCrcTabN = kKmax + 32;
+constexpr uint32_t kPoly24A = 0x864CFBu;  // D^24+D^23+D^18+D^17+D^14+D^11+D^10+D^7+D^6+D^5+D^4+D^3+D+1
+constexpr uint32_t kPoly24B = 0x800063u;  // D^24+D^23+D^6+D^5+D+1
+constexpr int kMaxSlotsPerWg = 64;        // code blocks per work group
+constexpr int kMaxWgThreads = 256;
+
+// Host-side tables (tables.cpp).
+int k_index(int32_t K);             // index in the size table or -1
+int32_t k_of_index(int i);          // size of table entry i
+void qpp_coeffs(int i, int32_t *f1, int32_t *f2);
+int segment(int32_t tbs, int32_t seg[8]);  // B C L K+ K- C+ C- F; 0 ok, -1 range
+void crc_shift_table(uint32_t poly, uint32_t *out, int n);  // out[m] = x^m mod g
+
+// One work item of the decode kernel: `ncb` code blocks of the same size K,
+// each cut into `nw` windows of W steps; lane l < ncb*nw of the work group
+// runs window l % nw of block slot l / nw.
+struct DecItem {
+    int32_t K, nw, W, ncb;
+    int32_t cb0;     // first entry of this item in the code block list
+    int32_t f1, f2;  // QPP coefficients
+    int32_t S;       // trellis steps per checkpoint segment (8 or 16; divides W)
+    int32_t lds_slot;  // LDS bytes per code block slot (extrinsic array + bitmap)
+    int32_t rsv;
+};
+
+// One code block of the decode kernel's list.
+struct DecCb {
+    int64_t llr_off;   // element offset of the [3][K+4] int16 LLRs
+    int64_t bits_off;  // byte offset of the packed payload output, -1 = none
+    int64_t hard_off;  // word offset of the full hard decision (TB assembly), -1 = none
+    int32_t out_idx;   // index into crc_ok / iters
+    int16_t F;
+    int8_t crc;        // 0 none, 1 CRC24A, 2 CRC24B
+    int8_t rsv;
+};
+
+struct DecArgs {
+    const DecItem *items;
+    int32_t n_items;
+    const DecCb *cbs;
+    const int16_t *llr;
+    uint8_t *bits;
+    uint8_t *crc_ok;
+    uint8_t *iters;
+    uint32_t *hard;
+    const uint32_t *crc_tab;  // [2][kCrcTabN]: 24A then 24B
+    char *scratch;
+    int64_t scratch_stride;   // bytes of global scratch per work group
+    int32_t max_iters, early_stop, win_init;
+};
+
+// One transport block for the assembly kernel (after the code blocks are decoded).
+struct TbItem {
+    int32_t tbs, B, C, F, L;
+    int32_t Kminus, Cminus, Kplus;
+    int64_t hard_off;   // word offset of block 0's hard bits; block r follows at
+                        // hard_off + sum_{q<r} hard_words(K_q)
+    int64_t bits_off;   // byte offset of the payload output, -1 = none
+    int32_t cb_idx0;    // index of block 0 in crc_ok / iters
+    int32_t res_idx;    // index into the result array
+};
+
+// Words of hard-decision storage per code block: the K bits plus one spare word.
+__host__ __device__ inline int64_t hard_words(int32_t K) { return (K + 31) / 32 + 1; }
+
+// One code block for the encoder kernel.
+struct EncCb {
+    int64_t src_bit;   // bit offset of the payload in the packed source
+    int64_t out_off;   // byte offset of the [3][K+4] output
+    int32_t K, f1, f2;
+    int16_t F;
+    int8_t crc;
+    int8_t rsv;
+};
+
+// Launchers (dec_kernels.hip / enc_kernels.hip).
+const void *decode_kernel_address();
+int launch_decode(const DecArgs &a, int grid, int wg_threads, int lds_bytes, void *stream);
+int launch_tb_assemble(const TbItem *items, int n_tb, const uint32_t *hard, const uint8_t *crc_ok,
+                       const uint8_t *iters, const uint32_t *crc_tab, uint8_t *bits, void *res,
+                       void *stream);
+int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
+                  const uint32_t *crc_tab, void *stream);
+int launch_tb_crc_attach(const uint8_t *payload, int32_t tbs, uint8_t *stream_bits,
+                         const uint32_t *crc_tab, void *stream);
+
+}  // namespace tdec

@@ -1,0 +1,57 @@
+"""The C-ABI library: it loads, exports every function include/tdec.h
+declares, and its host-only helpers (segmentation, table, QPP) agree with
+the oracle.  No GPU needed."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1905_01141_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tdec.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\([^;{]*\)\s*;", src)
+    return sorted(set(n for n in names if n not in ("sizeof",)))
+
+
+def test_library_exports_every_declared_function():
+    L = ct.CDLL(T.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(T.EXPORTS)
+
+
+def test_host_helpers_agree_with_oracle(orc):
+    assert np.array_equal(T.k_table(), orc.k_table())
+    for K in T.k_table().tolist():
+        pi, f1, f2 = T.qpp(K)
+        assert (f1, f2) == orc.qpp_params(K)
+        assert np.array_equal(pi, orc.qpp(K))
+    rng = np.random.default_rng(1)
+    for tbs in list(range(1, 300)) + rng.integers(1, 1 << 20, 200).tolist() + [6120, 6121]:
+        assert T.segment(int(tbs)) == orc.segment(int(tbs))
+        assert T.tb_llr_count(int(tbs)) == orc.tb_llr_count(int(tbs))
+    with pytest.raises(T.TdecError):
+        T.segment(0)
+    with pytest.raises(T.TdecError):
+        T.segment((1 << 20) + 1)
+
+
+def test_binding_rejects_oversized_descriptors():
+    """The binding refuses descriptors that would reach past a tensor."""
+    import torch
+    descs, n_llr, n_bytes = T.make_descs([(6144, 0, T.CRC24B)] * 2)
+    small = torch.zeros(n_llr - 1, dtype=torch.int16)
+    with pytest.raises(ValueError):
+        T._need(small, "int16", n_llr, "llr")
+    with pytest.raises(ValueError):
+        T._need(torch.zeros(n_llr, dtype=torch.int32), "int16", n_llr, "llr")
+    T._need(torch.zeros(n_llr, dtype=torch.int16), "int16", n_llr, "llr")
