@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark: decoded information throughput of the MI355X turbo decoder.
+
+Workload (one step = one launch decoding the whole batch):
+  4096 code blocks of K = 6144 (6120 payload bits + CRC24B), 16QAM over AWGN
+  at Es/N0 = 8 dB, int16 LLRs (scale 8, clamp +-2047), windowed max-log-MAP
+  with 32 windows of 192 steps and previous-iteration boundary init,
+  exactly 6 iterations (early stop off).
+Metric: decoded payload Gbit/s at 6 iterations = 4096 * 6120 * steps / wall.
+The LLRs are resident in device memory before the timed region starts.
+
+Also reported (stderr + extra JSON fields): the same batch as configured
+(at most 8 iterations with CRC24B early stop), the kernel's VALU roofline
+fraction, and the CPU oracle's throughput on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_CB = 4096
+K = 6144
+N_WIN = 32
+PAYLOAD = K - 24
+ITERS = 6
+MOD, ESN0 = "16qam", 8.0
+# max-log-MAP work per trellis step and half-iteration: branch metrics 2,
+# forward ACS 24, backward ACS 24, extrinsic 39 -> 89; two half-iterations.
+OPS_PER_KBIT_ITER = 178
+# packed int16 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 halves x 2.4 GHz
+PEAK_INT16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "turbo_decode_k6144x4096_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1905_01141_amd", "csrc", "dec_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def build_inputs(T, D, torch):
+    import numpy as np
+    import workload as wl
+    descs, n_llr, n_bytes = T.make_descs([(K, 0, T.CRC24B)] * N_CB)
+    pay_bits = wl.random_bits(wl.rng(2, 0), N_CB * PAYLOAD)
+    pay = torch.from_numpy(np.packbits(pay_bits)).cuda()
+    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    D.cb_encode_batch(descs, pay, coded)  # GPU turbo encoder (CRC24B + 2 RSC + QPP)
+    torch.cuda.synchronize()
+    llr = wl.channel_blocks(coded.cpu().numpy(), [(K, 0)] * N_CB, MOD, ESN0, wl.rng(2, 1))
+    return descs, llr, pay_bits, n_bytes
+
+
+def cpu_baseline(llr, sample_cbs: int, threads: int):
+    """The plain C oracle (never tuned) on `sample_cbs` blocks of the same
+    workload, one block per task on a thread pool."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as O
+    blk = 3 * (K + 4)
+    p = O.params(ITERS, 0, N_WIN, 1)
+
+    def one(i):
+        r = O.cb_decode(llr[i * blk:(i + 1) * blk], K, 0, O.CRC24B, p)
+        return r["ok"]
+
+    O.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        oks = list(ex.map(one, range(sample_cbs)))
+    dt = time.perf_counter() - t0
+    return {"value": round(sample_cbs * PAYLOAD / dt / 1e9, 6), "unit": "Gbit/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{sample_cbs} of the {N_CB} code blocks, {ITERS} iterations, "
+                      f"{N_WIN} windows, one block per task; {dt:.2f} s wall, "
+                      f"{sum(oks)} CRC pass"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(code blocks, transport blocks and cells are independent; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1905_01141_amd as T
+
+    torch.cuda.set_device(0)
+    D = T.Decoder(0)
+    log("[bench] building inputs: GPU encoder + 16QAM AWGN channel")
+    descs, llr_h, pay_bits, n_bytes = build_inputs(T, D, torch)
+    x = torch.from_numpy(llr_h).cuda()
+    bits = torch.zeros(n_bytes, dtype=torch.uint8, device="cuda")
+    ok = torch.zeros(N_CB, dtype=torch.uint8, device="cuda")
+    it = torch.zeros(N_CB, dtype=torch.uint8, device="cuda")
+    p6 = T.params(ITERS, 0, N_WIN, 1)
+    stream = torch.cuda.current_stream()
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        D.cb_decode_batch(descs, x, p6, bits, ok, it, stream=stream)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing {args.steps} steps")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        D.cb_decode_batch(descs, x, p6, bits, ok, it, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = e0.elapsed_time(e1)
+    ms_step = wall * 1e3 / args.steps
+    value = N_CB * PAYLOAD * args.steps / wall / 1e9
+    launch_s = dev_ms / 1e3 / args.steps
+    ops = OPS_PER_KBIT_ITER * N_CB * K * ITERS
+    achieved = ops / launch_s / 1e12
+
+    # correctness of the timed output against the transmitted payload
+    got = np.unpackbits(bits.cpu().numpy())
+    okh = ok.cpu().numpy()
+    errs = int(np.count_nonzero(got.reshape(N_CB, -1)[:, :PAYLOAD] !=
+                                pay_bits.reshape(N_CB, PAYLOAD)))
+    log(f"[bench] 6-iteration run: {value:.3f} Gbit/s, {ms_step:.3f} ms/step, "
+        f"kernel {launch_s * 1e3:.3f} ms, CRC pass {int(okh.sum())}/{N_CB}, bit errors {errs}")
+
+    # as configured: <= 8 iterations, CRC24B early stop
+    p8 = T.params(8, 1, N_WIN, 1)
+    D.cb_decode_batch(descs, x, p8, bits, ok, it, stream=stream)
+    torch.cuda.synchronize()
+    n_cfg = max(1, args.steps // 2)
+    t1 = time.perf_counter()
+    for _ in range(n_cfg):
+        D.cb_decode_batch(descs, x, p8, bits, ok, it, stream=stream)
+    torch.cuda.synchronize()
+    wall8 = time.perf_counter() - t1
+    iters8 = it.cpu().numpy()
+    as_cfg = {"value": round(N_CB * PAYLOAD * n_cfg / wall8 / 1e9, 4), "unit": "Gbit/s",
+              "max_iters": 8, "early_stop": 1, "mean_iters": round(float(iters8.mean()), 4),
+              "max_iters_seen": int(iters8.max()),
+              "crc_pass": int(ok.cpu().numpy().sum())}
+    log(f"[bench] as configured: {as_cfg}")
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {n} bytes read + {n} bytes written")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] CPU oracle baseline on {threads} threads, {args.cpu_sample} blocks")
+        cpu = cpu_baseline(llr_h, args.cpu_sample, threads)
+
+    line = {
+        "metric": "decoded info Gbit/s @6 iters",
+        "value": round(value, 4),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic (random payload, GPU turbo encoder, 16QAM AWGN, quantised LLRs)",
+        "config": {"workload": "uniform batch: 4096 code blocks K=6144 with CRC24B, 16QAM AWGN "
+                               "Es/N0 8 dB, int16 LLRs, 32 windows x 192 steps with "
+                               "previous-iteration boundary init, exactly 6 iterations",
+                   "n_cb": N_CB, "K": K, "n_windows": N_WIN, "win_init": 1,
+                   "max_iters": ITERS, "early_stop": 0, "modulation": MOD, "esn0_db": ESN0},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_INT16_TOPS, 2), "unit": "TOP/s",
+                     "frac": round(achieved / PEAK_INT16_TOPS, 4),
+                     "traffic": measured_traffic()},
+        "cpu_baseline": cpu,
+        "as_configured": as_cfg,
+        "kernel_ms": round(launch_s * 1e3, 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

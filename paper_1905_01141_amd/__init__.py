@@ -9,6 +9,7 @@ GPU is present -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes as ct
+import functools
 import os
 
 import numpy as np
@@ -43,6 +44,10 @@ class CbDesc(ct.Structure):
     _fields_ = [("llr_off", ct.c_int64), ("bits_off", ct.c_int64), ("K", ct.c_int32),
                 ("F", ct.c_int16), ("crc", ct.c_int8), ("rsv", ct.c_int8)]
 
+
+# tdec_cb_desc as a numpy record (same layout) for vectorised checks
+DESC_DTYPE = np.dtype([("llr_off", "<i8"), ("bits_off", "<i8"), ("K", "<i4"), ("F", "<i2"),
+                       ("crc", "i1"), ("rsv", "i1")])
 
 # tdec_tb_result as stored in device memory
 TB_RESULT_DTYPE = np.dtype([("tb_ok", "<i4"), ("max_iters_used", "<i4"), ("C", "<i4"),
@@ -122,6 +127,7 @@ def cb_sizes(tbs: int) -> list[tuple[int, int]]:
             for r in range(s["C"])]
 
 
+@functools.lru_cache(maxsize=4096)
 def tb_llr_count(tbs: int) -> int:
     n = lib().tdec_tb_llr_count(int(tbs))
     if n < 0:
@@ -156,9 +162,15 @@ def make_descs(cbs) -> tuple[ct.Array, int, int]:
     return descs, llr_off, bits_off
 
 
-def _payload_bytes(d) -> int:
-    L = 0 if d.crc == CRC_NONE else 24
-    return max(0, (d.K - d.F - L + 7) // 8)
+def _desc_extent(descs):
+    """(LLR elements, payload bytes) a descriptor array reaches, vectorised."""
+    if len(descs) == 0:
+        return 0, 0
+    v = np.frombuffer(descs, dtype=DESC_DTYPE, count=len(descs))
+    K = v["K"].astype(np.int64)
+    L = np.where(v["crc"] == CRC_NONE, 0, 24)
+    nb = np.maximum(0, (K - v["F"] - L + 7) // 8)
+    return int((v["llr_off"] + 3 * (K + 4)).max()), int((v["bits_off"] + nb).max())
 
 
 def _need(t, dtype: str, n: int, name: str):
@@ -201,10 +213,10 @@ class Decoder:
         """llr: int16 CUDA tensor; bits: uint8 CUDA tensor or None; crc_ok /
         iters: uint8 CUDA tensors with one entry per code block."""
         n = len(descs)
-        _need(llr, "int16", max((d.llr_off + 3 * (d.K + 4) for d in descs), default=0), "llr")
+        n_llr, n_bits = _desc_extent(descs)
+        _need(llr, "int16", n_llr, "llr")
         if bits is not None:
-            _need(bits, "uint8", max((d.bits_off + _payload_bytes(d) for d in descs), default=0),
-                  "bits")
+            _need(bits, "uint8", n_bits, "bits")
         _need(crc_ok, "uint8", n, "crc_ok")
         _need(iters, "uint8", n, "iters")
         _check("cb_decode_batch",
@@ -226,11 +238,11 @@ class Decoder:
         llr_off = np.ascontiguousarray(llr_off, np.int64)
         bits_off = None if bits_off is None else np.ascontiguousarray(bits_off, np.int64)
         n = tbs.size
-        _need(llr, "int16", max((int(llr_off[i]) + tb_llr_count(int(tbs[i])) for i in range(n)),
-                                default=0), "llr")
-        if bits is not None:
-            _need(bits, "uint8", max((int(bits_off[i]) + (int(tbs[i]) + 7) // 8 for i in range(n)),
-                                     default=0), "bits")
+        if n:
+            counts = np.array([tb_llr_count(int(t)) for t in tbs], np.int64)
+            _need(llr, "int16", int((llr_off + counts).max()), "llr")
+            if bits is not None:
+                _need(bits, "uint8", int((bits_off + (tbs.astype(np.int64) + 7) // 8).max()), "bits")
         _need(res, "uint8", n * TB_RESULT_BYTES, "res")
         _check("tb_decode_batch",
                lib().tb_decode_batch(self._h, tbs.size, _np_ptr(tbs), _np_ptr(llr_off),
@@ -238,9 +250,9 @@ class Decoder:
                                      _dptr(res), _stream(stream)))
 
     def cb_encode_batch(self, descs, payload, coded, stream=None):
-        _need(payload, "uint8", max((d.bits_off + _payload_bytes(d) for d in descs), default=0),
-              "payload")
-        _need(coded, "uint8", max((d.llr_off + 3 * (d.K + 4) for d in descs), default=0), "coded")
+        n_llr, n_bits = _desc_extent(descs)
+        _need(payload, "uint8", n_bits, "payload")
+        _need(coded, "uint8", n_llr, "coded")
         _check("cb_encode_batch",
                lib().cb_encode_batch(self._h, len(descs), ct.cast(descs, ct.c_void_p),
                                      _dptr(payload), _dptr(coded), _stream(stream)))

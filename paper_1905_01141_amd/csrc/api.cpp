@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tdec.h"
+#include "tdec.h"
 #include "tdec_internal.h"
 
 using namespace tdec;
@@ -36,7 +36,7 @@ struct PlanSlot {
     int n_items = 0, grid = 0, wg = 0, lds = 0;
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
-    size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
+    size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0, off_qtab = 0;
 };
 
 }  // namespace
@@ -54,21 +54,14 @@ struct tdec_ctx {
     size_t flags_cap = 0;
     uint8_t *d_encbuf = nullptr;
     size_t encbuf_bytes = 0;
+    uint32_t *d_counter = nullptr;  // work distribution counter of the decode kernel
     PlanSlot slots[kPlanSlots];
     uint64_t clock = 0;
-    int lds_budget = 27 * 1024;  // LDS bytes per work group the planner aims for
+    int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
 };
 
 namespace {
-
-int slot_bytes_for(int32_t K)
-{
-    const int e = K + ((K - 1) >> 6);             // padded int16 entries
-    const int ewords = (e + 1) / 2;
-    const int bytes = (ewords + (int)hard_words(K)) * 4;
-    return (bytes + 15) & ~15;
-}
 
 bool params_ok(const tdec_params *p)
 {
@@ -89,7 +82,7 @@ int32_t pick_windows(int32_t K)
 
 bool windows_ok(int32_t K, int32_t nw)
 {
-    return nw >= 1 && nw <= kMaxWgThreads && K % nw == 0 && (K / nw) % 8 == 0;
+    return nw >= 1 && nw <= kMaxWgThreads / 2 && K % nw == 0 && (K / nw) % kSeg == 0;
 }
 
 struct CbReq {
@@ -110,9 +103,16 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     });
     int max_nw = 1;
     for (auto &r : reqs) max_nw = std::max(max_nw, r.nw);
-    const int wg = std::min(kMaxWgThreads, ((max_nw + 63) / 64) * 64);
+    // two lanes per window, in two halves of the work group (forward-first
+    // and backward-first waves)
+    const int half = ((max_nw + 63) / 64) * 64;
+    const int wg = 2 * half;
+    if (wg > kMaxWgThreads) return TDEC_EINVAL;
     std::vector<DecItem> items;
     std::vector<DecCb> cbl;
+    // QPP address tables, one per (K, nw) shape
+    std::vector<uint16_t> qtab;
+    std::vector<std::pair<int64_t, int32_t>> shapes;  // (K * 1024 + nw, offset)
     cbl.reserve(reqs.size());
     int lds = 0;
     int64_t stride = 0;
@@ -120,9 +120,10 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     while (i < order.size()) {
         const CbReq &r0 = reqs[order[i]];
         const int K = r0.K, nw = r0.nw, W = K / nw;
-        const int sb = slot_bytes_for(K);
-        int cap = std::min(wg / nw, kMaxSlotsPerWg);
+        const int sb = lds_slot_bytes(K);
+        int cap = std::min(half / nw, kMaxSlotsPerWg);
         cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
+        cap = std::min(cap, 65536 / sb);  // decoder 2 keeps 16-bit LDS addresses
         DecItem it;
         it.K = K;
         it.nw = nw;
@@ -132,9 +133,27 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         qpp_coeffs(k_index(K), &f1, &f2);
         it.f1 = f1;
         it.f2 = f2;
-        it.S = 8;
         it.lds_slot = sb;
-        it.rsv = 0;
+        {
+            const int64_t key = (int64_t)K * 1024 + nw;
+            int32_t off = -1;
+            for (auto &sh : shapes)
+                if (sh.first == key) off = sh.second;
+            if (off < 0) {
+                off = (int32_t)qtab.size();
+                shapes.push_back({key, off});
+                qtab.resize(qtab.size() + K);
+                // unit u = t4 * nw + w holds steps k = w * W + 4 * t4 + j
+                std::vector<int32_t> pi(K);
+                tdec_qpp(K, pi.data(), nullptr, nullptr);
+                for (int u = 0; u < K / 4; ++u) {
+                    const int t4 = u / nw, w = u % nw;
+                    for (int j = 0; j < 4; ++j)
+                        qtab[off + 4 * u + j] = (uint16_t)(2 * epad(pi[w * W + 4 * t4 + j]));
+                }
+            }
+            it.qtab = off;
+        }
         int n = 0;
         while (i < order.size() && n < cap && reqs[order[i]].K == K && reqs[order[i]].nw == nw) {
             cbl.push_back(reqs[order[i]].cb);
@@ -145,8 +164,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         items.push_back(it);
         lds = std::max(lds, n * sb);
         const int lanes = n * nw;
-        const int64_t need = (int64_t)n * K * 6 + (int64_t)(W / it.S) * lanes * 16 +
-                             (((int64_t)(W / it.S) * lanes * 8 + 15) & ~(int64_t)15) +
+        const int64_t need = (int64_t)n * K * 8 + (int64_t)(W / kSeg) * lanes * 16 +
                              (int64_t)4 * lanes * 16 + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
@@ -163,17 +181,19 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     grid = (int)std::min<int64_t>(grid, fit);
     grid = std::max(grid, 1);
 
-    // serialise: [items][cbs][tbs]
+    // serialise: [items][cbs][tbs][qpp tables]
     ps.off_items = 0;
     ps.off_cbs = (items.size() * sizeof(DecItem) + 255) & ~(size_t)255;
     ps.off_tbs = ps.off_cbs + ((cbl.size() * sizeof(DecCb) + 255) & ~(size_t)255);
     const size_t ntb = tbs ? tbs->size() : 0;
-    const size_t total = ps.off_tbs + ntb * sizeof(TbItem);
+    ps.off_qtab = ps.off_tbs + ((ntb * sizeof(TbItem) + 255) & ~(size_t)255);
+    const size_t total = ps.off_qtab + qtab.size() * sizeof(uint16_t);
     if (total > kPlanSlotBytes) return TDEC_ENOMEM;
     blob.assign(total, 0);
     memcpy(blob.data() + ps.off_items, items.data(), items.size() * sizeof(DecItem));
     memcpy(blob.data() + ps.off_cbs, cbl.data(), cbl.size() * sizeof(DecCb));
     if (ntb) memcpy(blob.data() + ps.off_tbs, tbs->data(), ntb * sizeof(TbItem));
+    memcpy(blob.data() + ps.off_qtab, qtab.data(), qtab.size() * sizeof(uint16_t));
     ps.n_items = (int)items.size();
     ps.n_cb = (int)cbl.size();
     ps.n_tb = (int)ntb;
@@ -230,6 +250,8 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.crc_tab = ctx->d_crc_tab;
     a.scratch = ctx->d_scratch;
     a.scratch_stride = ps->stride;
+    a.counter = ctx->d_counter;
+    a.qtab = (const uint16_t *)(ps->d_buf + ps->off_qtab);
     a.max_iters = p->max_iters;
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
@@ -324,7 +346,9 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
               hipMalloc(&c->d_hard, c->hard_words_cap * 4) == hipSuccess &&
               hipMalloc(&c->d_ok, c->flags_cap) == hipSuccess &&
               hipMalloc(&c->d_it, c->flags_cap) == hipSuccess &&
-              hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess;
+              hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess &&
+              hipMalloc(&c->d_counter, 64) == hipSuccess &&
+              hipMemset(c->d_counter, 0, 64) == hipSuccess;
     for (auto &s : c->slots) {
         ok = ok && hipMalloc(&s.d_buf, kPlanSlotBytes) == hipSuccess &&
              hipHostMalloc(&s.h_buf, kPlanSlotBytes, hipHostMallocDefault) == hipSuccess &&
@@ -355,6 +379,7 @@ void tdec_destroy(tdec_ctx *c)
     (void)hipFree(c->d_ok);
     (void)hipFree(c->d_it);
     (void)hipFree(c->d_encbuf);
+    (void)hipFree(c->d_counter);
     for (auto &s : c->slots) {
         if (s.d_buf) (void)hipFree(s.d_buf);
         if (s.h_buf) (void)hipHostFree(s.h_buf);
@@ -377,6 +402,16 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
     if (!ctx || n_cb < 0 || !params_ok(params)) return TDEC_EINVAL;
     if (n_cb == 0) return TDEC_OK;
     if (!desc || !d_llr || !d_crc_ok || !d_iters) return TDEC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    // a batch identical to a cached one reuses its (validated) plan
+    std::string key(1, 'C');
+    key.append((const char *)&params->n_windows, sizeof(int32_t));
+    key.push_back(d_bits ? 1 : 0);
+    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (hit) return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st);
     std::vector<CbReq> reqs((size_t)n_cb);
     for (int32_t i = 0; i < n_cb; ++i) {
         const tdec_cb_desc &d = desc[i];
@@ -397,15 +432,7 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
         r.cb.crc = d.crc;
         r.cb.rsv = 0;
     }
-    hipStream_t st = (hipStream_t)stream;
-    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
-    std::string key(1, 'C');
-    key.append((const char *)&params->n_windows, sizeof(int32_t));
-    key.push_back(d_bits ? 1 : 0);
-    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
-    bool hit;
-    PlanSlot *ps = lookup(ctx, key, &hit);
-    if (!hit) {
+    {
         std::vector<char> blob;
         tdec_status s = build_decode_plan(ctx, reqs, *ps, blob, nullptr);
         if (s != TDEC_OK) {

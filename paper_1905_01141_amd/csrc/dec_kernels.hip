@@ -9,27 +9,38 @@
 // CRC check that may stop the block early.
 //
 // Mapping to CDNA4 (one code block never leaves its work group):
-//   * one lane = one trellis window; all 8 state metrics of the window live
-//     in the lane as packed int16 pairs, so an add-compare-select step is 8
-//     v_pk_add_i16 (saturating) + 4 v_pk_max_i16 with the broadcasts and
-//     swaps folded into op_sel: no cross-lane traffic at all;
-//   * forward metrics are kept as checkpoints every S steps (global scratch)
-//     and recomputed segment by segment in registers during the backward
-//     sweep, which computes the extrinsic from the stored segment;
-//   * the extrinsic/a-priori array of a block lives in LDS for the whole
-//     decode (padded one int16 per 64 to spread banks); decoder 2 reaches it
-//     through the QPP address, generated per step by its second-order
-//     recurrence;
+//   * all 8 state metrics of a trellis window live in one lane as packed
+//     int16 pairs: an add-compare-select step is 8 saturating v_pk_add_i16 +
+//     4 v_pk_max_i16 with the broadcasts and swaps folded into op_sel, and no
+//     cross-lane traffic;
+//   * every window has two lanes in two different waves ("X" schedule): the
+//     forward-first lane runs the forward recursion over the first half of
+//     the window while the backward-first lane runs the backward recursion
+//     over the second half, both leaving checkpoints every 8 steps; then each
+//     lane takes the other half, recomputes the other recursion segment by
+//     segment from those checkpoints into registers and runs its own
+//     recursion over it, emitting the extrinsic.  Each wave runs one code
+//     path; the dependent chain per window is half its length;
+//   * the extrinsic / a-priori array of a block lives in LDS for the whole
+//     decode; decoder 1 reads it 8 steps per ds_read_b128, decoder 2 through
+//     LDS addresses of the QPP permutation precomputed once per block;
 //   * the channel LLRs are restaged once per block into a window-interleaved
-//     layout in global scratch, so the 32 lanes of a block read one 128-byte
-//     line per load (16 B per lane = 4 trellis steps);
+//     layout in global scratch (one 16-byte load = 4 trellis steps of one
+//     lane, the lanes of a wave reading consecutive 16-byte pieces);
 //   * hard decisions are OR-ed into an LDS bitmap, the CRC is a per-window
 //     LFSR combined across windows with x^n mod g tables.
 //
-// Metric layouts: alpha "P" = {(a0,a4),(a1,a5),(a2,a6),(a3,a7)},
-// beta "Q" = {(b0,b1),(b2,b3),(b4,b5),(b6,b7)} with state s = 4 a_{k-1} +
-// 2 a_{k-2} + a_{k-3}.  Branch metric pairs of a step: g00 = (0, Lsa+Lp),
-// g01 = (Lp, Lsa); their swaps g11 and g10 complete the four values.
+// Metric layouts: "P" = {(m0,m4),(m1,m5),(m2,m6),(m3,m7)},
+// "Q" = {(m0,m1),(m2,m3),(m4,m5),(m6,m7)} with state s = 4 a_{k-1} +
+// 2 a_{k-2} + a_{k-3}; forward metrics run in P, backward metrics in Q.
+// Branch metric pairs of a step: g00 = (0, Lsa+Lp), g01 = (Lp, Lsa); their
+// swaps g11 and g10 complete the four values u*Lsa + z*Lp.
+//
+// Fixed point: metrics are shifted so that their maximum is 0 after steps
+// 1 and 2 of a recursion and after every even step, and left alone after odd
+// steps from the third on; candidate sums saturate.  With the input clamps
+// (|Lsa| <= 4094, |Lp| <= 2047) no value that decides a maximum ever leaves
+// int16, so every result equals the exact (unbounded) max-log-MAP.
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -48,26 +59,85 @@ __device__ __forceinline__ s2 as_s2(uint32_t u) { return __builtin_bit_cast(s2, 
 __device__ __forceinline__ uint32_t as_u(s2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 constexpr short kNeg = -32768;
+constexpr int S = kSeg;
 
-// g00 = (0, Lp + Lsa) from g01 = (Lp, Lsa).
+// g00 = (0, Lp + Lsa) from g01 = (Lp, Lsa).  Built with v_perm so that the
+// compiler keeps the pair opaque and folds the swapped uses into op_sel.
 __device__ __forceinline__ s2 mk_g00(s2 g01)
 {
-    s2 x = g01 + swp(g01);  // |Lp + Lsa| <= 6141: no wrap
-    return as_s2(as_u(x) & 0xFFFF0000u);
+    const s2 x = g01 + swp(g01);  // |Lp + Lsa| <= 6141: no wrap
+    return as_s2(__builtin_amdgcn_perm(0u, as_u(x), 0x03020c0cu));
 }
+
+// The four branch metric pairs are g00, g01 and their swaps; a broadcast
+// plus a swapped pair is the swap of the broadcast plus the pair, which puts
+// every swap on an operand of a max or add where it folds into op_sel.
 
 // Forward add-compare-select, P layout in and out.
 __device__ __forceinline__ void acs_fwd(s2 A[4], s2 g00, s2 g01)
 {
-    const s2 g11 = swp(g00), g10 = swp(g01);
-    const s2 n0 = vmax(adds(bcx(A[0]), g00), adds(bcx(A[1]), g11));
-    const s2 n1 = vmax(adds(bcx(A[2]), g10), adds(bcx(A[3]), g01));
-    const s2 n2 = vmax(adds(bcy(A[0]), g01), adds(bcy(A[1]), g10));
-    const s2 n3 = vmax(adds(bcy(A[2]), g11), adds(bcy(A[3]), g00));
+    const s2 n0 = vmax(adds(bcx(A[0]), g00), swp(adds(bcx(A[1]), g00)));
+    const s2 n1 = vmax(swp(adds(bcx(A[2]), g01)), adds(bcx(A[3]), g01));
+    const s2 n2 = vmax(adds(bcy(A[0]), g01), swp(adds(bcy(A[1]), g01)));
+    const s2 n3 = vmax(swp(adds(bcy(A[2]), g00)), adds(bcy(A[3]), g00));
     A[0] = n0;
     A[1] = n1;
     A[2] = n2;
     A[3] = n3;
+}
+
+// Forward step that also returns the extrinsic of the step: the candidate
+// sums alpha_k(p) + gamma(p -> n) of the recursion, plus beta_{k+1}(n) (P
+// layout), maximised per input bit u.  Le = M1 - M0 - Lsa modulo 2^16 (the
+// true value fits int16).
+__device__ __forceinline__ int acs_fwd_le(s2 A[4], s2 g00, s2 g01, const s2 BP[4])
+{
+    const s2 t0 = adds(bcx(A[0]), g00), t1 = swp(adds(bcx(A[1]), g00));
+    const s2 t2 = swp(adds(bcx(A[2]), g01)), t3 = adds(bcx(A[3]), g01);
+    const s2 t4 = adds(bcy(A[0]), g01), t5 = swp(adds(bcy(A[1]), g01));
+    const s2 t6 = swp(adds(bcy(A[2]), g00)), t7 = adds(bcy(A[3]), g00);
+    // halves (u=0, u=1) for p = 0, 3, 4, 7 and (u=1, u=0) for p = 1, 2, 5, 6
+    const s2 n = vmax(vmax(adds(t0, BP[0]), adds(t3, BP[1])), vmax(adds(t4, BP[2]), adds(t7, BP[3])));
+    const s2 s = vmax(vmax(adds(t1, BP[0]), adds(t2, BP[1])), vmax(adds(t5, BP[2]), adds(t6, BP[3])));
+    const s2 m = vmax(n, swp(s));
+    A[0] = vmax(t0, t1);
+    A[1] = vmax(t2, t3);
+    A[2] = vmax(t4, t5);
+    A[3] = vmax(t6, t7);
+    return (int)(short)(m.y - m.x - g01.y);
+}
+
+// Backward step, Q layout in and out.
+__device__ __forceinline__ void acs_bwd(s2 B[4], s2 g00, s2 g01)
+{
+    const s2 c00 = adds(bcx(B[0]), g00), c01 = swp(adds(bcx(B[2]), g00));
+    const s2 c10 = swp(adds(bcy(B[0]), g01)), c11 = adds(bcy(B[2]), g01);
+    const s2 c20 = adds(bcx(B[1]), g01), c21 = swp(adds(bcx(B[3]), g01));
+    const s2 c30 = swp(adds(bcy(B[1]), g00)), c31 = adds(bcy(B[3]), g00);
+    B[0] = vmax(c00, c01);
+    B[1] = vmax(c10, c11);
+    B[2] = vmax(c20, c21);
+    B[3] = vmax(c30, c31);
+}
+
+// Backward step that also returns the extrinsic from alpha_k (Q layout):
+// the candidate sums beta_{k+1}(n) + gamma(p -> n) plus alpha_k(p).
+__device__ __forceinline__ int acs_bwd_le(s2 B[4], const s2 AQ[4], s2 g00, s2 g01)
+{
+    const s2 c00 = adds(bcx(B[0]), g00), c01 = swp(adds(bcx(B[2]), g00));
+    const s2 c10 = swp(adds(bcy(B[0]), g01)), c11 = adds(bcy(B[2]), g01);
+    const s2 c20 = adds(bcx(B[1]), g01), c21 = swp(adds(bcx(B[3]), g01));
+    const s2 c30 = swp(adds(bcy(B[1]), g00)), c31 = adds(bcy(B[3]), g00);
+    const s2 n = vmax(vmax(adds(AQ[0], c00), adds(AQ[1], c11)),
+                      vmax(adds(AQ[2], c20), adds(AQ[3], c31)));
+    const s2 s = vmax(vmax(adds(AQ[0], c01), adds(AQ[1], c10)),
+                      vmax(adds(AQ[2], c21), adds(AQ[3], c30)));
+    const s2 m = vmax(n, swp(s));
+    B[0] = vmax(c00, c01);
+    B[1] = vmax(c10, c11);
+    B[2] = vmax(c20, c21);
+    B[3] = vmax(c30, c31);
+    return (int)(short)(m.y - m.x - g01.y);
 }
 
 // Shift a metric vector so that its maximum is 0.
@@ -81,31 +151,7 @@ __device__ __forceinline__ void normalise(s2 V[4])
     V[3] = subs(V[3], m);
 }
 
-// Backward step: from beta_{k+1} (Q layout) and the forward metric alpha_k
-// (Q layout) compute the extrinsic Le(k) and replace B by beta_k.
-__device__ __forceinline__ int bwd_le(s2 B[4], const s2 AQ[4], s2 g00, s2 g01)
-{
-    const s2 g11 = swp(g00), g10 = swp(g01);
-    // candidates beta_{k+1}(next) + gamma for the branches of states 2j, 2j+1
-    const s2 c00 = adds(bcx(B[0]), g00), c01 = adds(bcx(B[2]), g11);
-    const s2 c10 = adds(bcy(B[0]), g10), c11 = adds(bcy(B[2]), g01);
-    const s2 c20 = adds(bcx(B[1]), g01), c21 = adds(bcx(B[3]), g10);
-    const s2 c30 = adds(bcy(B[1]), g11), c31 = adds(bcy(B[3]), g00);
-    // alpha + candidate: halves ordered (u=0, u=1) in n, (u=1, u=0) in s
-    const s2 n = vmax(vmax(adds(AQ[0], c00), adds(AQ[1], c11)),
-                      vmax(adds(AQ[2], c20), adds(AQ[3], c31)));
-    const s2 s = vmax(vmax(adds(AQ[0], c01), adds(AQ[1], c10)),
-                      vmax(adds(AQ[2], c21), adds(AQ[3], c30)));
-    const s2 m = vmax(n, swp(s));
-    B[0] = vmax(c00, c01);
-    B[1] = vmax(c10, c11);
-    B[2] = vmax(c20, c21);
-    B[3] = vmax(c30, c31);
-    // Le = M1 - M0 - Lsa, exact modulo 2^16 (the true value fits int16)
-    return (int)(short)(m.y - m.x - g01.y);
-}
-
-__device__ __forceinline__ void to_q(const s2 A[4], s2 Q[4])
+__device__ __forceinline__ void p_to_q(const s2 A[4], s2 Q[4])
 {
     Q[0] = (s2){A[0].x, A[1].x};
     Q[1] = (s2){A[2].x, A[3].x};
@@ -113,21 +159,21 @@ __device__ __forceinline__ void to_q(const s2 A[4], s2 Q[4])
     Q[3] = (s2){A[2].y, A[3].y};
 }
 
-// 0.75 * e truncated toward zero, clamped to +-2047 (clamping e to +-2730
-// first gives the same value and keeps 3e in int16 range).
+__device__ __forceinline__ void q_to_p(const s2 Q[4], s2 P[4])
+{
+    P[0] = (s2){Q[0].x, Q[2].x};
+    P[1] = (s2){Q[0].y, Q[2].y};
+    P[2] = (s2){Q[1].x, Q[3].x};
+    P[3] = (s2){Q[1].y, Q[3].y};
+}
+
+// 0.75 * e truncated toward zero, clamped to +-2047.  Clamping e to +-2730
+// first gives the same value; 0.75 * e is exact in fp32 and the conversion
+// back truncates toward zero.
 __device__ __forceinline__ int scale_ext(int e)
 {
     e = max(-2730, min(2730, e));
-    const int t = 3 * e;
-    return (t + ((t >> 31) & 3)) >> 2;
-}
-
-__device__ __forceinline__ int epad(int j) { return j + (j >> 6); }
-
-__device__ __forceinline__ uint32_t modadd(uint32_t a, uint32_t b, uint32_t K)
-{
-    const uint32_t s = a + b;
-    return min(s, s - K);
+    return (int)((float)e * 0.75f);
 }
 
 __device__ __forceinline__ uint4 pack4(const s2 V[4])
@@ -142,26 +188,9 @@ __device__ __forceinline__ void unpack4(uint4 u, s2 V[4])
     V[3] = as_s2(u.w);
 }
 
-// Everything one lane needs for a constituent pass over its window.
-struct LaneCtx {
-    int K, W, nw, w, lo;
-    uint32_t f2x2;      // 2 f2 mod K
-    uint32_t pi0, g0;   // QPP position and increment at the window start
-    short *E;           // LDS extrinsic / a-priori array of the block (padded)
-    uint32_t *bm;       // LDS hard-decision bitmap of the block
-    const int4 *R1;     // restaged (Lp1 | Ls << 16), [t/4][w] x 4 steps
-    const uint2 *R2;    // restaged Lp2, [t/4][w] x 4 steps
-    uint4 *ck_a;        // forward checkpoints [seg][lane]
-    uint2 *ck_p;        // QPP state at the checkpoints [seg][lane]
-    int lanes;          // lanes of the item (checkpoint stride)
-    int lane;
-    bool first, last;
-};
-
-// Forward metric step i (1-based, counted from the window start) is
-// normalised for i <= 2 and for even i; window 0 re-pins the states that
-// cannot be reached after 1 and 2 steps to minus infinity.
-template <int S>
+// Forward step i = i0 + t + 1 (counted from the window start) is normalised
+// for i <= 2 and for even i; in window 0 the states that cannot be reached
+// after 1 and 2 steps are pinned back to minus infinity.
 __device__ __forceinline__ void fwd_post(s2 A[4], int i0, int t, bool first)
 {
     if ((t & 1) || (i0 == 0 && t == 0)) normalise(A);
@@ -173,152 +202,281 @@ __device__ __forceinline__ void fwd_post(s2 A[4], int i0, int t, bool first)
     }
 }
 
-// One constituent decoder pass over the lane's window.
-//   DEC 1: natural order, systematic + a-priori from E, parity 1; writes
-//          E[j] = Ls[j] + scaled Le[j] (decoder 2's systematic + a-priori).
-//   DEC 2: interleaved order, E[pi(k)] holds Ls + La, parity 2; writes
-//          E[pi(k)] = scaled Le[k] and the hard decision of pi(k).
-// The window's boundary metrics go to the neighbours' slots for the next
-// iteration (alpha at the window end, beta at the window start).
-template <int DEC, int S>
-__device__ void run_pass(const LaneCtx &c, const s2 Ainit[4], const s2 Binit[4], uint4 *bnd_a_out,
-                         uint4 *bnd_b_out)
+// Backward metric at local position i = i0 + t is normalised when W - i <= 2
+// or W - i is even (W and i0 are multiples of 8).
+__device__ __forceinline__ bool bwd_norm(int i0, int t, int W) { return !(t & 1) || (i0 == W - S && t >= S - 2); }
+
+// Everything a lane needs for one constituent pass over its window.
+struct Win {
+    int W, M, lo, wi, lanes;
+    bool first, last;
+    short *E;            // LDS extrinsic array of the block (padded); for decoder 2
+                         // the LDS base, since its addresses include the slot offset
+    const uint4 *R;      // restaged input: [t/4][window] x 4 steps, one int32 per step
+    uint4 *ck;           // checkpoints [segment][window]
+};
+
+// The restaged inputs of 8 steps starting at local step i0.
+__device__ __forceinline__ void load_seg(const Win &c, int i0, uint32_t r[S])
 {
-    const int nseg = c.W / S;
-    s2 A[4] = {Ainit[0], Ainit[1], Ainit[2], Ainit[3]};
-    uint32_t pi = c.pi0, g = c.g0;
-    const uint32_t K = (uint32_t)c.K;
-
-    // ---- forward sweep: checkpoints only
-    for (int seg = 0; seg < nseg; ++seg) {
-        const int i0 = seg * S;
-        c.ck_a[seg * c.lanes + c.lane] = pack4(A);
-        if (DEC == 2) c.ck_p[seg * c.lanes + c.lane] = make_uint2(pi, g);
-        uint32_t r[S];
-        if (DEC == 1) {
-#pragma unroll
-            for (int m = 0; m < S / 4; ++m) {
-                const int4 q = c.R1[((i0 >> 2) + m) * c.nw + c.w];
-                r[4 * m + 0] = q.x;
-                r[4 * m + 1] = q.y;
-                r[4 * m + 2] = q.z;
-                r[4 * m + 3] = q.w;
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < S / 4; ++m) {
-                const uint2 q = c.R2[((i0 >> 2) + m) * c.nw + c.w];
-                r[4 * m + 0] = q.x & 0xFFFFu;
-                r[4 * m + 1] = q.x >> 16;
-                r[4 * m + 2] = q.y & 0xFFFFu;
-                r[4 * m + 3] = q.y >> 16;
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-            s2 g01;
-            if (DEC == 1) {
-                const uint32_t e = (uint16_t)c.E[epad(c.lo + i0 + t)];
-                g01 = as_s2(r[t] + (e << 16));
-            } else {
-                const uint32_t e = (uint16_t)c.E[epad((int)pi)];
-                g01 = as_s2(r[t] | (e << 16));
-                pi = modadd(pi, g, K);
-                g = modadd(g, c.f2x2, K);
-            }
-            acs_fwd(A, mk_g00(g01), g01);
-            fwd_post<S>(A, i0, t, c.first);
-        }
-    }
-    if (!c.last) *bnd_a_out = pack4(A);
-
-    // ---- backward sweep: recompute each segment's forward metrics, then
-    //      run beta over it and emit the extrinsic
-    s2 Bq[4] = {Binit[0], Binit[1], Binit[2], Binit[3]};
-    for (int seg = nseg - 1; seg >= 0; --seg) {
-        const int i0 = seg * S;
-        unpack4(c.ck_a[seg * c.lanes + c.lane], A);
-        if (DEC == 2) {
-            const uint2 p = c.ck_p[seg * c.lanes + c.lane];
-            pi = p.x;
-            g = p.y;
-        }
-        uint32_t r[S];
-        if (DEC == 1) {
-#pragma unroll
-            for (int m = 0; m < S / 4; ++m) {
-                const int4 q = c.R1[((i0 >> 2) + m) * c.nw + c.w];
-                r[4 * m + 0] = q.x;
-                r[4 * m + 1] = q.y;
-                r[4 * m + 2] = q.z;
-                r[4 * m + 3] = q.w;
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < S / 4; ++m) {
-                const uint2 q = c.R2[((i0 >> 2) + m) * c.nw + c.w];
-                r[4 * m + 0] = q.x & 0xFFFFu;
-                r[4 * m + 1] = q.x >> 16;
-                r[4 * m + 2] = q.y & 0xFFFFu;
-                r[4 * m + 3] = q.y >> 16;
-            }
-        }
-        s2 AQ[S][4];
-        s2 G01[S];
-        uint32_t aux[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-            s2 g01;
-            if (DEC == 1) {
-                const uint32_t e = (uint16_t)c.E[epad(c.lo + i0 + t)];
-                g01 = as_s2(r[t] + (e << 16));
-                aux[t] = r[t];
-            } else {
-                const uint32_t e = (uint16_t)c.E[epad((int)pi)];
-                g01 = as_s2(r[t] | (e << 16));
-                aux[t] = pi;
-                pi = modadd(pi, g, K);
-                g = modadd(g, c.f2x2, K);
-            }
-            G01[t] = g01;
-            to_q(A, AQ[t]);
-            acs_fwd(A, mk_g00(g01), g01);
-            fwd_post<S>(A, i0, t, c.first);
-        }
-#pragma unroll
-        for (int t = S - 1; t >= 0; --t) {
-            const s2 g01 = G01[t];
-            const int le = bwd_le(Bq, AQ[t], mk_g00(g01), g01);
-            // beta at local position i0+t; steps from its init = W - i0 - t
-            if (!(t & 1) || (seg == nseg - 1 && t >= S - 2)) normalise(Bq);
-            const int q = scale_ext(le);
-            if (DEC == 1) {
-                const int ls = (int)(short)(aux[t] >> 16);
-                c.E[epad(c.lo + i0 + t)] = (short)(ls + q);
-            } else {
-                const int p = (int)aux[t];
-                c.E[epad(p)] = (short)q;
-                if ((int)g01.y + le > 0) atomicOr(&c.bm[p >> 5], 0x80000000u >> (p & 31));
-            }
-        }
-    }
-    if (!c.first) *bnd_b_out = pack4(Bq);
+    const uint4 q0 = c.R[(size_t)(i0 >> 2) * c.lanes + c.wi];
+    const uint4 q1 = c.R[(size_t)((i0 >> 2) + 1) * c.lanes + c.wi];
+    r[0] = q0.x; r[1] = q0.y; r[2] = q0.z; r[3] = q0.w;
+    r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w;
 }
 
-// CRC (LFSR form, MSB first) of natural bits [b0, b1) of a block's bitmap.
-__device__ uint32_t crc_range(const uint32_t *bm, int b0, int b1, uint32_t poly)
+// Branch metric pairs g01 = (Lp, Lsa) of 8 steps.
+//   decoder 1: r = Lp1 | Ls << 16 and Lsa = Ls + E[j] (natural order, one
+//              ds_read_b128 for the 8 steps);
+//   decoder 2: r = Lp2 | addr << 16 with addr the LDS byte offset of
+//              E[pi(k)], which holds Ls + La for decoder 2.
+template <int DEC>
+__device__ __forceinline__ void gammas(const Win &c, int i0, const uint32_t r[S], s2 g01[S])
+{
+    if (DEC == 1) {
+        const uint4 e = *(const uint4 *)(c.E + epad(c.lo + i0));
+        const uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            // E holds 2 La + hard bit (decoder 2's output); high half of the
+            // sum: Ls + La (no carry between halves); low half: Lp
+            const s2 la2 = as_s2(ew[t >> 1]) >> (s2){1, 1};
+            const s2 ee = (t & 1) ? la2 : swp(la2);
+            const s2 sum = as_s2(r[t]) + ee;
+            g01[t] = as_s2(__builtin_amdgcn_perm(as_u(sum), r[t], 0x07060100u));
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const uint32_t e = *(const uint16_t *)((const char *)c.E + (r[t] >> 16));
+            g01[t] = as_s2(__builtin_amdgcn_perm(e, r[t], 0x05040100u));
+        }
+    }
+}
+
+// Output of one step: decoder 1 stores Ls + scaled Le (decoder 2's
+// systematic + a-priori) at its natural position; decoder 2 stores twice the
+// scaled Le (decoder 1's next a-priori) plus the hard decision of pi(k) in
+// the low bit.  The hard decisions stay readable from the low bits until the
+// next decoder-1 pass, i.e. through the CRC check and the output.
+template <int DEC>
+__device__ __forceinline__ void emit(const Win &c, int i0, int t, uint32_t r, s2 g01, int le)
+{
+    const int q = scale_ext(le);
+    if (DEC == 1) {
+        c.E[epad(c.lo + i0) + t] = (short)((int)(short)(r >> 16) + q);
+    } else {
+        const uint32_t a = r >> 16;
+        const int bit = (int)g01.y + le > 0;
+        *(short *)((char *)c.E + a) = (short)(2 * q + bit);
+    }
+}
+
+// Every phase loop prefetches the next segment's restaged inputs (and, in
+// phase 2, its checkpoint) one segment ahead; the last segment reloads itself.
+
+// ---- phase 1, forward-first lane: alpha over [0, M) with checkpoints.
+template <int DEC>
+__device__ void ph1_fwd(const Win &c, s2 A[4])
+{
+    if (c.M <= 0) return;
+    uint32_t r[S];
+    load_seg(c, 0, r);
+    for (int i0 = 0; i0 < c.M; i0 += S) {
+        uint32_t rn[S];
+        load_seg(c, min(i0 + S, c.M - S), rn);
+        c.ck[(size_t)(i0 / S) * c.lanes + c.wi] = pack4(A);
+        s2 g[S];
+        gammas<DEC>(c, i0, r, g);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            acs_fwd(A, mk_g00(g[t]), g[t]);
+            fwd_post(A, i0, t, c.first);
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) r[t] = rn[t];
+    }
+}
+
+// ---- phase 1, backward-first lane: beta over [M, W) with checkpoints
+// (beta at the end of every segment).
+template <int DEC>
+__device__ void ph1_bwd(const Win &c, s2 B[4])
+{
+    uint32_t r[S];
+    load_seg(c, c.W - S, r);
+    for (int i0 = c.W - S; i0 >= c.M; i0 -= S) {
+        uint32_t rn[S];
+        load_seg(c, max(i0 - S, c.M), rn);
+        c.ck[(size_t)(i0 / S) * c.lanes + c.wi] = pack4(B);
+        s2 g[S];
+        gammas<DEC>(c, i0, r, g);
+#pragma unroll
+        for (int t = S - 1; t >= 0; --t) {
+            acs_bwd(B, mk_g00(g[t]), g[t]);
+            if (bwd_norm(i0, t, c.W)) normalise(B);
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) r[t] = rn[t];
+    }
+}
+
+// Phase 2 is software-pipelined: the recomputation of the next segment (it
+// depends only on that segment's checkpoint) is interleaved step by step with
+// the extrinsic pass over the current segment, which doubles the independent
+// work available to each wave.  Inputs are fetched two segments ahead.
+
+__device__ __forceinline__ uint4 ck_at(const Win &c, int i0)
+{
+    return c.ck[(size_t)(i0 / S) * c.lanes + c.wi];
+}
+
+// ---- phase 2, forward-first lane: the upper half [M, W) in forward order.
+// Per segment: beta recomputed backward from the checkpoint at its end, then
+// alpha forward over it with the extrinsic.
+template <int DEC>
+__device__ void ph2_fwd(const Win &c, s2 A[4])
+{
+    if (c.M >= c.W) return;
+    const int last = c.W - S;
+    int i0 = c.M;
+    uint32_t r[S], rn[S], rnn[S];
+    s2 g[S], g0[S], BP[S][4];
+    load_seg(c, i0, r);
+    uint4 ckn = ck_at(c, min(i0 + S, last));
+    load_seg(c, min(i0 + S, last), rn);
+    {
+        s2 B[4];
+        unpack4(ck_at(c, i0), B);
+        gammas<DEC>(c, i0, r, g);
+#pragma unroll
+        for (int t = S - 1; t >= 0; --t) {
+            q_to_p(B, BP[t]);
+            g0[t] = mk_g00(g[t]);
+            acs_bwd(B, g0[t], g[t]);
+            if (bwd_norm(i0, t, c.W)) normalise(B);
+        }
+    }
+    for (; i0 < last; i0 += S) {
+        const int i1 = i0 + S;
+        load_seg(c, min(i1 + S, last), rnn);
+        const uint4 cknn = ck_at(c, min(i1 + S, last));
+        s2 Bn[4], gn[S], g0n[S], BPn[S][4];
+        unpack4(ckn, Bn);
+        gammas<DEC>(c, i1, rn, gn);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int u = S - 1 - t;  // recompute step of the next segment
+            q_to_p(Bn, BPn[u]);
+            g0n[u] = mk_g00(gn[u]);
+            acs_bwd(Bn, g0n[u], gn[u]);
+            if (bwd_norm(i1, u, c.W)) normalise(Bn);
+            const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
+            fwd_post(A, i0, t, c.first);
+            emit<DEC>(c, i0, t, r[t], g[t], le);
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            r[t] = rn[t];
+            rn[t] = rnn[t];
+            g[t] = gn[t];
+            g0[t] = g0n[t];
+            BP[t][0] = BPn[t][0];
+            BP[t][1] = BPn[t][1];
+            BP[t][2] = BPn[t][2];
+            BP[t][3] = BPn[t][3];
+        }
+        ckn = cknn;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
+        fwd_post(A, i0, t, c.first);
+        emit<DEC>(c, i0, t, r[t], g[t], le);
+    }
+}
+
+// ---- phase 2, backward-first lane: the lower half [0, M) in backward order.
+// Per segment: alpha recomputed forward from the checkpoint at its start,
+// then beta backward over it with the extrinsic.
+template <int DEC>
+__device__ void ph2_bwd(const Win &c, s2 B[4])
+{
+    if (c.M <= 0) return;
+    int i0 = c.M - S;
+    uint32_t r[S], rn[S], rnn[S];
+    s2 g[S], g0[S], AQ[S][4];
+    load_seg(c, i0, r);
+    uint4 ckn = ck_at(c, max(i0 - S, 0));
+    load_seg(c, max(i0 - S, 0), rn);
+    {
+        s2 A[4];
+        unpack4(ck_at(c, i0), A);
+        gammas<DEC>(c, i0, r, g);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            p_to_q(A, AQ[t]);
+            g0[t] = mk_g00(g[t]);
+            acs_fwd(A, g0[t], g[t]);
+            fwd_post(A, i0, t, c.first);
+        }
+    }
+    for (; i0 > 0; i0 -= S) {
+        const int i1 = i0 - S;
+        load_seg(c, max(i1 - S, 0), rnn);
+        const uint4 cknn = ck_at(c, max(i1 - S, 0));
+        s2 An[4], gn[S], g0n[S], AQn[S][4];
+        unpack4(ckn, An);
+        gammas<DEC>(c, i1, rn, gn);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            p_to_q(An, AQn[t]);  // recompute step of the next segment
+            g0n[t] = mk_g00(gn[t]);
+            acs_fwd(An, g0n[t], gn[t]);
+            fwd_post(An, i1, t, c.first);
+            const int u = S - 1 - t;
+            const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
+            if (bwd_norm(i0, u, c.W)) normalise(B);
+            emit<DEC>(c, i0, u, r[u], g[u], le);
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            r[t] = rn[t];
+            rn[t] = rnn[t];
+            g[t] = gn[t];
+            g0[t] = g0n[t];
+            AQ[t][0] = AQn[t][0];
+            AQ[t][1] = AQn[t][1];
+            AQ[t][2] = AQn[t][2];
+            AQ[t][3] = AQn[t][3];
+        }
+        ckn = cknn;
+    }
+#pragma unroll
+    for (int u = S - 1; u >= 0; --u) {
+        const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
+        if (bwd_norm(i0, u, c.W)) normalise(B);
+        emit<DEC>(c, i0, u, r[u], g[u], le);
+    }
+}
+
+// Hard decision of natural position j: the low bit of E after decoder 2.
+__device__ __forceinline__ uint32_t hard_bit(const short *E, int j) { return (uint32_t)E[epad(j)] & 1u; }
+
+// CRC (LFSR form, MSB first) of natural bits [b0, b1) of a block.
+__device__ uint32_t crc_range(const short *E, int b0, int b1, uint32_t poly)
 {
     uint32_t r = 0;
-    int b = b0;
-    while (b < b1) {
-        uint32_t wd = bm[b >> 5] << (b & 31);
-        const int n = min(32 - (b & 31), b1 - b);
-        for (int q = 0; q < n; ++q) {
-            const uint32_t top = ((r >> 23) ^ (wd >> 31)) & 1u;
-            r = ((r << 1) & 0xFFFFFFu) ^ (top ? poly : 0u);
-            wd <<= 1;
+    for (int j = b0 & ~7; j < b1; j += 8) {
+        const uint4 v = *(const uint4 *)(E + epad(j));  // 8 positions, 16-byte aligned
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t bit = (w[q >> 1] >> (16 * (q & 1))) & 1u;
+            const uint32_t top = ((r >> 23) ^ bit) & 1u;
+            const uint32_t nr = ((r << 1) & 0xFFFFFFu) ^ (top ? poly : 0u);
+            r = (j + q >= b0 && j + q < b1) ? nr : r;
         }
-        b += n;
     }
     return r;
 }
@@ -342,45 +500,105 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
     __shared__ int s_iters[kMaxSlotsPerWg];
     __shared__ int s_ok[kMaxSlotsPerWg];
 
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = blockDim.x, half = nthr >> 1;
+    const bool bwd_first = tid >= half;       // wave-uniform role
+    const int wi = bwd_first ? tid - half : tid;  // window index within the item
     char *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
 
-    for (int item_i = blockIdx.x; item_i < a.n_items; item_i += gridDim.x) {
+    // Items are handed out dynamically: every work group starts with item
+    // blockIdx.x and then takes the next unclaimed one from a counter, so
+    // blocks that stop early free their work group for more work.  The last
+    // work group to finish resets the counter for the next launch.
+    __shared__ int s_next;
+    for (int item_i = blockIdx.x; item_i < a.n_items; item_i = s_next) {
         const DecItem it = a.items[item_i];
-        const int K = it.K, nw = it.nw, W = it.W, ncb = it.ncb, S = it.S;
+        const int K = it.K, nw = it.nw, W = it.W, ncb = it.ncb;
         const int lanes = ncb * nw;
-        // global scratch layout of this item
-        int4 *R1all = (int4 *)scr;                                   // ncb * K * 4 B
-        uint16_t *R2all = (uint16_t *)(scr + (int64_t)ncb * K * 4);  // ncb * K * 2 B
-        char *p = scr + (int64_t)ncb * K * 6;
-        const int nseg = W / S;
-        uint4 *ck_a = (uint4 *)p;
-        p += (int64_t)nseg * lanes * 16;
-        uint2 *ck_p = (uint2 *)p;
-        p += ((int64_t)nseg * lanes * 8 + 15) & ~(int64_t)15;
-        uint4 *bnd = (uint4 *)p;  // [dec 2][alpha/beta 2][lanes]
+        // global scratch of this item: restaged inputs of both decoders,
+        // checkpoints, window boundary metrics
+        uint32_t *R1 = (uint32_t *)scr;                          // ncb*K int32
+        uint32_t *R2 = R1 + (int64_t)ncb * K;                    // ncb*K int32
+        uint4 *ck = (uint4 *)(R2 + (int64_t)ncb * K);            // (W/S)*lanes
+        uint4 *bnd = ck + (int64_t)(W / S) * lanes;              // [4][lanes]
 
-        // ---- restage the channel LLRs, clear the extrinsic arrays
-        const int ewords = (epad(K - 1) + 2) / 2;  // int32 words of E
-        const int bwords = (int)hard_words(K);
-        for (int cs = 0; cs < ncb; ++cs) {
-            const DecCb cb = a.cbs[it.cb0 + cs];
-            const int16_t *src = a.llr + cb.llr_off;
-            const int N = K + 4;
-            short *r1h = (short *)(R1all) + (int64_t)cs * K * 2;
-            uint16_t *r2 = R2all + (int64_t)cs * K;
-            for (int pp = tid; pp < K; pp += nthr) {
-                const int ww = pp / W, t = pp - ww * W;
-                const int idx = ((t >> 2) * nw + ww) * 4 + (t & 3);
-                short ls = clamp_llr(src[pp]), lp1 = clamp_llr(src[N + pp]);
-                const short lp2 = clamp_llr(src[2 * N + pp]);
-                if (pp < cb.F) ls = lp1 = -kLlrMax;
-                r1h[2 * idx] = lp1;
-                r1h[2 * idx + 1] = ls;
-                r2[idx] = (uint16_t)lp2;
+        // ---- restage the channel LLRs, clear LDS.  One unit = 4 trellis
+        // steps of one window; consecutive threads take consecutive windows,
+        // so every 16-byte store is part of a contiguous run; each thread
+        // keeps 4 units of loads in flight.
+        {
+            const int esz = lds_e_bytes(K);
+            const int units = K >> 2;
+            const uint2 *qt = (const uint2 *)(a.qtab + it.qtab);
+            uint4 *R1v = (uint4 *)R1, *R2v = (uint4 *)R2;
+            for (int cs = 0; cs < ncb; ++cs) {
+                const DecCb cb = a.cbs[it.cb0 + cs];
+                const int16_t *src = a.llr + cb.llr_off;
+                const int N = K + 4;
+                const bool aligned = (cb.llr_off & 3) == 0;
+                const uint32_t so = (uint32_t)(cs * it.lds_slot);
+                const uint32_t so2 = so | (so << 16);
+                for (int u0 = tid; u0 < units; u0 += 4 * nthr) {
+                    uint2 v[4][3], q[4];
+                    int pos[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int u = min(u0 + m * nthr, units - 1);
+                        const int t4 = u / nw, ww = u - t4 * nw;
+                        const int p = ww * W + 4 * t4;
+                        pos[m] = p;
+                        q[m] = qt[u];
+                        if (aligned) {
+                            v[m][0] = *(const uint2 *)(src + p);
+                            v[m][1] = *(const uint2 *)(src + N + p);
+                            v[m][2] = *(const uint2 *)(src + 2 * N + p);
+                        } else {
+#pragma unroll
+                            for (int st = 0; st < 3; ++st) {
+                                const int16_t *s0 = src + st * N + p;
+                                v[m][st] = make_uint2((uint16_t)s0[0] | ((uint32_t)(uint16_t)s0[1] << 16),
+                                                      (uint16_t)s0[2] | ((uint32_t)(uint16_t)s0[3] << 16));
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int u = u0 + m * nthr;
+                        if (u >= units) break;
+                        const int t4 = u / nw, ww = u - t4 * nw;
+                        const s2 lo = (s2){(short)-kLlrMax, (short)-kLlrMax};
+                        const s2 hi = (s2){(short)kLlrMax, (short)kLlrMax};
+                        uint32_t ls[2], lp[2], z[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            ls[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][0].y : v[m][0].x), hi), lo));
+                            lp[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][1].y : v[m][1].x), hi), lo));
+                            z[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][2].y : v[m][2].x), hi), lo));
+                        }
+                        if (pos[m] < cb.F) {  // filler: systematic and parity 1 are known zeros
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                if (pos[m] + j < cb.F) {
+                                    const uint32_t msk = 0xFFFFu << (16 * (j & 1));
+                                    const uint32_t neg = 0xF801F801u & msk;  // -2047 in that half
+                                    ls[j >> 1] = (ls[j >> 1] & ~msk) | neg;
+                                    lp[j >> 1] = (lp[j >> 1] & ~msk) | neg;
+                                }
+                        }
+                        const uint32_t qa0 = q[m].x + so2, qa1 = q[m].y + so2;
+                        const size_t o = (size_t)t4 * lanes + cs * nw + ww;
+                        R1v[o] = make_uint4(__builtin_amdgcn_perm(ls[0], lp[0], 0x05040100u),
+                                            __builtin_amdgcn_perm(ls[0], lp[0], 0x07060302u),
+                                            __builtin_amdgcn_perm(ls[1], lp[1], 0x05040100u),
+                                            __builtin_amdgcn_perm(ls[1], lp[1], 0x07060302u));
+                        R2v[o] = make_uint4(__builtin_amdgcn_perm(qa0, z[0], 0x05040100u),
+                                            __builtin_amdgcn_perm(qa0, z[0], 0x07060302u),
+                                            __builtin_amdgcn_perm(qa1, z[1], 0x05040100u),
+                                            __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
+                    }
+                }
+                uint32_t *slot = (uint32_t *)(lds + (int64_t)cs * it.lds_slot);
+                for (int q = tid; q < esz / 4; q += nthr) slot[q] = 0;
             }
-            uint32_t *slot = (uint32_t *)(lds + (int64_t)cs * it.lds_slot);
-            for (int q = tid; q < ewords + bwords; q += nthr) slot[q] = 0;
         }
         if (tid < ncb) {
             s_done[tid] = 0;
@@ -388,38 +606,28 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
             s_ok[tid] = 0;
         }
 
-        // ---- lane role
-        const bool active = tid < lanes;
-        const int cs = active ? tid / nw : 0;
-        const int w = active ? tid - cs * nw : 0;
-        const DecCb cb = a.cbs[it.cb0 + (active ? cs : 0)];
-        LaneCtx lc;
-        lc.K = K;
-        lc.W = W;
-        lc.nw = nw;
-        lc.w = w;
-        lc.lo = w * W;
-        lc.f2x2 = (uint32_t)((2 * it.f2) % K);
-        {
-            const uint64_t k0 = (uint64_t)w * W;
-            lc.pi0 = (uint32_t)(((uint64_t)it.f1 * k0 + (uint64_t)it.f2 * ((k0 * k0) % K)) % K);
-            lc.g0 = (uint32_t)(((uint64_t)it.f1 + (uint64_t)it.f2 * (2 * k0 + 1)) % K);
-        }
-        lc.E = (short *)(lds + (int64_t)cs * it.lds_slot);
-        lc.bm = (uint32_t *)(lds + (int64_t)cs * it.lds_slot) + ewords;
-        lc.R1 = R1all + (int64_t)cs * K / 4;
-        lc.R2 = (const uint2 *)(R2all + (int64_t)cs * K);
-        lc.ck_a = ck_a;
-        lc.ck_p = ck_p;
-        lc.lanes = lanes;
-        lc.lane = tid;
-        lc.first = w == 0;
-        lc.last = w == nw - 1;
+        // ---- lane role within the item
+        const bool active = wi < lanes;
+        const int cs = active ? wi / nw : 0;
+        const int w = active ? wi - cs * nw : 0;
+        const DecCb cb = a.cbs[it.cb0 + cs];
+        Win c;
+        c.W = W;
+        c.M = win_split(W);
+        c.lo = w * W;
+        c.wi = wi;
+        c.lanes = lanes;
+        c.first = w == 0;
+        c.last = w == nw - 1;
+        c.E = (short *)(lds + (int64_t)cs * it.lds_slot);
+        c.ck = ck;
+        // decoder 2 addresses E through byte offsets from the slot of block 0
+        short *E0 = (short *)lds;
 
-        // trellis termination: beta_K of both encoders (Q layout), closed form
-        // along the forced zero-feedback path from each state
+        // trellis termination of both encoders: beta_K (Q layout) in closed
+        // form along the forced zero-feedback path from each state
         s2 tb[2][4];
-        if (active && lc.last) {
+        if (active && c.last && bwd_first) {
             const int16_t *src = a.llr + cb.llr_off;
             const int N = K + 4;
             for (int d = 0; d < 2; ++d) {
@@ -445,60 +653,59 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
         for (int iter = 1; iter <= a.max_iters; ++iter) {
             const bool run = active && !s_done[cs];
             const bool prev = a.win_init && iter > 1;
-            if (run) {
-                // clear this block's bitmap and CRC accumulator for decoder 2
-                for (int q = w; q < bwords; q += nw) lc.bm[q] = 0;
-                if (w == 0) s_crc[cs] = 0;
-                s2 Ai[4], Bi[4];
-                const s2 z = (s2){0, 0};
-                if (lc.first) {
-                    Ai[0] = (s2){0, kNeg};
-                    Ai[1] = Ai[2] = Ai[3] = (s2){kNeg, kNeg};
-                } else if (prev) {
-                    unpack4(bnd[0 * lanes + tid], Ai);
-                } else {
-                    Ai[0] = Ai[1] = Ai[2] = Ai[3] = z;
+            const s2 z = (s2){0, 0};
+            s2 V[4];  // this lane's running metric (alpha or beta)
+#pragma unroll
+            for (int dec = 1; dec <= 2; ++dec) {
+                Win cd = c;
+                cd.R = (const uint4 *)(dec == 1 ? R1 : R2);
+                if (dec == 2) cd.E = E0;
+                uint4 *bA = bnd + (dec - 1) * 2 * lanes;  // alpha boundaries of this decoder
+                uint4 *bB = bA + lanes;                   // beta boundaries
+                if (run) {
+                    if (dec == 1 && w == 0 && !bwd_first) s_crc[cs] = 0;
+                    if (!bwd_first) {
+                        if (c.first) {
+                            V[0] = (s2){0, kNeg};
+                            V[1] = V[2] = V[3] = (s2){kNeg, kNeg};
+                        } else if (prev) {
+                            unpack4(bA[wi], V);
+                        } else {
+                            V[0] = V[1] = V[2] = V[3] = z;
+                        }
+                        if (dec == 1) ph1_fwd<1>(cd, V); else ph1_fwd<2>(cd, V);
+                    } else {
+                        if (c.last) {
+                            for (int j = 0; j < 4; ++j) V[j] = tb[dec - 1][j];
+                        } else if (prev) {
+                            unpack4(bB[wi], V);
+                        } else {
+                            V[0] = V[1] = V[2] = V[3] = z;
+                        }
+                        if (dec == 1) ph1_bwd<1>(cd, V); else ph1_bwd<2>(cd, V);
+                    }
                 }
-                if (lc.last) {
-                    for (int j = 0; j < 4; ++j) Bi[j] = tb[0][j];
-                } else if (prev) {
-                    unpack4(bnd[1 * lanes + tid], Bi);
-                } else {
-                    Bi[0] = Bi[1] = Bi[2] = Bi[3] = z;
+                __syncthreads();
+                if (run) {
+                    if (!bwd_first) {
+                        if (dec == 1) ph2_fwd<1>(cd, V); else ph2_fwd<2>(cd, V);
+                        if (!c.last) bA[wi + 1] = pack4(V);  // alpha at the window end
+                    } else {
+                        if (dec == 1) ph2_bwd<1>(cd, V); else ph2_bwd<2>(cd, V);
+                        if (!c.first) bB[wi - 1] = pack4(V);  // beta at the window start
+                    }
                 }
-                run_pass<1, 8>(lc, Ai, Bi, &bnd[0 * lanes + tid + 1], &bnd[1 * lanes + tid - 1]);
+                __syncthreads();
             }
-            __syncthreads();
-            if (run) {
-                s2 Ai[4], Bi[4];
-                const s2 z = (s2){0, 0};
-                if (lc.first) {
-                    Ai[0] = (s2){0, kNeg};
-                    Ai[1] = Ai[2] = Ai[3] = (s2){kNeg, kNeg};
-                } else if (prev) {
-                    unpack4(bnd[2 * lanes + tid], Ai);
-                } else {
-                    Ai[0] = Ai[1] = Ai[2] = Ai[3] = z;
-                }
-                if (lc.last) {
-                    for (int j = 0; j < 4; ++j) Bi[j] = tb[1][j];
-                } else if (prev) {
-                    unpack4(bnd[3 * lanes + tid], Bi);
-                } else {
-                    Bi[0] = Bi[1] = Bi[2] = Bi[3] = z;
-                }
-                run_pass<2, 8>(lc, Ai, Bi, &bnd[2 * lanes + tid + 1], &bnd[3 * lanes + tid - 1]);
-            }
-            __syncthreads();
-            const bool check = run && cb.crc != 0 && (a.early_stop || iter == a.max_iters);
+            const bool check = run && !bwd_first && cb.crc != 0 && (a.early_stop || iter == a.max_iters);
             if (check) {
-                const int b0 = max((int)cb.F, lc.lo), b1 = lc.lo + W;
-                uint32_t r = b0 < b1 ? crc_range(lc.bm, b0, b1, poly) : 0u;
+                const int b0 = max((int)cb.F, c.lo), b1 = c.lo + W;
+                uint32_t r = b0 < b1 ? crc_range(c.E, b0, b1, poly) : 0u;
                 r = crc_shift(r, K - b1, T);
                 if (r) atomicXor(&s_crc[cs], r);
             }
             __syncthreads();
-            if (run && w == 0) {
+            if (run && w == 0 && !bwd_first) {
                 const bool pass = cb.crc == 0 || s_crc[cs] == 0;
                 if (a.early_stop && cb.crc != 0 && pass) {
                     s_done[cs] = 1;
@@ -513,8 +720,8 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
             if (!__syncthreads_or(active && !s_done[cs])) break;
         }
 
-        // ---- outputs
-        if (active) {
+        // ---- outputs (the forward-first lanes of each block)
+        if (active && !bwd_first) {
             const int L = cb.crc ? 24 : 0;
             if (cb.bits_off >= 0 && a.bits) {
                 const int nbits = K - cb.F - L;
@@ -522,16 +729,22 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
                 uint8_t *out = a.bits + cb.bits_off;
                 for (int bb = w; bb < nbytes; bb += nw) {
                     const int pos = cb.F + 8 * bb;
-                    const uint64_t two = ((uint64_t)lc.bm[pos >> 5] << 32) | lc.bm[(pos >> 5) + 1];
-                    uint32_t byte = (uint32_t)(two >> (56 - (pos & 31))) & 0xFFu;
                     const int valid = min(8, nbits - 8 * bb);
-                    byte &= (0xFFu << (8 - valid)) & 0xFFu;
+                    uint32_t byte = 0;
+                    for (int k = 0; k < 8; ++k)
+                        byte = (byte << 1) | (k < valid ? hard_bit(c.E, pos + k) : 0u);
                     out[bb] = (uint8_t)byte;
                 }
             }
             if (cb.hard_off >= 0 && a.hard) {
                 uint32_t *h = a.hard + cb.hard_off;
-                for (int q = w; q < bwords; q += nw) h[q] = lc.bm[q];
+                const int hw = (int)hard_words(K);
+                for (int q = w; q < hw; q += nw) {
+                    uint32_t v = 0;
+                    for (int k = 0; k < 32; ++k)
+                        v = (v << 1) | (32 * q + k < K ? hard_bit(c.E, 32 * q + k) : 0u);
+                    h[q] = v;
+                }
             }
             if (w == 0) {
                 a.crc_ok[cb.out_idx] = (uint8_t)s_ok[cs];
@@ -539,6 +752,15 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
             }
         }
         __syncthreads();
+        if (tid == 0) s_next = (int)gridDim.x + (int)atomicAdd(&a.counter[0], 1u);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.counter[1], 1u) == gridDim.x - 1) {
+            atomicExch(&a.counter[0], 0u);
+            atomicExch(&a.counter[1], 0u);
+        }
     }
 }
 

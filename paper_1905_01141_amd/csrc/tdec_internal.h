@@ -16,6 +16,7 @@ constexpr uint32_t kPoly24A = 0x864CFBu;  // D^24+D^23+D^18+D^17+D^14+D^11+D^10+
 constexpr uint32_t kPoly24B = 0x800063u;  // D^24+D^23+D^6+D^5+D+1
 constexpr int kMaxSlotsPerWg = 64;        // code blocks per work group
 constexpr int kMaxWgThreads = 256;
+constexpr int kSeg = 8;  // trellis steps per checkpoint segment
 
 // Host-side tables (tables.cpp).
 int k_index(int32_t K);             // index in the size table or -1
@@ -31,9 +32,8 @@ struct DecItem {
     int32_t K, nw, W, ncb;
     int32_t cb0;     // first entry of this item in the code block list
     int32_t f1, f2;  // QPP coefficients
-    int32_t S;       // trellis steps per checkpoint segment (8 or 16; divides W)
-    int32_t lds_slot;  // LDS bytes per code block slot (extrinsic array + bitmap)
-    int32_t rsv;
+    int32_t lds_slot;  // LDS bytes per code block slot (extrinsic array)
+    int32_t qtab;      // element offset of this shape's QPP address table in DecArgs::qtab
 };
 
 // One code block of the decode kernel's list.
@@ -59,6 +59,11 @@ struct DecArgs {
     const uint32_t *crc_tab;  // [2][kCrcTabN]: 24A then 24B
     char *scratch;
     int64_t scratch_stride;   // bytes of global scratch per work group
+    uint32_t *counter;        // [2]: next item, finished work groups (zero between launches)
+    // QPP address tables, one per (K, windows) shape: for unit u = t4 * nw + w
+    // (4 trellis steps of window w) the LDS byte offsets 2 * epad(pi(k)),
+    // k = w * W + 4 * t4 + j, j = 0..3, relative to the block's slot
+    const uint16_t *qtab;
     int32_t max_iters, early_stop, win_init;
 };
 
@@ -75,6 +80,16 @@ struct TbItem {
 
 // Words of hard-decision storage per code block: the K bits plus one spare word.
 __host__ __device__ inline int64_t hard_words(int32_t K) { return (K + 31) / 32 + 1; }
+
+// LDS layout of one code block slot of the decode kernel: the extrinsic
+// array (int16, padded with 8 entries after every 64 so that windows start in
+// different banks).  After decoder 2 its low bits hold the hard decisions.
+__host__ __device__ inline int32_t epad(int32_t j) { return j + ((j >> 6) << 3); }
+__host__ __device__ inline int32_t lds_e_bytes(int32_t K) { return ((epad(K - 1) + 1) * 2 + 15) & ~15; }
+__host__ __device__ inline int32_t lds_slot_bytes(int32_t K) { return (lds_e_bytes(K) + 63) & ~63; }
+// Split point of a window of W steps between its forward-first lane
+// (steps [0, M)) and its backward-first lane (steps [M, W)).
+__host__ __device__ inline int32_t win_split(int32_t W) { return (W / 16) * 8; }
 
 // One code block for the encoder kernel.
 struct EncCb {
