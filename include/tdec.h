@@ -182,6 +182,52 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
                             const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
                             void *stream);
 
+/* ---------------------------------------------------------------- captured launches */
+/* A fixed batch, planned once and captured (with its own device copy of the
+ * plan) into a HIP graph that replays the whole decode -- one persistent
+ * launch for code blocks, decode + transport block assembly for transport
+ * blocks -- with a single hipGraphLaunch.  It serves the case the paper's
+ * scheduler is built for: every TTI brings a batch of the same shape (the
+ * same cells and allocations), so the launch can be prepared once.
+ *
+ * The graph binds every pointer given at capture time; a replay decodes the
+ * current contents of d_llr into the same outputs.  It uses the context's
+ * workspace, so replays obey the context's rule: no two calls (direct or
+ * replayed) of one context run at the same time.  The kernels reset their
+ * own work counter, so the graph holds no memset node.  Arguments and errors
+ * are those of cb_decode_batch / tb_decode_batch; ENOMEM also when the
+ * plan's device copy cannot be allocated. */
+typedef struct tdec_graph tdec_graph;
+tdec_status tdec_graph_cb_decode(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                                 const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                                 uint8_t *d_crc_ok, uint8_t *d_iters, tdec_graph **out);
+tdec_status tdec_graph_tb_decode(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                 const int64_t *llr_off, const int64_t *bits_off,
+                                 const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                                 tdec_tb_result *d_res, tdec_graph **out);
+/* Enqueue one replay on `stream`. */
+tdec_status tdec_graph_launch(tdec_graph *g, void *stream);
+void tdec_graph_destroy(tdec_graph *g);
+
+/* ---------------------------------------------------------------- autotuner */
+/* Choose the window count of each code block size by measurement: for every
+ * K in Ks (host array of n_k table sizes), time a batch of
+ * max(1, batch_bits / K) blocks (at most 16384) at max_iters iterations
+ * without early stop (the decode time does not depend on the LLR values
+ * then, so the batch holds zeros) for every window count n with K % n == 0,
+ * K/n a multiple of 8, K/n >= min_W (n = 1 always qualifies) and n <= 128,
+ * and keep the fastest per decoded bit.  min_W (>= 8) is the error-rate
+ * floor: shorter windows decode worse.  The choice becomes what n_windows = 0 and tdec_pick_windows use on
+ * this context; out_nw / out_ns_per_kbit (host, n_k entries, each may be
+ * NULL) receive the choice and its time in ns per 1000 code block bits.
+ * Runs on `stream` and synchronises it; allocates and frees temporary
+ * device buffers. */
+tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t min_W,
+                          int32_t max_iters, int64_t batch_bits, int32_t *out_nw,
+                          float *out_ns_per_kbit, void *stream);
+/* Forget every tuned choice (back to the built-in rule). */
+void tdec_autotune_reset(tdec_ctx *ctx);
+
 /* ---------------------------------------------------------------- encoding */
 /* The rate-1/3 turbo encoder of the paper's encoding function (Sec. IV-B,
  * Fig. 3): two RSC encoders separated by the QPP interleaver, output

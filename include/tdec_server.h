@@ -1,0 +1,141 @@
+/*
+ * tdec_server.h -- serving loop of libtdec (C ABI).
+ *
+ * The GPU counterpart of the paper's channel coding thread pool (Sec. IV-B
+ * "Thread-pool", Sec. IV-C "Queuing principles", Algorithms 1 and 2): every
+ * TTI a batch of transport blocks arrives; the paper queues their code blocks
+ * and lets free cores pick them up in FIFO order, each running a whole decode
+ * without preemption.  Here a native worker thread takes everything that is
+ * waiting and decodes it as one persistent launch (code block parallelism
+ * inside the launch, as in the paper's finest granularity), then hands the
+ * bits and flags back in host memory.  The paper's performance captor
+ * (Sec. IV-D) becomes the per-TB latency record: arrival to results in host
+ * memory, with p50/p99 and the count of deadline misses.
+ *
+ * Admission happens at submission:
+ *   - budget: the TB's LLRs must fit in the server's device-resident slot
+ *     arena (hbm budget); otherwise it is rejected (TDEC_SERVE_REJ_BUDGET);
+ *   - deadline: with admission bit TDEC_ADMIT_DEADLINE set, a TB whose
+ *     predicted completion (queue ahead of it plus its own decode, from a
+ *     service-time model learned from past launches) lies beyond its arrival
+ *     plus deadline_us is rejected (TDEC_SERVE_REJ_DEADLINE).  A TB that is
+ *     admitted and still finishes late counts as a deadline miss.
+ * Admitted TBs have their LLRs copied asynchronously into their slot on a
+ * copy stream; the decode launch waits for those copies on the device.
+ *
+ * Threading: submit, poll and stats may be called from any host thread (the
+ * server serialises them); the server's worker thread is the only user of
+ * the decoder context it was given, which must not be used by anyone else
+ * while the server exists.
+ *
+ * Modelled executor: tdec_server_create_model runs the same queueing,
+ * admission, batching and statistics with no device at all; a "launch"
+ * sleeps for max(lat_ns, ns_per_kbit * K-kbits of the batch) and reports
+ * every TB as decoded (tb_ok = 1).  It exists to test the scheduler and to
+ * plan capacity on a host without a GPU.
+ */
+#ifndef TDEC_SERVER_H
+#define TDEC_SERVER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tdec.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TDEC_SERVE_CONTINUOUS = 0, /* decode everything waiting as one launch whenever the GPU is free */
+    TDEC_SERVE_PER_TB = 1      /* one launch per TB in arrival order (the plain form, for comparison) */
+};
+enum { TDEC_ADMIT_BUDGET = 1, TDEC_ADMIT_DEADLINE = 2 };
+enum {
+    TDEC_SERVE_DONE = 0,         /* decoded; tb_ok tells whether CRC24A passed */
+    TDEC_SERVE_REJ_BUDGET = 1,   /* rejected at submission: slot arena full */
+    TDEC_SERVE_REJ_DEADLINE = 2, /* rejected at submission: predicted to miss its deadline */
+    TDEC_SERVE_REJ_INVALID = 3,  /* rejected at submission: tbs out of range or C > 64 */
+    TDEC_SERVE_ERROR = 4         /* admitted, but its launch failed (a HIP error) */
+};
+
+typedef struct {
+    size_t slot_budget_bytes; /* device bytes for resident LLR slots (0 = 1 GiB) */
+    int32_t deadline_us;      /* arrival-to-results deadline (HARQ), e.g. 3000 */
+    int32_t max_batch_cb;     /* most code blocks per launch (0 = 8192) */
+    int32_t mode;             /* TDEC_SERVE_CONTINUOUS or TDEC_SERVE_PER_TB */
+    int32_t admission;        /* OR of TDEC_ADMIT_* (the budget check is always on) */
+    int64_t model_lat_ns;     /* service model prior: duration of a small launch */
+    int64_t model_ns_per_kbit;/* service model prior: ns per 1000 code block bits */
+    tdec_params params;       /* decoder parameters of every launch */
+} tdec_server_cfg;
+
+typedef struct {
+    uint64_t tag;        /* the caller's tag from submission */
+    int32_t tbs;         /* payload bits */
+    int32_t status;      /* TDEC_SERVE_* */
+    int32_t tb_ok;       /* CRC24A pass (DONE only) */
+    int32_t max_iters_used;
+    int32_t C;           /* code blocks */
+    int32_t batch_tbs;   /* TBs in the launch that decoded it */
+    int64_t t_arrive_ns; /* as given at submission (CLOCK_MONOTONIC, tdec_now_ns) */
+    int64_t t_done_ns;   /* bits and flags in host memory; t_arrive_ns for rejections */
+} tdec_server_result;
+
+typedef struct {
+    int64_t submitted, admitted, rej_budget, rej_deadline, rej_invalid;
+    int64_t completed, tb_fail, deadline_miss, batches;
+    int64_t payload_bits;      /* sum of tbs over completed TBs */
+    int64_t busy_ns;           /* sum of launch-to-results time over launches */
+    int64_t lat_p50_ns, lat_p99_ns, lat_p999_ns, lat_max_ns, lat_mean_ns; /* completed TBs */
+    int64_t model_lat_ns, model_ns_per_kbit;  /* the service model as learned so far */
+    int64_t slots_in_use_bytes, slots_peak_bytes;
+    double mean_batch_tbs, mean_batch_cbs;
+} tdec_serve_stats;
+
+typedef struct tdec_server tdec_server;
+
+/* CLOCK_MONOTONIC in nanoseconds: the time base of arrivals and completions. */
+int64_t tdec_now_ns(void);
+
+/* Create a server that decodes on `ctx` (the server allocates its slot arena
+ * and staging buffers on the context's device).  EINVAL for a bad config,
+ * ENOMEM when the arena cannot be allocated. */
+tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_server **out);
+
+/* The same server with the modelled executor (no device is touched). */
+tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
+                                     int64_t ns_per_kbit, tdec_server **out);
+
+/* Submit n transport blocks that arrived at t_arrive_ns (one TTI's batch).
+ * For block i: tags[i] is returned with its result, tbs[i] its payload size,
+ * h_llr[i] its tdec_tb_llr_count(tbs[i]) int16 LLRs (host memory, best
+ * pinned; read asynchronously), h_bits[i] where ceil(tbs/8) payload bytes are
+ * written (may be NULL).  Both buffers must stay valid until the block's
+ * result has been polled.  status[i] (may be NULL) receives TDEC_SERVE_DONE
+ * for admitted blocks or the rejection reason; rejected blocks also produce
+ * a result.  Returns the number admitted, or a negative tdec_status. */
+int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
+                           const int16_t *const *h_llr, uint8_t *const *h_bits,
+                           int64_t t_arrive_ns, int32_t *status);
+
+/* Move up to `max` finished results (completion order) into out; waits up
+ * to wait_us for the first one when none is ready.  Returns the count. */
+int32_t tdec_server_poll(tdec_server *s, tdec_server_result *out, int32_t max, int32_t wait_us);
+
+/* Wait until every admitted block has completed (or timeout_ms passed:
+ * then EBUSY). */
+tdec_status tdec_server_drain(tdec_server *s, int32_t timeout_ms);
+
+/* Counters and latency percentiles of completed blocks since creation (or
+ * the last reset). */
+tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out);
+void tdec_server_reset_stats(tdec_server *s);
+
+/* Drain, stop the worker and free the server's device memory. */
+void tdec_server_destroy(tdec_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

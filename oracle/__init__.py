@@ -91,6 +91,8 @@ def lib():
         L.or_cb_decode_batch.argtypes = [ct.c_int32, ct.c_void_p, ct.c_void_p, P(Params),
                                          ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.or_tb_decode.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p, P(TbResult)]
+        L.or_tb_decode_w.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p,
+                                     ct.c_void_p, P(TbResult)]
         _lib = L
     return _lib
 
@@ -243,10 +245,16 @@ def cb_decode_batch(descs, llr, p: Params, n_bits_bytes: int):
 
 
 def tb_decode(llr, tbs: int, p: Params):
+    return tb_decode_windows(llr, tbs, p, None)
+
+
+def tb_decode_windows(llr, tbs: int, p: Params, nw_per_cb):
+    """tb_decode with a window count per code block (None: p.n_windows)."""
     llr = np.ascontiguousarray(llr, np.int16)
     bits = np.zeros((tbs + 7) // 8, np.uint8)
     res = TbResult()
-    if lib().or_tb_decode(_ptr(llr), tbs, ct.byref(p), _ptr(bits), ct.byref(res)):
+    nw = None if nw_per_cb is None else np.ascontiguousarray(nw_per_cb, np.int32)
+    if lib().or_tb_decode_w(_ptr(llr), tbs, ct.byref(p), _ptr(nw), _ptr(bits), ct.byref(res)):
         raise ValueError("bad tb_decode arguments")
     return bits, {"tb_ok": res.tb_ok, "max_iters_used": res.max_iters_used, "C": res.C,
                   "cb_ok": list(res.cb_ok[:res.C]), "cb_iters": list(res.cb_iters[:res.C])}

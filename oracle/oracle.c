@@ -678,6 +678,12 @@ int or_cb_decode_batch(int32_t n_cb, const or_cb_desc *desc, const int16_t *llr,
 int or_tb_decode(const int16_t *llr, int32_t tbs, const or_params *p, uint8_t *bits,
                  or_tb_result *res)
 {
+    return or_tb_decode_w(llr, tbs, p, NULL, bits, res);
+}
+
+int or_tb_decode_w(const int16_t *llr, int32_t tbs, const or_params *p, const int32_t *nw,
+                   uint8_t *bits, or_tb_result *res)
+{
     or_seg sg;
     if (!llr || !res || or_segment(tbs, &sg) || sg.C > 64) return -1;
     uint8_t *b = malloc(sg.B);
@@ -690,7 +696,9 @@ int or_tb_decode(const int16_t *llr, int32_t tbs, const or_params *p, uint8_t *b
         const int32_t crc = sg.C > 1 ? OR_CRC24B : OR_CRC24A;
         uint8_t *hard = malloc(K);
         int32_t ok = 0, it = 0;
-        if (or_cb_decode_ex(llr + off, K, F, crc, p, hard, NULL, &ok, &it, 0, NULL)) {
+        or_params pr = *p;
+        if (nw) pr.n_windows = nw[r];
+        if (or_cb_decode_ex(llr + off, K, F, crc, &pr, hard, NULL, &ok, &it, 0, NULL)) {
             free(hard);
             free(b);
             return -1;

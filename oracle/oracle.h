@@ -155,6 +155,11 @@ typedef struct {
  * tb_ok is the CRC24A check of the reassembled block payloads. */
 int or_tb_decode(const int16_t *llr, int32_t tbs, const or_params *p, uint8_t *bits,
                  or_tb_result *res);
+/* The same with one window count per code block (nw[r] for block r; NULL =
+ * p->n_windows for every block), as a decoder that picks windows per size
+ * runs it. */
+int or_tb_decode_w(const int16_t *llr, int32_t tbs, const or_params *p, const int32_t *nw,
+                   uint8_t *bits, or_tb_result *res);
 
 #ifdef __cplusplus
 }

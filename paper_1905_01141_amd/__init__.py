@@ -21,7 +21,14 @@ CRC_NONE, CRC24A, CRC24B = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EDEVICE", -5: "EBUSY"}
 EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tdec_create",
            "tdec_destroy", "tdec_pick_windows", "cb_decode_batch", "tb_decode", "tb_decode_batch",
-           "cb_encode_batch", "tb_encode")
+           "cb_encode_batch", "tb_encode", "tdec_now_ns", "tdec_server_create",
+           "tdec_server_create_model", "tdec_server_submit", "tdec_server_poll",
+           "tdec_server_drain", "tdec_server_stats", "tdec_server_reset_stats",
+           "tdec_server_destroy", "tdec_graph_cb_decode", "tdec_graph_tb_decode",
+           "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset")
+SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
+ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
+SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
 
 
 class TdecError(RuntimeError):
@@ -43,6 +50,31 @@ class Seg(ct.Structure):
 class CbDesc(ct.Structure):
     _fields_ = [("llr_off", ct.c_int64), ("bits_off", ct.c_int64), ("K", ct.c_int32),
                 ("F", ct.c_int16), ("crc", ct.c_int8), ("rsv", ct.c_int8)]
+
+
+class ServerCfg(ct.Structure):
+    _fields_ = [("slot_budget_bytes", ct.c_size_t), ("deadline_us", ct.c_int32),
+                ("max_batch_cb", ct.c_int32), ("mode", ct.c_int32), ("admission", ct.c_int32),
+                ("model_lat_ns", ct.c_int64), ("model_ns_per_kbit", ct.c_int64),
+                ("params", Params)]
+
+
+class ServeResult(ct.Structure):
+    _fields_ = [("tag", ct.c_uint64), ("tbs", ct.c_int32), ("status", ct.c_int32),
+                ("tb_ok", ct.c_int32), ("max_iters_used", ct.c_int32), ("C", ct.c_int32),
+                ("batch_tbs", ct.c_int32), ("t_arrive_ns", ct.c_int64), ("t_done_ns", ct.c_int64)]
+
+
+class ServeStats(ct.Structure):
+    _fields_ = [(n, ct.c_int64) for n in (
+        "submitted", "admitted", "rej_budget", "rej_deadline", "rej_invalid", "completed",
+        "tb_fail", "deadline_miss", "batches", "payload_bits", "busy_ns", "lat_p50_ns",
+        "lat_p99_ns", "lat_p999_ns", "lat_max_ns", "lat_mean_ns", "model_lat_ns",
+        "model_ns_per_kbit", "slots_in_use_bytes", "slots_peak_bytes")] + [
+        ("mean_batch_tbs", ct.c_double), ("mean_batch_cbs", ct.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 # tdec_cb_desc as a numpy record (same layout) for vectorised checks
@@ -80,6 +112,26 @@ def lib():
         L.tb_decode_batch.argtypes = [vp, i32, vp, vp, vp, vp, P(Params), vp, vp, vp]
         L.cb_encode_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         L.tb_encode.argtypes = [vp, vp, i32, vp, vp]
+        L.tdec_graph_cb_decode.argtypes = [vp, i32, vp, vp, P(Params), vp, vp, vp, P(vp)]
+        L.tdec_graph_tb_decode.argtypes = [vp, i32, vp, vp, vp, vp, P(Params), vp, vp, P(vp)]
+        L.tdec_graph_launch.argtypes = [vp, vp]
+        L.tdec_graph_destroy.argtypes = [vp]
+        L.tdec_graph_destroy.restype = None
+        L.tdec_autotune.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
+        L.tdec_autotune_reset.argtypes = [vp]
+        L.tdec_autotune_reset.restype = None
+        L.tdec_now_ns.restype = i64
+        L.tdec_now_ns.argtypes = []
+        L.tdec_server_create.argtypes = [vp, P(ServerCfg), P(vp)]
+        L.tdec_server_create_model.argtypes = [P(ServerCfg), i64, i64, P(vp)]
+        L.tdec_server_submit.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
+        L.tdec_server_poll.argtypes = [vp, vp, i32, i32]
+        L.tdec_server_drain.argtypes = [vp, i32]
+        L.tdec_server_stats.argtypes = [vp, P(ServeStats)]
+        L.tdec_server_reset_stats.argtypes = [vp]
+        L.tdec_server_reset_stats.restype = None
+        L.tdec_server_destroy.argtypes = [vp]
+        L.tdec_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -249,6 +301,52 @@ class Decoder:
                                      _np_ptr(bits_off), _dptr(llr), ct.byref(p), _dptr(bits),
                                      _dptr(res), _stream(stream)))
 
+    def graph_cb_decode(self, descs, llr, p: Params, bits=None, crc_ok=None, iters=None):
+        """Plan and capture a code block batch; returns a Graph whose launch()
+        replays it (the tensors must outlive the Graph)."""
+        n_llr, n_bits = _desc_extent(descs)
+        _need(llr, "int16", n_llr, "llr")
+        if bits is not None:
+            _need(bits, "uint8", n_bits, "bits")
+        _need(crc_ok, "uint8", len(descs), "crc_ok")
+        _need(iters, "uint8", len(descs), "iters")
+        h = ct.c_void_p()
+        _check("tdec_graph_cb_decode",
+               lib().tdec_graph_cb_decode(self._h, len(descs), ct.cast(descs, ct.c_void_p),
+                                          _dptr(llr), ct.byref(p), _dptr(bits), _dptr(crc_ok),
+                                          _dptr(iters), ct.byref(h)))
+        return Graph(h, self, (llr, bits, crc_ok, iters))
+
+    def graph_tb_decode(self, tbs, llr_off, bits_off, llr, p: Params, bits, res):
+        tbs = np.ascontiguousarray(tbs, np.int32)
+        llr_off = np.ascontiguousarray(llr_off, np.int64)
+        bits_off = None if bits_off is None else np.ascontiguousarray(bits_off, np.int64)
+        counts = np.array([tb_llr_count(int(t)) for t in tbs], np.int64)
+        _need(llr, "int16", int((llr_off + counts).max()), "llr")
+        if bits is not None:
+            _need(bits, "uint8", int((bits_off + (tbs.astype(np.int64) + 7) // 8).max()), "bits")
+        _need(res, "uint8", tbs.size * TB_RESULT_BYTES, "res")
+        h = ct.c_void_p()
+        _check("tdec_graph_tb_decode",
+               lib().tdec_graph_tb_decode(self._h, tbs.size, _np_ptr(tbs), _np_ptr(llr_off),
+                                          _np_ptr(bits_off), _dptr(llr), ct.byref(p),
+                                          _dptr(bits), _dptr(res), ct.byref(h)))
+        return Graph(h, self, (llr, bits, res))
+
+    def autotune(self, Ks, min_W=64, max_iters=6, batch_bits=25_000_000, stream=None):
+        """Measure and set the window count of each size in Ks; returns
+        {K: (n_windows, ns per 1000 code block bits)}."""
+        Ks = np.ascontiguousarray(Ks, np.int32)
+        nw = np.zeros(Ks.size, np.int32)
+        ns = np.zeros(Ks.size, np.float32)
+        _check("tdec_autotune",
+               lib().tdec_autotune(self._h, Ks.size, _np_ptr(Ks), int(min_W), int(max_iters),
+                                   int(batch_bits), _np_ptr(nw), _np_ptr(ns), _stream(stream)))
+        return {int(k): (int(a), float(b)) for k, a, b in zip(Ks, nw, ns)}
+
+    def autotune_reset(self):
+        lib().tdec_autotune_reset(self._h)
+
     def cb_encode_batch(self, descs, payload, coded, stream=None):
         n_llr, n_bits = _desc_extent(descs)
         _need(payload, "uint8", n_bits, "payload")
@@ -264,6 +362,27 @@ class Decoder:
                                             _stream(stream)))
 
 
+class Graph:
+    """A captured decode (tdec_graph); launch() enqueues one replay."""
+
+    def __init__(self, h, decoder, keep):
+        self._h, self._decoder, self._keep = h, decoder, keep
+
+    def launch(self, stream=None):
+        _check("tdec_graph_launch", lib().tdec_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tdec_graph_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def parse_tb_results(raw: np.ndarray) -> list[dict]:
     """Decode the bytes of tdec_tb_result entries copied back to the host."""
     arr = np.frombuffer(np.ascontiguousarray(raw).tobytes(), dtype=TB_RESULT_DTYPE)
@@ -274,3 +393,95 @@ def parse_tb_results(raw: np.ndarray) -> list[dict]:
                     "C": C, "cb_ok": [int(x) for x in r["cb_ok"][:C]],
                     "cb_iters": [int(x) for x in r["cb_iters"][:C]]})
     return out
+
+
+# ----------------------------------------------------------------------------- serving loop
+def now_ns() -> int:
+    """CLOCK_MONOTONIC in ns, the serving loop's time base."""
+    return int(lib().tdec_now_ns())
+
+
+def server_cfg(params: Params, deadline_us=3000, slot_budget_bytes=0, max_batch_cb=0,
+               mode=SERVE_CONTINUOUS, admission=ADMIT_BUDGET, model_lat_ns=0,
+               model_ns_per_kbit=0) -> ServerCfg:
+    return ServerCfg(slot_budget_bytes, deadline_us, max_batch_cb, mode, admission,
+                     model_lat_ns, model_ns_per_kbit, params)
+
+
+class Server:
+    """The native serving loop (include/tdec_server.h).  Create with a
+    Decoder (GPU executor) or with Server.model(...) (modelled executor, no
+    device)."""
+
+    def __init__(self, decoder: "Decoder | None", cfg: ServerCfg, _model=None):
+        h = ct.c_void_p()
+        if _model is None:
+            _check("tdec_server_create",
+                   lib().tdec_server_create(decoder._h, ct.byref(cfg), ct.byref(h)))
+        else:
+            _check("tdec_server_create_model",
+                   lib().tdec_server_create_model(ct.byref(cfg), int(_model[0]),
+                                                  int(_model[1]), ct.byref(h)))
+        self._h = h
+        self._decoder = decoder  # keeps the context alive
+        self._keep = {}          # tag -> buffers that must outlive the request
+
+    @classmethod
+    def model(cls, cfg: ServerCfg, lat_ns: int, ns_per_kbit: int) -> "Server":
+        return cls(None, cfg, _model=(lat_ns, ns_per_kbit))
+
+    def submit(self, tags, tbs, llr_ptrs, bits_ptrs=None, t_arrive_ns=None, keep=None):
+        """Submit one arrival batch.  llr_ptrs / bits_ptrs: host addresses
+        (ints) of each block's int16 LLRs and payload buffer; `keep` (a list
+        per block, optional) holds objects that must stay alive until the
+        result is polled.  Returns (admitted count, status array)."""
+        tags = np.ascontiguousarray(tags, np.uint64)
+        tbs = np.ascontiguousarray(tbs, np.int32)
+        n = tags.size
+        if tbs.size != n or len(llr_ptrs) != n:
+            raise ValueError("tags, tbs and llr_ptrs differ in length")
+        lp = np.ascontiguousarray(llr_ptrs, np.uint64)
+        bp = None if bits_ptrs is None else np.ascontiguousarray(bits_ptrs, np.uint64)
+        st = np.zeros(n, np.int32)
+        t = now_ns() if t_arrive_ns is None else int(t_arrive_ns)
+        if keep is not None:
+            for i in range(n):
+                self._keep[int(tags[i])] = keep[i]
+        k = lib().tdec_server_submit(self._h, n, _np_ptr(tags), _np_ptr(tbs), _np_ptr(lp),
+                                     _np_ptr(bp), t, _np_ptr(st))
+        if k < 0:
+            raise TdecError("tdec_server_submit", k)
+        return k, st
+
+    def poll(self, max_n=4096, wait_us=0) -> list[dict]:
+        buf = (ServeResult * max_n)()
+        k = lib().tdec_server_poll(self._h, ct.cast(buf, ct.c_void_p), max_n, int(wait_us))
+        out = []
+        for r in buf[:k]:
+            d = {n: getattr(r, n) for n, _ in ServeResult._fields_}
+            self._keep.pop(int(r.tag), None)
+            out.append(d)
+        return out
+
+    def drain(self, timeout_ms=60000):
+        _check("tdec_server_drain", lib().tdec_server_drain(self._h, int(timeout_ms)))
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        _check("tdec_server_stats", lib().tdec_server_stats(self._h, ct.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        lib().tdec_server_reset_stats(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tdec_server_destroy(self._h)
+            self._h = ct.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

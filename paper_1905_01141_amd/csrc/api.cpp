@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,7 @@ namespace {
 constexpr int kPlanSlots = 8;
 constexpr size_t kPlanSlotBytes = 8u << 20;
 constexpr int kLdsPerCu = 160 * 1024;
+constexpr size_t kQtabEntries = 4u << 20;  // QPP table arena (8 MiB): every size at ~11 window counts
 
 struct PlanSlot {
     std::string key;
@@ -36,7 +38,7 @@ struct PlanSlot {
     int n_items = 0, grid = 0, wg = 0, lds = 0;
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
-    size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0, off_qtab = 0;
+    size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
 }  // namespace
@@ -55,8 +57,17 @@ struct tdec_ctx {
     uint8_t *d_encbuf = nullptr;
     size_t encbuf_bytes = 0;
     uint32_t *d_counter = nullptr;  // work distribution counter of the decode kernel
+    // QPP LDS-address tables, one per (K, windows) shape, appended on first
+    // use and kept for the context's lifetime; the pinned mirror is never
+    // rewritten, so its asynchronous uploads need no synchronisation
+    uint16_t *d_qtab = nullptr;
+    uint16_t *h_qtab = nullptr;
+    size_t qtab_cap = 0, qtab_used = 0;
+    std::map<int64_t, int64_t> qtab_off;
     PlanSlot slots[kPlanSlots];
     uint64_t clock = 0;
+    int32_t tuned_nw[kNumK] = {};  // autotuned window count per size (0 = default rule)
+    uint32_t tune_gen = 0;         // bumped whenever tuned_nw changes (enters plan keys)
     int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
 };
@@ -80,6 +91,13 @@ int32_t pick_windows(int32_t K)
     return best;
 }
 
+int32_t ctx_windows(const tdec_ctx *ctx, int32_t K)
+{
+    const int i = k_index(K);
+    if (ctx && i >= 0 && ctx->tuned_nw[i] > 0) return ctx->tuned_nw[i];
+    return pick_windows(K);
+}
+
 bool windows_ok(int32_t K, int32_t nw)
 {
     return nw >= 1 && nw <= kMaxWgThreads / 2 && K % nw == 0 && (K / nw) % kSeg == 0;
@@ -90,9 +108,42 @@ struct CbReq {
     DecCb cb;
 };
 
+// Fill the QPP address table of shape (K, nw) into dst: unit u = t4 * nw + w
+// holds the LDS byte offsets 2 * epad(pi(k)) of steps k = w * W + 4 * t4 + j.
+void qtab_fill(int32_t K, int32_t nw, uint16_t *dst)
+{
+    const int32_t W = K / nw;
+    std::vector<int32_t> pi(K);
+    tdec_qpp(K, pi.data(), nullptr, nullptr);
+    for (int u = 0; u < K / 4; ++u) {
+        const int t4 = u / nw, w = u % nw;
+        for (int j = 0; j < 4; ++j) dst[4 * u + j] = (uint16_t)(2 * epad(pi[w * W + 4 * t4 + j]));
+    }
+}
+
+// Element offset of the (K, nw) table in the context's table arena, adding
+// it (upload enqueued on `st`) on first use; -1 when the arena is full.
+int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
+{
+    const int64_t key = (int64_t)K * 1024 + nw;
+    auto f = ctx->qtab_off.find(key);
+    if (f != ctx->qtab_off.end()) return f->second;
+    const size_t n = ((size_t)K + 7) & ~(size_t)7;
+    if (ctx->qtab_used + n > ctx->qtab_cap) return -1;
+    const int64_t off = (int64_t)ctx->qtab_used;
+    qtab_fill(K, nw, ctx->h_qtab + off);
+    if (hipMemcpyAsync(ctx->d_qtab + off, ctx->h_qtab + off, (size_t)K * 2, hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return -1;
+    ctx->qtab_used += n;
+    ctx->qtab_off[key] = off;
+    return off;
+}
+
 // Build the decode plan (items + code block list) from a request.
 tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot &ps,
-                              std::vector<char> &blob, const std::vector<TbItem> *tbs)
+                              std::vector<char> &blob, const std::vector<TbItem> *tbs,
+                              hipStream_t st)
 {
     // group by (K, nw), biggest blocks first
     std::vector<int> order(reqs.size());
@@ -110,9 +161,6 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     if (wg > kMaxWgThreads) return TDEC_EINVAL;
     std::vector<DecItem> items;
     std::vector<DecCb> cbl;
-    // QPP address tables, one per (K, nw) shape
-    std::vector<uint16_t> qtab;
-    std::vector<std::pair<int64_t, int32_t>> shapes;  // (K * 1024 + nw, offset)
     cbl.reserve(reqs.size());
     int lds = 0;
     int64_t stride = 0;
@@ -135,24 +183,9 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         it.f2 = f2;
         it.lds_slot = sb;
         {
-            const int64_t key = (int64_t)K * 1024 + nw;
-            int32_t off = -1;
-            for (auto &sh : shapes)
-                if (sh.first == key) off = sh.second;
-            if (off < 0) {
-                off = (int32_t)qtab.size();
-                shapes.push_back({key, off});
-                qtab.resize(qtab.size() + K);
-                // unit u = t4 * nw + w holds steps k = w * W + 4 * t4 + j
-                std::vector<int32_t> pi(K);
-                tdec_qpp(K, pi.data(), nullptr, nullptr);
-                for (int u = 0; u < K / 4; ++u) {
-                    const int t4 = u / nw, w = u % nw;
-                    for (int j = 0; j < 4; ++j)
-                        qtab[off + 4 * u + j] = (uint16_t)(2 * epad(pi[w * W + 4 * t4 + j]));
-                }
-            }
-            it.qtab = off;
+            const int64_t off = qtab_get(ctx, K, nw, st);
+            if (off < 0) return TDEC_ENOMEM;
+            it.qtab = (int32_t)off;
         }
         int n = 0;
         while (i < order.size() && n < cap && reqs[order[i]].K == K && reqs[order[i]].nw == nw) {
@@ -181,19 +214,17 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     grid = (int)std::min<int64_t>(grid, fit);
     grid = std::max(grid, 1);
 
-    // serialise: [items][cbs][tbs][qpp tables]
+    // serialise: [items][cbs][tbs]
     ps.off_items = 0;
     ps.off_cbs = (items.size() * sizeof(DecItem) + 255) & ~(size_t)255;
     ps.off_tbs = ps.off_cbs + ((cbl.size() * sizeof(DecCb) + 255) & ~(size_t)255);
     const size_t ntb = tbs ? tbs->size() : 0;
-    ps.off_qtab = ps.off_tbs + ((ntb * sizeof(TbItem) + 255) & ~(size_t)255);
-    const size_t total = ps.off_qtab + qtab.size() * sizeof(uint16_t);
+    const size_t total = ps.off_tbs + ntb * sizeof(TbItem);
     if (total > kPlanSlotBytes) return TDEC_ENOMEM;
     blob.assign(total, 0);
     memcpy(blob.data() + ps.off_items, items.data(), items.size() * sizeof(DecItem));
     memcpy(blob.data() + ps.off_cbs, cbl.data(), cbl.size() * sizeof(DecCb));
     if (ntb) memcpy(blob.data() + ps.off_tbs, tbs->data(), ntb * sizeof(TbItem));
-    memcpy(blob.data() + ps.off_qtab, qtab.data(), qtab.size() * sizeof(uint16_t));
     ps.n_items = (int)items.size();
     ps.n_cb = (int)cbl.size();
     ps.n_tb = (int)ntb;
@@ -251,11 +282,195 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.scratch = ctx->d_scratch;
     a.scratch_stride = ps->stride;
     a.counter = ctx->d_counter;
-    a.qtab = (const uint16_t *)(ps->d_buf + ps->off_qtab);
+    a.qtab = ctx->d_qtab;
     a.max_iters = p->max_iters;
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
     if (launch_decode(a, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+// Plan cache keys: everything the plan depends on (the tuned window table
+// enters through its generation counter).
+std::string cb_key(int32_t n_cb, const tdec_cb_desc *desc, const tdec_params *p, bool bits,
+                   uint32_t gen)
+{
+    std::string key(1, 'C');
+    key.append((const char *)&p->n_windows, sizeof(int32_t));
+    key.append((const char *)&gen, sizeof gen);
+    key.push_back(bits ? 1 : 0);
+    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
+    return key;
+}
+
+std::string tb_key(int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
+                   const int64_t *bits_off, const tdec_params *p, uint32_t gen)
+{
+    std::string key(1, 'T');
+    key.append((const char *)&p->n_windows, sizeof(int32_t));
+    key.append((const char *)&gen, sizeof gen);
+    key.push_back(bits_off ? 1 : 0);
+    key.append((const char *)tbs, sizeof(int32_t) * (size_t)n_tb);
+    key.append((const char *)llr_off, sizeof(int64_t) * (size_t)n_tb);
+    if (bits_off) key.append((const char *)bits_off, sizeof(int64_t) * (size_t)n_tb);
+    return key;
+}
+
+// Validate code block descriptors and turn them into plan requests.
+tdec_status make_cb_reqs(const tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                         const tdec_params *params, bool bits, std::vector<CbReq> &reqs)
+{
+    reqs.resize((size_t)n_cb);
+    for (int32_t i = 0; i < n_cb; ++i) {
+        const tdec_cb_desc &d = desc[i];
+        if (k_index(d.K) < 0 || d.F < 0 || d.F >= d.K || d.crc < 0 || d.crc > 2 || d.llr_off < 0)
+            return TDEC_EINVAL;
+        if (d.crc && d.K - d.F < 24) return TDEC_EINVAL;
+        if (bits && d.bits_off < 0) return TDEC_EINVAL;
+        const int32_t nw = params->n_windows ? params->n_windows : ctx_windows(ctx, d.K);
+        if (!windows_ok(d.K, nw)) return TDEC_EINVAL;
+        CbReq &r = reqs[i];
+        r.K = d.K;
+        r.nw = nw;
+        r.cb.llr_off = d.llr_off;
+        r.cb.bits_off = bits ? d.bits_off : -1;
+        r.cb.hard_off = -1;
+        r.cb.out_idx = i;
+        r.cb.F = d.F;
+        r.cb.crc = d.crc;
+        r.cb.rsv = 0;
+    }
+    return TDEC_OK;
+}
+
+// Segment transport blocks into plan requests plus the assembly list.
+tdec_status make_tb_reqs(const tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                         const int64_t *llr_off, const int64_t *bits_off,
+                         const tdec_params *params, std::vector<CbReq> &reqs,
+                         std::vector<TbItem> &tbl)
+{
+    tbl.assign((size_t)n_tb, TbItem{});
+    reqs.clear();
+    int64_t hard = 0;
+    int32_t cbi = 0;
+    for (int32_t t = 0; t < n_tb; ++t) {
+        int32_t s[8];
+        if (segment(tbs[t], s)) return TDEC_ERANGE;
+        if (s[1] > 64) return TDEC_ERANGE;
+        if (llr_off[t] < 0 || (bits_off && bits_off[t] < 0)) return TDEC_EINVAL;
+        TbItem &ti = tbl[t];
+        ti.tbs = tbs[t];
+        ti.B = s[0];
+        ti.C = s[1];
+        ti.L = s[2];
+        ti.Kplus = s[3];
+        ti.Kminus = s[4];
+        ti.Cminus = s[6];
+        ti.F = s[7];
+        ti.hard_off = hard;
+        ti.bits_off = bits_off ? bits_off[t] : -1;
+        ti.cb_idx0 = cbi;
+        ti.res_idx = t;
+        int64_t off = llr_off[t];
+        for (int r = 0; r < s[1]; ++r) {
+            const int32_t K = r < s[6] ? s[4] : s[3];
+            const int32_t nw = params->n_windows ? params->n_windows : ctx_windows(ctx, K);
+            if (!windows_ok(K, nw)) return TDEC_EINVAL;
+            CbReq q;
+            q.K = K;
+            q.nw = nw;
+            q.cb.llr_off = off;
+            q.cb.bits_off = -1;
+            q.cb.hard_off = hard;
+            q.cb.out_idx = cbi;
+            q.cb.F = (int16_t)(r == 0 ? s[7] : 0);
+            q.cb.crc = (int8_t)(s[1] > 1 ? TDEC_CRC24B : TDEC_CRC24A);
+            q.cb.rsv = 0;
+            reqs.push_back(q);
+            off += 3 * (int64_t)(K + 4);
+            hard += hard_words(K);
+            ++cbi;
+        }
+    }
+    if ((size_t)hard > ctx->hard_words_cap || (size_t)cbi > ctx->flags_cap) return TDEC_ENOMEM;
+    return TDEC_OK;
+}
+
+// Decode + assemble launches of a transport block plan whose device copy is at d_plan.
+tdec_status launch_tb_plan(tdec_ctx *ctx, PlanSlot *ps, char *d_plan, const int16_t *d_llr,
+                           const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
+                           hipStream_t st)
+{
+    PlanSlot v = *ps;
+    v.d_buf = d_plan;
+    tdec_status s = launch_plan(ctx, &v, d_llr, params, nullptr, ctx->d_ok, ctx->d_it, true, st);
+    if (s != TDEC_OK) return s;
+    if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ctx->d_hard,
+                           ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
+        return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+}  // namespace
+
+struct tdec_graph {
+    tdec_ctx *ctx = nullptr;
+    char *d_plan = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+};
+
+namespace {
+
+void graph_free(tdec_graph *g)
+{
+    if (!g) return;
+    if (g->ge) (void)hipGraphExecDestroy(g->ge);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    if (g->d_plan) (void)hipFree(g->d_plan);
+    delete g;
+}
+
+// Build a plan into a private device copy, then capture `body` on a private
+// stream into an instantiated graph.
+template <class F>
+tdec_status graph_capture(tdec_ctx *ctx, std::vector<CbReq> &reqs,
+                                 const std::vector<TbItem> *tbl, F body, tdec_graph **out)
+{
+    PlanSlot ps;
+    std::vector<char> blob;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TDEC_EDEVICE;
+    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs);
+    tdec_graph *g = nullptr;
+    if (s == TDEC_OK) {
+        g = new tdec_graph();
+        g->ctx = ctx;
+        if (hipMalloc(&g->d_plan, blob.size()) != hipSuccess ||
+            hipMemcpyAsync(g->d_plan, blob.data(), blob.size(), hipMemcpyHostToDevice, cs) !=
+                hipSuccess ||
+            hipStreamSynchronize(cs) != hipSuccess)
+            s = TDEC_ENOMEM;
+    }
+    if (s == TDEC_OK) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            s = TDEC_EDEVICE;
+        } else {
+            s = body(ps, g->d_plan, cs);
+            hipGraph_t gr = nullptr;
+            const bool ended = hipStreamEndCapture(cs, &gr) == hipSuccess;
+            g->g = gr;
+            if (s == TDEC_OK && (!ended || !gr ||
+                                 hipGraphInstantiate(&g->ge, gr, nullptr, nullptr, 0) != hipSuccess))
+                s = TDEC_EDEVICE;
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (s != TDEC_OK) {
+        graph_free(g);
+        return s;
+    }
+    *out = g;
     return TDEC_OK;
 }
 
@@ -333,7 +548,9 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
     c->flags_cap = 1 << 20;
     c->encbuf_bytes = 1 << 20;
     const size_t plan_bytes = (size_t)kPlanSlots * kPlanSlotBytes;
-    const size_t fixed = tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes;
+    c->qtab_cap = kQtabEntries;
+    const size_t fixed =
+        tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes + c->qtab_cap * 2;
     if (c->budget < fixed + (16u << 20)) {
         delete c;
         return TDEC_ENOMEM;
@@ -348,7 +565,9 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
               hipMalloc(&c->d_it, c->flags_cap) == hipSuccess &&
               hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess &&
               hipMalloc(&c->d_counter, 64) == hipSuccess &&
-              hipMemset(c->d_counter, 0, 64) == hipSuccess;
+              hipMemset(c->d_counter, 0, 64) == hipSuccess &&
+              hipMalloc(&c->d_qtab, c->qtab_cap * 2) == hipSuccess &&
+              hipHostMalloc(&c->h_qtab, c->qtab_cap * 2, hipHostMallocDefault) == hipSuccess;
     for (auto &s : c->slots) {
         ok = ok && hipMalloc(&s.d_buf, kPlanSlotBytes) == hipSuccess &&
              hipHostMalloc(&s.h_buf, kPlanSlotBytes, hipHostMallocDefault) == hipSuccess &&
@@ -359,6 +578,17 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
         crc_shift_table(kPoly24A, tab.data(), kCrcTabN);
         crc_shift_table(kPoly24B, tab.data() + kCrcTabN, kCrcTabN);
         ok = hipMemcpy(c->d_crc_tab, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok) {
+        // the tables of every size at its default window count
+        for (int i = 0; i < kNumK; ++i) {
+            const int32_t K = k_of_index(i), nw = pick_windows(K);
+            const int64_t off = (int64_t)c->qtab_used;
+            qtab_fill(K, nw, c->h_qtab + off);
+            c->qtab_off[(int64_t)K * 1024 + nw] = off;
+            c->qtab_used += ((size_t)K + 7) & ~(size_t)7;
+        }
+        ok = hipMemcpy(c->d_qtab, c->h_qtab, c->qtab_used * 2, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
         tdec_destroy(c);
@@ -380,6 +610,8 @@ void tdec_destroy(tdec_ctx *c)
     (void)hipFree(c->d_it);
     (void)hipFree(c->d_encbuf);
     (void)hipFree(c->d_counter);
+    if (c->d_qtab) (void)hipFree(c->d_qtab);
+    if (c->h_qtab) (void)hipHostFree(c->h_qtab);
     for (auto &s : c->slots) {
         if (s.d_buf) (void)hipFree(s.d_buf);
         if (s.h_buf) (void)hipHostFree(s.h_buf);
@@ -392,7 +624,7 @@ int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K)
 {
     (void)ctx;
     if (k_index(K) < 0) return 0;
-    return pick_windows(K);
+    return ctx_windows(ctx, K);
 }
 
 tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
@@ -405,45 +637,19 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
     // a batch identical to a cached one reuses its (validated) plan
-    std::string key(1, 'C');
-    key.append((const char *)&params->n_windows, sizeof(int32_t));
-    key.push_back(d_bits ? 1 : 0);
-    key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
+    const std::string key = cb_key(n_cb, desc, params, d_bits != nullptr, ctx->tune_gen);
     bool hit;
     PlanSlot *ps = lookup(ctx, key, &hit);
     if (hit) return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st);
-    std::vector<CbReq> reqs((size_t)n_cb);
-    for (int32_t i = 0; i < n_cb; ++i) {
-        const tdec_cb_desc &d = desc[i];
-        if (k_index(d.K) < 0 || d.F < 0 || d.F >= d.K || d.crc < 0 || d.crc > 2 || d.llr_off < 0)
-            return TDEC_EINVAL;
-        if (d.crc && d.K - d.F < 24) return TDEC_EINVAL;
-        if (d_bits && d.bits_off < 0) return TDEC_EINVAL;
-        const int32_t nw = params->n_windows ? params->n_windows : pick_windows(d.K);
-        if (!windows_ok(d.K, nw)) return TDEC_EINVAL;
-        CbReq &r = reqs[i];
-        r.K = d.K;
-        r.nw = nw;
-        r.cb.llr_off = d.llr_off;
-        r.cb.bits_off = d_bits ? d.bits_off : -1;
-        r.cb.hard_off = -1;
-        r.cb.out_idx = i;
-        r.cb.F = d.F;
-        r.cb.crc = d.crc;
-        r.cb.rsv = 0;
-    }
-    {
-        std::vector<char> blob;
-        tdec_status s = build_decode_plan(ctx, reqs, *ps, blob, nullptr);
-        if (s != TDEC_OK) {
-            ps->key.clear();
-            return s;
-        }
-        s = upload(ctx, ps, key, blob, st);
-        if (s != TDEC_OK) {
-            ps->key.clear();
-            return s;
-        }
+    std::vector<CbReq> reqs;
+    tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
+    if (s != TDEC_OK) return s;
+    std::vector<char> blob;
+    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st);
+    if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
+    if (s != TDEC_OK) {
+        ps->key.clear();
+        return s;
     }
     return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st);
 }
@@ -457,79 +663,27 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
     if (n_tb == 0) return TDEC_OK;
     if (!tbs || !llr_off || !d_llr || !d_res) return TDEC_EINVAL;
     if (d_bits && !bits_off) return TDEC_EINVAL;
-    std::vector<CbReq> reqs;
-    std::vector<TbItem> tbl((size_t)n_tb);
-    int64_t hard = 0;
-    int32_t cbi = 0;
-    for (int32_t t = 0; t < n_tb; ++t) {
-        int32_t s[8];
-        if (segment(tbs[t], s)) return TDEC_ERANGE;
-        if (s[1] > 64) return TDEC_ERANGE;
-        if (llr_off[t] < 0 || (d_bits && bits_off[t] < 0)) return TDEC_EINVAL;
-        TbItem &ti = tbl[t];
-        ti.tbs = tbs[t];
-        ti.B = s[0];
-        ti.C = s[1];
-        ti.L = s[2];
-        ti.Kplus = s[3];
-        ti.Kminus = s[4];
-        ti.Cminus = s[6];
-        ti.F = s[7];
-        ti.hard_off = hard;
-        ti.bits_off = d_bits ? bits_off[t] : -1;
-        ti.cb_idx0 = cbi;
-        ti.res_idx = t;
-        int64_t off = llr_off[t];
-        for (int r = 0; r < s[1]; ++r) {
-            const int32_t K = r < s[6] ? s[4] : s[3];
-            const int32_t nw = params->n_windows ? params->n_windows : pick_windows(K);
-            if (!windows_ok(K, nw)) return TDEC_EINVAL;
-            CbReq q;
-            q.K = K;
-            q.nw = nw;
-            q.cb.llr_off = off;
-            q.cb.bits_off = -1;
-            q.cb.hard_off = hard;
-            q.cb.out_idx = cbi;
-            q.cb.F = (int16_t)(r == 0 ? s[7] : 0);
-            q.cb.crc = (int8_t)(s[1] > 1 ? TDEC_CRC24B : TDEC_CRC24A);
-            q.cb.rsv = 0;
-            reqs.push_back(q);
-            off += 3 * (int64_t)(K + 4);
-            hard += hard_words(K);
-            ++cbi;
-        }
-    }
-    if ((size_t)hard > ctx->hard_words_cap || (size_t)cbi > ctx->flags_cap) return TDEC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
-    std::string key(1, 'T');
-    key.append((const char *)&params->n_windows, sizeof(int32_t));
-    key.push_back(d_bits ? 1 : 0);
-    key.append((const char *)tbs, sizeof(int32_t) * (size_t)n_tb);
-    key.append((const char *)llr_off, sizeof(int64_t) * (size_t)n_tb);
-    if (d_bits) key.append((const char *)bits_off, sizeof(int64_t) * (size_t)n_tb);
+    const std::string key =
+        tb_key(n_tb, tbs, llr_off, d_bits ? bits_off : nullptr, params, ctx->tune_gen);
     bool hit;
     PlanSlot *ps = lookup(ctx, key, &hit);
     if (!hit) {
+        std::vector<CbReq> reqs;
+        std::vector<TbItem> tbl;
+        tdec_status s = make_tb_reqs(ctx, n_tb, tbs, llr_off, d_bits ? bits_off : nullptr, params,
+                                     reqs, tbl);
+        if (s != TDEC_OK) return s;
         std::vector<char> blob;
-        tdec_status s = build_decode_plan(ctx, reqs, *ps, blob, &tbl);
-        if (s != TDEC_OK) {
-            ps->key.clear();
-            return s;
-        }
-        s = upload(ctx, ps, key, blob, st);
+        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st);
+        if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
         if (s != TDEC_OK) {
             ps->key.clear();
             return s;
         }
     }
-    tdec_status s = launch_plan(ctx, ps, d_llr, params, nullptr, ctx->d_ok, ctx->d_it, true, st);
-    if (s != TDEC_OK) return s;
-    if (launch_tb_assemble((const TbItem *)(ps->d_buf + ps->off_tbs), ps->n_tb, ctx->d_hard,
-                           ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
-        return TDEC_EDEVICE;
-    return TDEC_OK;
+    return launch_tb_plan(ctx, ps, ps->d_buf, d_llr, params, d_bits, d_res, st);
 }
 
 tdec_status tb_decode(tdec_ctx *ctx, const int16_t *d_llr, int32_t tbs, const tdec_params *params,
@@ -537,6 +691,160 @@ tdec_status tb_decode(tdec_ctx *ctx, const int16_t *d_llr, int32_t tbs, const td
 {
     const int64_t lo = 0, bo = 0;
     return tb_decode_batch(ctx, 1, &tbs, &lo, &bo, d_llr, params, d_bits, d_res, stream);
+}
+
+
+// ---------------------------------------------------------------- graphs
+
+tdec_status tdec_graph_cb_decode(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                                 const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                                 uint8_t *d_crc_ok, uint8_t *d_iters, tdec_graph **out)
+{
+    if (!out) return TDEC_EINVAL;
+    *out = nullptr;
+    if (!ctx || n_cb <= 0 || !params_ok(params) || !desc || !d_llr || !d_crc_ok || !d_iters)
+        return TDEC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::vector<CbReq> reqs;
+    tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
+    if (s != TDEC_OK) return s;
+    const tdec_params p = *params;
+    return graph_capture(ctx, reqs, nullptr,
+                         [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
+                             PlanSlot v = ps;
+                             v.d_buf = d_plan;
+                             return launch_plan(ctx, &v, d_llr, &p, d_bits, d_crc_ok, d_iters,
+                                                false, cs);
+                         },
+                         out);
+}
+
+tdec_status tdec_graph_tb_decode(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                 const int64_t *llr_off, const int64_t *bits_off,
+                                 const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                                 tdec_tb_result *d_res, tdec_graph **out)
+{
+    if (!out) return TDEC_EINVAL;
+    *out = nullptr;
+    if (!ctx || n_tb <= 0 || !params_ok(params) || !tbs || !llr_off || !d_llr || !d_res)
+        return TDEC_EINVAL;
+    if (d_bits && !bits_off) return TDEC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    std::vector<CbReq> reqs;
+    std::vector<TbItem> tbl;
+    tdec_status s =
+        make_tb_reqs(ctx, n_tb, tbs, llr_off, d_bits ? bits_off : nullptr, params, reqs, tbl);
+    if (s != TDEC_OK) return s;
+    const tdec_params p = *params;
+    return graph_capture(ctx, reqs, &tbl,
+                         [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
+                             return launch_tb_plan(ctx, &ps, d_plan, d_llr, &p, d_bits, d_res, cs);
+                         },
+                         out);
+}
+
+tdec_status tdec_graph_launch(tdec_graph *g, void *stream)
+{
+    if (!g || !g->ge) return TDEC_EINVAL;
+    if (hipSetDevice(g->ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    return hipGraphLaunch(g->ge, (hipStream_t)stream) == hipSuccess ? TDEC_OK : TDEC_EDEVICE;
+}
+
+void tdec_graph_destroy(tdec_graph *g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    graph_free(g);
+}
+
+// ---------------------------------------------------------------- autotuner
+
+tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t min_W,
+                          int32_t max_iters, int64_t batch_bits, int32_t *out_nw,
+                          float *out_ns_per_kbit, void *stream)
+{
+    if (!ctx || n_k < 0 || (n_k && !Ks) || min_W < 8 || max_iters < 1 || max_iters > 16 ||
+        batch_bits < 0)
+        return TDEC_EINVAL;
+    for (int32_t i = 0; i < n_k; ++i)
+        if (k_index(Ks[i]) < 0) return TDEC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t max_cb = std::min<int64_t>((int64_t)ctx->flags_cap, 16384);
+    int64_t max_llr = 0;
+    for (int32_t i = 0; i < n_k; ++i) {
+        const int64_t n = std::min<int64_t>(max_cb, std::max<int64_t>(1, batch_bits / Ks[i]));
+        max_llr = std::max<int64_t>(max_llr, n * 3 * (Ks[i] + 4));
+    }
+    int16_t *d_llr = nullptr;
+    uint8_t *d_ok = nullptr, *d_it = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tdec_status rs = TDEC_OK;
+    if (hipMalloc(&d_llr, (size_t)std::max<int64_t>(max_llr, 1) * 2) != hipSuccess ||
+        hipMalloc(&d_ok, (size_t)max_cb) != hipSuccess ||
+        hipMalloc(&d_it, (size_t)max_cb) != hipSuccess ||
+        hipMemsetAsync(d_llr, 0, (size_t)std::max<int64_t>(max_llr, 1) * 2, st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rs = TDEC_ENOMEM;
+    for (int32_t i = 0; i < n_k && rs == TDEC_OK; ++i) {
+        const int32_t K = Ks[i];
+        const int64_t n = std::min<int64_t>(max_cb, std::max<int64_t>(1, batch_bits / K));
+        std::vector<tdec_cb_desc> desc((size_t)n);
+        for (int64_t c = 0; c < n; ++c) {
+            desc[c].llr_off = c * 3 * (K + 4);
+            desc[c].bits_off = 0;
+            desc[c].K = K;
+            desc[c].F = 0;
+            desc[c].crc = TDEC_CRC_NONE;
+            desc[c].rsv = 0;
+        }
+        int32_t best_nw = pick_windows(K);
+        float best = -1.f;
+        for (int32_t nw = 1; nw <= kMaxWgThreads / 2 && rs == TDEC_OK; ++nw) {
+            if (K % nw || (K / nw) % kSeg || (nw > 1 && K / nw < min_W)) continue;
+            const tdec_params p = {max_iters, 0, nw, 1};
+            float ms = 0.f, t = 0.f;
+            for (int rep = 0; rep < 4 && rs == TDEC_OK; ++rep) {
+                // the first launch builds and uploads the plan and is not timed
+                if (hipEventRecord(e0, st) != hipSuccess) rs = TDEC_EDEVICE;
+                tdec_status s =
+                    cb_decode_batch(ctx, (int32_t)n, desc.data(), d_llr, &p, nullptr, d_ok, d_it, st);
+                if (s == TDEC_ENOMEM) break;  // this shape does not fit the workspace
+                if (s != TDEC_OK) rs = s;
+                if (rs == TDEC_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                      hipEventSynchronize(e1) != hipSuccess ||
+                                      hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                    rs = TDEC_EDEVICE;
+                if (rep == 0) continue;
+                ms = (rep == 1 || t < ms) ? t : ms;
+            }
+            if (rs != TDEC_OK || ms <= 0.f) continue;
+            const float ns_kbit = ms * 1e6f / ((float)n * (float)K / 1000.f);
+            if (best < 0.f || ns_kbit < best) {
+                best = ns_kbit;
+                best_nw = nw;
+            }
+        }
+        if (rs != TDEC_OK) break;
+        ctx->tuned_nw[k_index(K)] = best_nw;
+        if (out_nw) out_nw[i] = best_nw;
+        if (out_ns_per_kbit) out_ns_per_kbit[i] = best;
+    }
+    ++ctx->tune_gen;
+    (void)hipStreamSynchronize(st);
+    if (d_llr) (void)hipFree(d_llr);
+    if (d_ok) (void)hipFree(d_ok);
+    if (d_it) (void)hipFree(d_it);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rs;
+}
+
+void tdec_autotune_reset(tdec_ctx *ctx)
+{
+    if (!ctx) return;
+    for (auto &v : ctx->tuned_nw) v = 0;
+    ++ctx->tune_gen;
 }
 
 static tdec_status encode_list(tdec_ctx *ctx, std::vector<EncCb> &list, const std::string &key,

@@ -1,0 +1,586 @@
+// server.cpp -- serving loop of libtdec: admission, device-resident LLR
+// slots, continuous batching and the per-TB latency record (tdec_server.h).
+//
+// The paper runs channel decoding as jobs of a thread pool fed by a FIFO
+// queue (Sec. IV-B "Thread-pool", Algorithm 1 appends the code blocks of
+// every UE's transport block; Sec. IV-C, Algorithm 2 lets the next free core
+// take the next job and run it to completion).  On one GPU the natural unit
+// of dispatch is a launch, not a core: one worker thread drains the queue
+// into a single persistent decode launch whenever the previous one has
+// finished, so code block parallelism happens inside the launch and the
+// queue never holds more than one launch's worth of waiting time.
+#include <hip/hip_runtime.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "tdec.h"
+#include "tdec_server.h"
+
+namespace {
+
+int64_t mono_ns()
+{
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+// First-fit allocator over [0, cap) bytes with coalescing of free extents;
+// extents are 256-byte aligned.
+class Arena {
+public:
+    void init(int64_t cap)
+    {
+        cap_ = cap;
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+        used_ = peak_ = 0;
+    }
+    int64_t alloc(int64_t n)
+    {
+        n = (n + 255) & ~(int64_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                const int64_t off = it->first, rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                used_ += n;
+                peak_ = std::max(peak_, used_);
+                return off;
+            }
+        return -1;
+    }
+    void release(int64_t off, int64_t n)
+    {
+        n = (n + 255) & ~(int64_t)255;
+        used_ -= n;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + n == nx->first) {
+            n += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+    int64_t used() const { return used_; }
+    int64_t peak() const { return peak_; }
+    void reset_peak() { peak_ = used_; }
+
+private:
+    std::map<int64_t, int64_t> free_;
+    int64_t cap_ = 0, used_ = 0, peak_ = 0;
+};
+
+struct Pending {
+    uint64_t tag;
+    int32_t tbs, C;
+    int64_t kbits;  // sum of K over the code blocks (bits)
+    int64_t slot_off, slot_bytes;
+    uint8_t *h_bits;
+    int64_t t_arrive;
+    uint64_t copy_seq;    // copy event that covers this block's upload
+    int64_t pred_dur;     // per-TB mode: predicted launch duration counted in the queue
+};
+
+constexpr int kCopyEvents = 64;
+
+}  // namespace
+
+struct tdec_server {
+    tdec_server_cfg cfg{};
+    tdec_ctx *ctx = nullptr;
+    bool model = false;
+    int64_t sim_lat = 0, sim_npk = 0;
+    int device = 0;
+    // device resources
+    int16_t *d_arena = nullptr;
+    hipStream_t copy_st = nullptr, dec_st = nullptr;
+    hipEvent_t copy_ev[kCopyEvents] = {};
+    hipEvent_t done_ev = nullptr;
+    uint64_t copy_seq = 0;  // events recorded so far
+    uint8_t *d_bits = nullptr, *h_bits_stage = nullptr;
+    size_t bits_cap = 0;
+    tdec_tb_result *d_res = nullptr, *h_res = nullptr;
+    int32_t res_cap = 0;
+    // queue state (under mu)
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> queue;
+    std::deque<tdec_server_result> done;
+    Arena arena;
+    int64_t inflight = 0;       // admitted, not yet completed
+    int64_t queued_kbits = 0;   // bits of code blocks waiting in the queue
+    int64_t queued_dur_ns = 0;  // per-TB mode: predicted durations of the queue
+    int64_t queued_cbs = 0;
+    int64_t run_end_pred = 0;   // predicted end of the running launch (0 = idle)
+    double m_lat = 0, m_npk = 0;  // service model: max(m_lat, m_npk * kbits)
+    // statistics (under mu)
+    tdec_serve_stats st{};
+    int64_t batch_tbs_sum = 0, batch_cbs_sum = 0;
+    std::vector<int64_t> lat;
+    bool stop = false;
+    std::thread worker;
+
+    int64_t dur(int64_t kbits) const
+    {
+        return (int64_t)std::max(m_lat, m_npk * (double)kbits / 1000.0);
+    }
+};
+
+namespace {
+
+struct Segm {
+    int32_t C = 0;
+    int64_t kbits = 0, n_llr = 0;
+};
+
+bool seg_of(int32_t tbs, Segm *o)
+{
+    tdec_seg s;
+    if (tdec_segment(tbs, &s) != TDEC_OK || s.C > 64) return false;
+    o->C = s.C;
+    o->kbits = (int64_t)s.Cplus * s.Kplus + (int64_t)s.Cminus * s.Kminus;
+    o->n_llr = tdec_tb_llr_count(tbs);
+    return true;
+}
+
+// Run one launch over `b` on the device; fills per-block results.
+void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res)
+{
+    const int n = (int)b.size();
+    std::vector<int32_t> tbs(n);
+    std::vector<int64_t> lo(n), bo(n);
+    uint64_t seq = 0;
+    int64_t bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        tbs[i] = b[i].tbs;
+        lo[i] = b[i].slot_off / 2;
+        bo[i] = bytes;
+        bytes += (b[i].tbs + 7) / 8;
+        seq = std::max(seq, b[i].copy_seq);
+    }
+    bool ok = hipStreamWaitEvent(s->dec_st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
+    ok = ok && tb_decode_batch(s->ctx, n, tbs.data(), lo.data(), bo.data(), s->d_arena,
+                               &s->cfg.params, s->d_bits, s->d_res, s->dec_st) == TDEC_OK;
+    ok = ok && hipMemcpyAsync(s->h_bits_stage, s->d_bits, (size_t)bytes, hipMemcpyDeviceToHost,
+                              s->dec_st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(s->h_res, s->d_res, sizeof(tdec_tb_result) * (size_t)n,
+                              hipMemcpyDeviceToHost, s->dec_st) == hipSuccess;
+    ok = ok && hipEventRecord(s->done_ev, s->dec_st) == hipSuccess;
+    ok = ok && hipEventSynchronize(s->done_ev) == hipSuccess;
+    for (int i = 0; i < n; ++i) {
+        tdec_server_result &r = res[i];
+        if (!ok) {
+            r.status = TDEC_SERVE_ERROR;
+            continue;
+        }
+        if (b[i].h_bits) memcpy(b[i].h_bits, s->h_bits_stage + bo[i], (size_t)(b[i].tbs + 7) / 8);
+        r.status = TDEC_SERVE_DONE;
+        r.tb_ok = s->h_res[i].tb_ok;
+        r.max_iters_used = s->h_res[i].max_iters_used;
+    }
+}
+
+void run_model(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
+               int64_t t0)
+{
+    int64_t kb = 0;
+    for (auto &p : b) kb += p.kbits;
+    const int64_t d = std::max<int64_t>(s->sim_lat, (int64_t)((double)s->sim_npk * kb / 1000.0));
+    std::this_thread::sleep_for(std::chrono::nanoseconds(std::max<int64_t>(0, t0 + d - mono_ns())));
+    for (auto &r : res) {
+        r.status = TDEC_SERVE_DONE;
+        r.tb_ok = 1;
+        r.max_iters_used = s->cfg.params.max_iters;
+    }
+}
+
+void worker_main(tdec_server *s)
+{
+    if (!s->model) (void)hipSetDevice(s->device);
+    std::vector<Pending> b;
+    std::vector<tdec_server_result> res;
+    for (;;) {
+        b.clear();
+        int64_t kb = 0, cbs = 0, t0 = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            if (s->queue.empty()) break;
+            // Take the oldest block, then more while the launch stays within
+            // max_batch_cb and is predicted to end before the oldest block's
+            // deadline (if even that block alone cannot make it, its deadline
+            // is lost anyway and the launch is filled for throughput).
+            const int64_t now = mono_ns();
+            const int64_t dl = s->queue.front().t_arrive + (int64_t)s->cfg.deadline_us * 1000;
+            const bool feasible = now + s->dur(s->queue.front().kbits) <= dl;
+            do {
+                const Pending &p = s->queue.front();
+                b.push_back(p);
+                kb += p.kbits;
+                cbs += p.C;
+                s->queue.pop_front();
+            } while (s->cfg.mode == TDEC_SERVE_CONTINUOUS && !s->queue.empty() &&
+                     cbs + s->queue.front().C <= s->cfg.max_batch_cb &&
+                     (!feasible || now + s->dur(kb + s->queue.front().kbits) <= dl));
+            s->queued_kbits -= kb;
+            s->queued_cbs -= cbs;
+            if (s->cfg.mode == TDEC_SERVE_PER_TB)
+                for (auto &p : b) s->queued_dur_ns -= p.pred_dur;
+            t0 = mono_ns();
+            s->run_end_pred = t0 + s->dur(kb);
+        }
+        res.assign(b.size(), tdec_server_result{});
+        if (s->model)
+            run_model(s, b, res, t0);
+        else
+            run_device(s, b, res);
+        const int64_t t1 = mono_ns();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < b.size(); ++i) {
+                tdec_server_result &r = res[i];
+                r.tag = b[i].tag;
+                r.tbs = b[i].tbs;
+                r.C = b[i].C;
+                r.batch_tbs = (int32_t)b.size();
+                r.t_arrive_ns = b[i].t_arrive;
+                r.t_done_ns = t1;
+                s->arena.release(b[i].slot_off, b[i].slot_bytes);
+                if (r.status == TDEC_SERVE_DONE) {
+                    ++s->st.completed;
+                    s->st.payload_bits += r.tbs;
+                    if (!r.tb_ok) ++s->st.tb_fail;
+                    const int64_t l = t1 - r.t_arrive_ns;
+                    s->lat.push_back(l);
+                    if (l > (int64_t)s->cfg.deadline_us * 1000) ++s->st.deadline_miss;
+                }
+                s->done.push_back(r);
+            }
+            s->inflight -= (int64_t)b.size();
+            ++s->st.batches;
+            s->batch_tbs_sum += (int64_t)b.size();
+            s->batch_cbs_sum += cbs;
+            s->st.busy_ns += t1 - t0;
+            // service model update: the regime the prediction was in learns
+            const double d = (double)(t1 - t0);
+            if (s->m_npk * (double)kb / 1000.0 < s->m_lat)
+                s->m_lat = 0.8 * s->m_lat + 0.2 * d;
+            else
+                s->m_npk = 0.8 * s->m_npk + 0.2 * d * 1000.0 / (double)std::max<int64_t>(kb, 1);
+            s->run_end_pred = 0;
+        }
+        s->cv_done.notify_all();
+    }
+}
+
+void free_device(tdec_server *s)
+{
+    if (s->model) return;
+    (void)hipSetDevice(s->device);
+    if (s->d_arena) (void)hipFree(s->d_arena);
+    if (s->d_bits) (void)hipFree(s->d_bits);
+    if (s->d_res) (void)hipFree(s->d_res);
+    if (s->h_bits_stage) (void)hipHostFree(s->h_bits_stage);
+    if (s->h_res) (void)hipHostFree(s->h_res);
+    for (auto &e : s->copy_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+    if (s->copy_st) (void)hipStreamDestroy(s->copy_st);
+    if (s->dec_st) (void)hipStreamDestroy(s->dec_st);
+}
+
+tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
+{
+    if (!cfg || cfg->deadline_us <= 0 || cfg->max_batch_cb < 0 ||
+        (cfg->mode != TDEC_SERVE_CONTINUOUS && cfg->mode != TDEC_SERVE_PER_TB) ||
+        cfg->params.max_iters < 1 || cfg->params.max_iters > 16 || cfg->model_lat_ns < 0 ||
+        cfg->model_ns_per_kbit < 0)
+        return TDEC_EINVAL;
+    s->cfg = *cfg;
+    if (!s->cfg.slot_budget_bytes) s->cfg.slot_budget_bytes = (size_t)1 << 30;
+    if (!s->cfg.max_batch_cb) s->cfg.max_batch_cb = 8192;
+    s->cfg.max_batch_cb = std::max(s->cfg.max_batch_cb, 64);  // a TB has at most 64 blocks
+    s->arena.init((int64_t)s->cfg.slot_budget_bytes);
+    s->m_lat = (double)(cfg->model_lat_ns ? cfg->model_lat_ns : 300000);
+    s->m_npk = (double)(cfg->model_ns_per_kbit ? cfg->model_ns_per_kbit : 50);
+    s->lat.reserve(1 << 16);
+    return TDEC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t tdec_now_ns(void) { return mono_ns(); }
+
+tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_server **out)
+{
+    if (!out || !ctx) return TDEC_EINVAL;
+    *out = nullptr;
+    tdec_server *s = new tdec_server();
+    tdec_status st = create_common(cfg, s);
+    if (st != TDEC_OK) {
+        delete s;
+        return st;
+    }
+    s->ctx = ctx;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return TDEC_EDEVICE;
+    }
+    s->bits_cap = (size_t)s->cfg.max_batch_cb * 768 + 64;
+    s->res_cap = s->cfg.max_batch_cb;
+    bool ok = hipMalloc(&s->d_arena, s->cfg.slot_budget_bytes) == hipSuccess &&
+              hipMalloc(&s->d_bits, s->bits_cap) == hipSuccess &&
+              hipMalloc(&s->d_res, sizeof(tdec_tb_result) * (size_t)s->res_cap) == hipSuccess &&
+              hipHostMalloc(&s->h_bits_stage, s->bits_cap, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->h_res, sizeof(tdec_tb_result) * (size_t)s->res_cap,
+                            hipHostMallocDefault) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->dec_st, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) == hipSuccess;
+    for (auto &e : s->copy_ev)
+        ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    // every copy event starts recorded, so that a wait on it never blocks on nothing
+    for (auto &e : s->copy_ev) ok = ok && hipEventRecord(e, s->copy_st) == hipSuccess;
+    if (!ok) {
+        free_device(s);
+        delete s;
+        return TDEC_ENOMEM;
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return TDEC_OK;
+}
+
+tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
+                                     int64_t ns_per_kbit, tdec_server **out)
+{
+    if (!out || lat_ns < 0 || ns_per_kbit < 0) return TDEC_EINVAL;
+    *out = nullptr;
+    tdec_server *s = new tdec_server();
+    tdec_status st = create_common(cfg, s);
+    if (st != TDEC_OK) {
+        delete s;
+        return st;
+    }
+    s->model = true;
+    s->sim_lat = lat_ns;
+    s->sim_npk = ns_per_kbit;
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return TDEC_OK;
+}
+
+int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
+                           const int16_t *const *h_llr, uint8_t *const *h_bits,
+                           int64_t t_arrive_ns, int32_t *status)
+{
+    if (!s || n < 0) return TDEC_EINVAL;
+    if (n == 0) return 0;
+    if (!tags || !tbs || !h_llr) return TDEC_EINVAL;
+    if (!s->model && hipSetDevice(s->device) != hipSuccess) return TDEC_EDEVICE;
+    int32_t admitted = 0;
+    bool copied = false;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const int64_t now = mono_ns();
+        const int64_t deadline = t_arrive_ns + (int64_t)s->cfg.deadline_us * 1000;
+        for (int32_t i = 0; i < n; ++i) {
+            ++s->st.submitted;
+            Segm g;
+            int32_t why = TDEC_SERVE_DONE;
+            int64_t off = -1, bytes = 0;
+            if (!seg_of(tbs[i], &g) || !h_llr[i]) {
+                why = TDEC_SERVE_REJ_INVALID;
+            } else {
+                bytes = g.n_llr * 2;
+                off = s->arena.alloc(bytes);
+                if (off < 0) why = TDEC_SERVE_REJ_BUDGET;
+            }
+            if (why == TDEC_SERVE_DONE && (s->cfg.admission & TDEC_ADMIT_DEADLINE)) {
+                // the block joins the next launch after the running one (or
+                // a later one once the queue exceeds a launch)
+                const int64_t start = std::max(now, s->run_end_pred);
+                int64_t pred;
+                int64_t limit = deadline;
+                if (s->cfg.mode == TDEC_SERVE_CONTINUOUS) {
+                    const int64_t launches =
+                        (s->queued_cbs + g.C + s->cfg.max_batch_cb - 1) / s->cfg.max_batch_cb;
+                    pred = start + s->dur(s->queued_kbits + g.kbits) +
+                           (launches - 1) * (int64_t)s->m_lat;
+                    // joining the same launch as the oldest waiting block
+                    // must not push that block past its own deadline
+                    if (launches == 1 && !s->queue.empty())
+                        limit = std::min(limit, s->queue.front().t_arrive +
+                                                    (int64_t)s->cfg.deadline_us * 1000);
+                } else {
+                    pred = start + s->queued_dur_ns + s->dur(g.kbits);
+                }
+                if (pred > limit) {
+                    why = TDEC_SERVE_REJ_DEADLINE;
+                    s->arena.release(off, bytes);
+                }
+            }
+            if (status) status[i] = why;
+            if (why != TDEC_SERVE_DONE) {
+                if (why == TDEC_SERVE_REJ_BUDGET) ++s->st.rej_budget;
+                if (why == TDEC_SERVE_REJ_DEADLINE) ++s->st.rej_deadline;
+                if (why == TDEC_SERVE_REJ_INVALID) ++s->st.rej_invalid;
+                tdec_server_result r{};
+                r.tag = tags[i];
+                r.tbs = tbs[i];
+                r.status = why;
+                r.C = g.C;
+                r.t_arrive_ns = r.t_done_ns = t_arrive_ns;
+                s->done.push_back(r);
+                continue;
+            }
+            if (!s->model &&
+                hipMemcpyAsync(s->d_arena + off / 2, h_llr[i], (size_t)bytes,
+                               hipMemcpyHostToDevice, s->copy_st) != hipSuccess) {
+                s->arena.release(off, bytes);
+                if (status) status[i] = TDEC_SERVE_ERROR;
+                tdec_server_result r{};
+                r.tag = tags[i];
+                r.tbs = tbs[i];
+                r.status = TDEC_SERVE_ERROR;
+                r.C = g.C;
+                r.t_arrive_ns = r.t_done_ns = t_arrive_ns;
+                s->done.push_back(r);
+                continue;
+            }
+            copied = !s->model;
+            Pending p;
+            p.tag = tags[i];
+            p.tbs = tbs[i];
+            p.C = g.C;
+            p.kbits = g.kbits;
+            p.slot_off = off;
+            p.slot_bytes = bytes;
+            p.h_bits = h_bits ? h_bits[i] : nullptr;
+            p.t_arrive = t_arrive_ns;
+            p.copy_seq = s->copy_seq + 1;
+            s->queue.push_back(p);
+            s->queued_kbits += g.kbits;
+            s->queued_cbs += g.C;
+            p.pred_dur = s->cfg.mode == TDEC_SERVE_PER_TB ? s->dur(g.kbits) : 0;
+            s->queued_dur_ns += p.pred_dur;
+            ++s->inflight;
+            ++s->st.admitted;
+            ++admitted;
+        }
+        if (copied) {
+            // record after this call's copies; the worker waits for it before
+            // it launches any of these blocks
+            ++s->copy_seq;
+            if (hipEventRecord(s->copy_ev[s->copy_seq % kCopyEvents], s->copy_st) != hipSuccess)
+                return TDEC_EDEVICE;
+        }
+    }
+    s->cv_work.notify_one();
+    s->cv_done.notify_all();
+    return admitted;
+}
+
+int32_t tdec_server_poll(tdec_server *s, tdec_server_result *out, int32_t max, int32_t wait_us)
+{
+    if (!s || !out || max <= 0) return 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && wait_us > 0)
+        s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us),
+                            [&] { return !s->done.empty(); });
+    int32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    return k;
+}
+
+tdec_status tdec_server_drain(tdec_server *s, int32_t timeout_ms)
+{
+    if (!s) return TDEC_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(std::max(timeout_ms, 0)),
+                                        [&] { return s->inflight == 0; });
+    return ok ? TDEC_OK : TDEC_EBUSY;
+}
+
+tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out)
+{
+    if (!s || !out) return TDEC_EINVAL;
+    std::vector<int64_t> v;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        *out = s->st;
+        v = s->lat;
+        out->model_lat_ns = (int64_t)s->m_lat;
+        out->model_ns_per_kbit = (int64_t)s->m_npk;
+        out->slots_in_use_bytes = s->arena.used();
+        out->slots_peak_bytes = s->arena.peak();
+        out->mean_batch_tbs = s->st.batches ? (double)s->batch_tbs_sum / s->st.batches : 0.0;
+        out->mean_batch_cbs = s->st.batches ? (double)s->batch_cbs_sum / s->st.batches : 0.0;
+    }
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        const size_t n = v.size();
+        // nearest-rank percentiles
+        auto q = [&](double f) {
+            size_t r = (size_t)((double)n * f + 0.999999999);
+            r = std::min(std::max<size_t>(r, 1), n);
+            return v[r - 1];
+        };
+        out->lat_p50_ns = q(0.50);
+        out->lat_p99_ns = q(0.99);
+        out->lat_p999_ns = q(0.999);
+        out->lat_max_ns = v.back();
+        long double sum = 0;
+        for (int64_t x : v) sum += x;
+        out->lat_mean_ns = (int64_t)(sum / n);
+    }
+    return TDEC_OK;
+}
+
+void tdec_server_reset_stats(tdec_server *s)
+{
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st = tdec_serve_stats{};
+    s->lat.clear();
+    s->batch_tbs_sum = s->batch_cbs_sum = 0;
+    s->arena.reset_peak();
+}
+
+void tdec_server_destroy(tdec_server *s)
+{
+    if (!s) return;
+    (void)tdec_server_drain(s, 60000);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    free_device(s);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,4 +1,4 @@
-"""The C-ABI library: it loads, exports every function include/tdec.h
+"""The C-ABI library: it loads, exports every function include/*.h
 declares, and its host-only helpers (segmentation, table, QPP) agree with
 the oracle.  No GPU needed."""
 import ctypes as ct
@@ -14,7 +14,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "tdec.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc))
+                  if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\([^;{]*\)\s*;", src)
     return sorted(set(n for n in names if n not in ("sizeof",)))

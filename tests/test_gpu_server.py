@@ -1,0 +1,102 @@
+"""The serving loop on the GPU: transport blocks submitted over several
+arrival batches come back with the oracle's bits and flags, in continuous
+batching and in per-TB mode."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workload as wl
+from inputs import tb_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    import paper_1905_01141_amd as T
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU is required for the gpu-marked tests")
+    return T, T.Decoder(0), torch
+
+
+def run_server(dev, mode, tbs_list, llr, lo, p, groups):
+    T, D, torch = dev
+    pinned = torch.empty(llr.size, dtype=torch.int16, pin_memory=True)
+    pinned.numpy()[:] = llr
+    base = pinned.data_ptr()
+    out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+    srv = T.Server(D, T.server_cfg(p, deadline_us=10_000_000, mode=mode))
+    try:
+        idx = np.array_split(np.arange(len(tbs_list)), groups)
+        for g in idx:
+            srv.submit(g.tolist(), [tbs_list[i] for i in g], [base + 2 * int(lo[i]) for i in g],
+                       [out[i].ctypes.data for i in g])
+            time.sleep(0.0005)
+        srv.drain(60000)
+        res, t0 = [], time.monotonic()
+        while len(res) < len(tbs_list) and time.monotonic() - t0 < 30:
+            res += srv.poll(4096, 100000)
+        st = srv.stats()
+    finally:
+        srv.close()
+    return out, {r["tag"]: r for r in res}, st
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_server_matches_oracle(dev, mode):
+    T = dev[0]
+    g = wl.rng(7, 1)
+    tbs_list = [int(x) for x in wl.tbs_log_uniform(g, 10)] + [40, 6120, 6121, 20000]
+    tbs_list = [min(t, 30000) for t in tbs_list]
+    esn0 = np.linspace(0.0, 5.0, len(tbs_list))
+    say(f"[server] mode={mode} tbs={tbs_list}")
+    llr, pays, lo, bo = tb_batch(tbs_list, "16qam", esn0, 7)
+    out, res, st = run_server(dev, mode, tbs_list, llr, lo, T.params(6, 1, 1, 0), 3)
+    assert st["completed"] == len(tbs_list) and st["rej_budget"] == 0
+    if mode == 1:
+        assert st["batches"] == len(tbs_list)
+    p = O.params(6, 1, 1, 0)
+    for i, tbs in enumerate(tbs_list):
+        ob, ores = O.tb_decode(llr[lo[i]:lo[i] + O.tb_llr_count(tbs)], tbs, p)
+        r = res[i]
+        assert r["status"] == T.SERVE_DONE
+        assert r["tb_ok"] == ores["tb_ok"] and r["max_iters_used"] == ores["max_iters_used"], i
+        assert r["C"] == ores["C"]
+        assert np.array_equal(out[i], ob), (i, tbs)
+        assert r["t_done_ns"] > r["t_arrive_ns"]
+
+
+def test_server_auto_windows_matches_direct_call(dev):
+    """With the tuned window counts the server returns what one direct
+    tb_decode_batch call returns (itself checked against the oracle)."""
+    T, D, torch = dev
+    g = wl.rng(8, 1)
+    tbs_list = [int(x) for x in wl.tbs_log_uniform(g, 16)]
+    say(f"[server] auto windows tbs={tbs_list}")
+    llr, pays, lo, bo = tb_batch(tbs_list, "64qam", 14.0, 8)
+    p = T.params(8, 1, 0, 1)
+    out, res, st = run_server(dev, 0, tbs_list, llr, lo, p, 4)
+    x = torch.from_numpy(llr).cuda()
+    nb = int(bo[-1] + (tbs_list[-1] + 7) // 8)
+    bits = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    rr = torch.zeros(len(tbs_list) * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    D.tb_decode_batch(tbs_list, lo, bo, x, p, bits, rr)
+    torch.cuda.synchronize()
+    gb = bits.cpu().numpy()
+    gr = T.parse_tb_results(rr.cpu().numpy())
+    for i, tbs in enumerate(tbs_list):
+        assert res[i]["tb_ok"] == gr[i]["tb_ok"]
+        assert res[i]["max_iters_used"] == gr[i]["max_iters_used"]
+        assert np.array_equal(out[i], gb[bo[i]:bo[i] + (tbs + 7) // 8])
+        # at 14 dB 64QAM every TB decodes
+        assert res[i]["tb_ok"] == 1
+        assert np.array_equal(np.unpackbits(out[i])[:tbs], pays[i])

@@ -313,3 +313,28 @@ def test_iteration_dataflow(orc, K, F, nw, win_init):
     r = orc.cb_decode(y.astype(np.int16), K, F, orc.CRC_NONE, orc.params(2, 0, nw, win_init))
     assert np.array_equal(r["lapp"], lapp)
     assert np.array_equal(r["bits"], (lapp > 0).astype(np.uint8))
+
+
+def test_tb_decode_per_block_windows_reduces_to_common_count(orc):
+    """Per-block window counts equal to the common count give the same TB
+    result, and each block of a per-block run equals that block decoded alone
+    with its own count (reassembly does not depend on the counts)."""
+    import workload as wl
+    tbs = 6121 + 6144  # 3 blocks: K 4096 (55 filler bits), 4160, 4160
+    sizes = orc.cb_sizes(tbs)
+    g = wl.rng(41, 0)
+    pay = wl.random_bits(g, tbs)
+    d, _ = orc.tb_encode(pay)
+    llr = wl.channel_blocks(d, sizes, "qpsk", 1.5, g)
+    p = orc.params(4, 0, 8, 1)
+    b0, r0 = orc.tb_decode(llr, tbs, p)
+    b1, r1 = orc.tb_decode_windows(llr, tbs, p, [8] * len(sizes))
+    assert r0 == r1 and np.array_equal(b0, b1)
+    nws = [1 if k % 16 else 2 for k, _ in sizes]
+    b2, r2 = orc.tb_decode_windows(llr, tbs, p, nws)
+    off = 0
+    for r, (K, F) in enumerate(sizes):
+        crc = orc.CRC24B if len(sizes) > 1 else orc.CRC24A
+        res = orc.cb_decode(llr[off:off + 3 * (K + 4)], K, F, crc, orc.params(4, 0, nws[r], 1))
+        assert res["ok"] == r2["cb_ok"][r] and res["iters"] == r2["cb_iters"][r]
+        off += 3 * (K + 4)

@@ -1,0 +1,189 @@
+"""Serving loop host logic (admission, batching, slot accounting, latency
+statistics) with the modelled executor: no device is touched, every
+"launch" lasts max(lat, ns_per_kbit * kbits)."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_1905_01141_amd as T
+
+MAX_TB = 75376  # 13 blocks of K = 5824
+SLOT_MAX = ((3 * 13 * (5824 + 4) * 2) + 255) // 256 * 256  # one max-size TB slot
+
+
+def _llr_buf(tbs):
+    return np.zeros(T.tb_llr_count(tbs), np.int16)
+
+
+def _submit(srv, tags, tbs, t=None):
+    bufs = [_llr_buf(x) for x in tbs]
+    k, st = srv.submit(tags, tbs, [b.ctypes.data for b in bufs], None, t, keep=bufs)
+    return k, st
+
+
+def _collect(srv, n, timeout=5.0):
+    out, t0 = [], time.monotonic()
+    while len(out) < n and time.monotonic() - t0 < timeout:
+        out += srv.poll(4096, 20000)
+    return out
+
+
+def _nearest_rank(v, q):
+    v = np.sort(np.asarray(v))
+    r = int(np.ceil(q * len(v) - 1e-9))
+    return int(v[min(max(r, 1), len(v)) - 1])
+
+
+def test_continuous_batching_merges_waiting_blocks():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000, model_lat_ns=2_000_000)
+    srv = T.Server.model(cfg, 2_000_000, 0)
+    try:
+        tags = []
+        for tti in range(6):
+            tg = list(range(tti * 20, tti * 20 + 20))
+            k, st = _submit(srv, tg, [4000] * 20)
+            assert k == 20 and (st == T.SERVE_DONE).all()
+            tags += tg
+            time.sleep(0.001)
+        srv.drain(10000)
+        res = _collect(srv, len(tags))
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert sorted(r["tag"] for r in res) == tags
+    assert all(r["status"] == T.SERVE_DONE and r["tb_ok"] == 1 for r in res)
+    assert s["completed"] == 120 and s["admitted"] == 120
+    # a launch lasts 2 ms while a TTI's blocks arrive every 1 ms: launches merge TTIs
+    assert s["batches"] < 120 and max(r["batch_tbs"] for r in res) > 20
+    assert s["mean_batch_tbs"] == pytest.approx(120 / s["batches"])
+    assert all(r["t_done_ns"] - r["t_arrive_ns"] >= 2_000_000 for r in res)
+    assert s["slots_in_use_bytes"] == 0
+
+
+def test_per_tb_mode_launches_each_block_alone():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000, mode=T.SERVE_PER_TB)
+    srv = T.Server.model(cfg, 200_000, 0)
+    try:
+        _submit(srv, list(range(15)), [3000] * 15)
+        srv.drain(10000)
+        res = _collect(srv, 15)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert s["batches"] == 15 and all(r["batch_tbs"] == 1 for r in res)
+    # FIFO: completion order is arrival order
+    assert [r["tag"] for r in res] == list(range(15))
+    # the i-th block waits for the i launches before it
+    lat = sorted(r["t_done_ns"] - r["t_arrive_ns"] for r in res)
+    assert lat[-1] >= 15 * 200_000
+
+
+def test_budget_admission_and_slot_release():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000,
+                       slot_budget_bytes=2 * SLOT_MAX + 1000)
+    srv = T.Server.model(cfg, 300_000, 0)
+    try:
+        k, st = _submit(srv, list(range(5)), [MAX_TB] * 5)
+        assert k == 2
+        assert list(st) == [T.SERVE_DONE] * 2 + [T.SERVE_REJ_BUDGET] * 3
+        s = srv.stats()
+        assert s["rej_budget"] == 3 and s["slots_in_use_bytes"] == 2 * SLOT_MAX
+        srv.drain(10000)
+        res = _collect(srv, 5)
+        # slots come back: the same request fits again
+        k2, _ = _submit(srv, [10, 11], [MAX_TB] * 2)
+        assert k2 == 2
+        srv.drain(10000)
+        res += _collect(srv, 2)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert sorted(r["status"] for r in res) == [0, 0, 0, 0, 1, 1, 1]
+    assert s["slots_in_use_bytes"] == 0 and s["slots_peak_bytes"] == 2 * SLOT_MAX
+
+
+def test_deadline_admission_rejects_predicted_misses():
+    # the model says a launch takes 5 ms; the deadline is 3 ms: nothing can make it
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=3000,
+                       admission=T.ADMIT_BUDGET | T.ADMIT_DEADLINE, model_lat_ns=5_000_000)
+    srv = T.Server.model(cfg, 5_000_000, 0)
+    try:
+        k, st = _submit(srv, list(range(4)), [1000] * 4)
+        res = _collect(srv, 4)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert k == 0 and (st == T.SERVE_REJ_DEADLINE).all()
+    assert s["rej_deadline"] == 4 and s["completed"] == 0
+    assert all(r["status"] == T.SERVE_REJ_DEADLINE for r in res)
+
+
+def test_deadline_admission_sheds_overload():
+    # every arrival brings ~3 ms of decoding (20 blocks of 6144 bits at 25 us
+    # per kbit) while arrivals come every ~1 ms: the predictor must shed load
+    # so that admitted blocks keep (close to) their deadline
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=3000,
+                       admission=T.ADMIT_BUDGET | T.ADMIT_DEADLINE,
+                       model_lat_ns=200_000, model_ns_per_kbit=25_000, max_batch_cb=64)
+    srv = T.Server.model(cfg, 200_000, 25_000)
+    n = 0
+    try:
+        t0 = time.monotonic()
+        while time.monotonic() - t0 < 0.12:
+            _submit(srv, list(range(n, n + 20)), [6120] * 20)
+            n += 20
+            time.sleep(0.001)
+        srv.drain(20000)
+        res = _collect(srv, n)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert len(res) == n
+    assert s["rej_deadline"] > 0 and s["completed"] > 0
+    done = [r for r in res if r["status"] == T.SERVE_DONE]
+    late = sum(r["t_done_ns"] - r["t_arrive_ns"] > 3_000_000 for r in done)
+    assert late <= 0.2 * len(done)
+
+
+def test_invalid_sizes_and_miss_counting():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=1000)
+    srv = T.Server.model(cfg, 1_500_000, 0)
+    try:
+        buf = _llr_buf(100)
+        k, st = srv.submit([1, 2, 3], [100, 0, 400000], [buf.ctypes.data] * 3, keep=[buf] * 3)
+        assert k == 1
+        assert list(st) == [T.SERVE_DONE, T.SERVE_REJ_INVALID, T.SERVE_REJ_INVALID]
+        srv.drain(10000)
+        res = _collect(srv, 3)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert s["rej_invalid"] == 2 and s["completed"] == 1
+    # a 1.5 ms launch against a 1 ms deadline: admitted (budget only) and late
+    assert s["deadline_miss"] == 1
+    assert {r["tag"]: r["status"] for r in res} == {1: 0, 2: 3, 3: 3}
+
+
+def test_latency_percentiles_match_results():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000)
+    srv = T.Server.model(cfg, 100_000, 2_000)
+    try:
+        rng = np.random.default_rng(5)
+        n = 0
+        for _ in range(30):
+            m = int(rng.integers(1, 8))
+            _submit(srv, list(range(n, n + m)), rng.integers(100, 20000, m).tolist())
+            n += m
+            time.sleep(0.0005)
+        srv.drain(10000)
+        res = _collect(srv, n)
+        s = srv.stats()
+    finally:
+        srv.close()
+    lat = [r["t_done_ns"] - r["t_arrive_ns"] for r in res]
+    assert s["completed"] == n == len(lat)
+    assert s["lat_p50_ns"] == _nearest_rank(lat, 0.50)
+    assert s["lat_p99_ns"] == _nearest_rank(lat, 0.99)
+    assert s["lat_max_ns"] == max(lat)
+    assert s["payload_bits"] == sum(r["tbs"] for r in res)
