@@ -14,6 +14,23 @@ Also reported (stderr + extra JSON fields): the same batch as configured
 fraction, and the CPU oracle's throughput on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --workload {tb,mixed,serving,cells} [options]
+
+The default workload is the uniform batch above; the others measure the
+remaining configurations and print one JSON line each:
+  tb      : one 75376-bit transport block (13 x K5824), QPSK Es/N0 2 dB,
+            exactly 6 iterations: latency alone (device and host-to-host) at
+            full length and at the library's window choice, and throughput
+            over a stream of such blocks;
+  mixed   : TTIs of 64 transport blocks (log-uniform sizes, QPSK/16QAM/64QAM,
+            Es/N0 uniform in [0, 18] dB, <= 8 iterations with CRC stop), each
+            TTI one captured-graph launch with autotuned windows;
+  serving : the serving loop under Poisson arrivals of 338*rho TBs per 1 ms
+            TTI (64QAM, Es/N0 uniform in [12, 22] dB, 3 ms deadline, 8 GB
+            slot budget): p50/p99 latency, misses, rejections, Gbit/s;
+  cells   : cells of 2 layers x one 75376-bit TB per TTI at 256QAM near 30 %
+            TB error rate, 8 iterations forced: the most cells whose p99
+            latency stays within 3 ms (binary search).
 """
 from __future__ import annotations
 
@@ -110,6 +127,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=N_CB)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--workload", default="uniform",
+                    choices=["uniform", "tb", "mixed", "serving", "cells"])
+    ap.add_argument("--rho", type=str, default="0.25,0.5,1,2,4",
+                    help="serving: load points (fractions of 40 cells' capacity)")
+    ap.add_argument("--ttis", type=int, default=3000, help="serving/cells: measured TTIs")
+    ap.add_argument("--mode", default="continuous", choices=["continuous", "per-tb"],
+                    help="serving: batching form")
+    ap.add_argument("--windows", default="tuned", choices=["tuned", "rule"],
+                    help="serving/cells: autotuned window counts (latency objective) or the "
+                         "library's built-in rule")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -123,6 +150,11 @@ def main():
     import paper_1905_01141_amd as T
 
     torch.cuda.set_device(0)
+    if args.workload != "uniform":
+        import bench_workloads as BW
+        line = getattr(BW, "run_" + args.workload)(args)
+        print(json.dumps(line), flush=True)
+        return
     D = T.Decoder(0)
     log("[bench] building inputs: GPU encoder + 16QAM AWGN channel")
     descs, llr_h, pay_bits, n_bytes = build_inputs(T, D, torch)

@@ -90,6 +90,10 @@ typedef struct {
     int64_t lat_p50_ns, lat_p99_ns, lat_p999_ns, lat_max_ns, lat_mean_ns; /* completed TBs */
     int64_t model_lat_ns, model_ns_per_kbit;  /* the service model as learned so far */
     int64_t slots_in_use_bytes, slots_peak_bytes;
+    /* per launch, the paper's performance captor delays: pre-processing
+     * (host: batch formation, plan, enqueue), coding (decode kernel), and
+     * post-processing (transport block assembly, copies back, copy-out) */
+    int64_t mean_pre_ns, mean_coding_ns, mean_post_ns;
     double mean_batch_tbs, mean_batch_cbs;
 } tdec_serve_stats;
 
@@ -118,6 +122,15 @@ tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
 int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
                            const int16_t *const *h_llr, uint8_t *const *h_bits,
                            int64_t t_arrive_ns, int32_t *status);
+
+/* The same for LLRs already in device memory (for instance written there by
+ * a demodulator running on the GPU): d_llr[i] are device pointers of the
+ * context's device.  The blocks are copied into the server's slots by one
+ * gather launch per 200 blocks on the copy stream, instead of one host copy
+ * each; the caller's buffers must stay valid until the results are polled. */
+int32_t tdec_server_submit_dev(tdec_server *s, int32_t n, const uint64_t *tags,
+                               const int32_t *tbs, const int16_t *const *d_llr,
+                               uint8_t *const *h_bits, int64_t t_arrive_ns, int32_t *status);
 
 /* Move up to `max` finished results (completion order) into out; waits up
  * to wait_us for the first one when none is ready.  Returns the count. */

@@ -32,6 +32,18 @@
  * twin") stores every metric in int16 with saturating adds, renormalises the
  * state metrics, and counts any saturation of a value that decides a result;
  * the tests require both to agree bit for bit.
+ *
+ * Pins (tests/test_oracle_*.py): CRC check values of the public catalogue,
+ * polynomial long division, linearity; the K step rule; worked segmentation
+ * examples and invariants; QPP bijection, recurrence form and two spot values;
+ * the encoder's impulse response and parity identity; the constituent decoder
+ * against brute force over all codewords; window plumbing against full
+ * length; the int16 twin against the exact build; noiseless round trip and
+ * codeword-translation symmetry of the full decoder.
+ * Parity unpinned (conformance of constants only): the full table of QPP
+ * coefficients and the order of the 12 tail bits follow TS 36.212 as recalled
+ * here; no copy of the standard is at hand to check them against, so a
+ * consistent misreading shared by encoder and decoder would pass every test.
  */
 #ifndef TDEC_ORACLE_H
 #define TDEC_ORACLE_H

@@ -25,7 +25,8 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_server_create_model", "tdec_server_submit", "tdec_server_poll",
            "tdec_server_drain", "tdec_server_stats", "tdec_server_reset_stats",
            "tdec_server_destroy", "tdec_graph_cb_decode", "tdec_graph_tb_decode",
-           "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset")
+           "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
+           "tdec_server_submit_dev")
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -70,7 +71,8 @@ class ServeStats(ct.Structure):
         "submitted", "admitted", "rej_budget", "rej_deadline", "rej_invalid", "completed",
         "tb_fail", "deadline_miss", "batches", "payload_bits", "busy_ns", "lat_p50_ns",
         "lat_p99_ns", "lat_p999_ns", "lat_max_ns", "lat_mean_ns", "model_lat_ns",
-        "model_ns_per_kbit", "slots_in_use_bytes", "slots_peak_bytes")] + [
+        "model_ns_per_kbit", "slots_in_use_bytes", "slots_peak_bytes", "mean_pre_ns",
+        "mean_coding_ns", "mean_post_ns")] + [
         ("mean_batch_tbs", ct.c_double), ("mean_batch_cbs", ct.c_double)]
 
     def as_dict(self) -> dict:
@@ -125,6 +127,7 @@ def lib():
         L.tdec_server_create.argtypes = [vp, P(ServerCfg), P(vp)]
         L.tdec_server_create_model.argtypes = [P(ServerCfg), i64, i64, P(vp)]
         L.tdec_server_submit.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
+        L.tdec_server_submit_dev.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
         L.tdec_server_poll.argtypes = [vp, vp, i32, i32]
         L.tdec_server_drain.argtypes = [vp, i32]
         L.tdec_server_stats.argtypes = [vp, P(ServeStats)]
@@ -430,11 +433,13 @@ class Server:
     def model(cls, cfg: ServerCfg, lat_ns: int, ns_per_kbit: int) -> "Server":
         return cls(None, cfg, _model=(lat_ns, ns_per_kbit))
 
-    def submit(self, tags, tbs, llr_ptrs, bits_ptrs=None, t_arrive_ns=None, keep=None):
-        """Submit one arrival batch.  llr_ptrs / bits_ptrs: host addresses
-        (ints) of each block's int16 LLRs and payload buffer; `keep` (a list
-        per block, optional) holds objects that must stay alive until the
-        result is polled.  Returns (admitted count, status array)."""
+    def submit(self, tags, tbs, llr_ptrs, bits_ptrs=None, t_arrive_ns=None, keep=None,
+               device=False):
+        """Submit one arrival batch.  llr_ptrs / bits_ptrs: addresses (ints)
+        of each block's int16 LLRs (host memory, or device memory with
+        device=True) and payload buffer (host); `keep` (a list per block,
+        optional) holds objects that must stay alive until the result is
+        polled.  Returns (admitted count, status array)."""
         tags = np.ascontiguousarray(tags, np.uint64)
         tbs = np.ascontiguousarray(tbs, np.int32)
         n = tags.size
@@ -447,8 +452,8 @@ class Server:
         if keep is not None:
             for i in range(n):
                 self._keep[int(tags[i])] = keep[i]
-        k = lib().tdec_server_submit(self._h, n, _np_ptr(tags), _np_ptr(tbs), _np_ptr(lp),
-                                     _np_ptr(bp), t, _np_ptr(st))
+        fn = lib().tdec_server_submit_dev if device else lib().tdec_server_submit
+        k = fn(self._h, n, _np_ptr(tags), _np_ptr(tbs), _np_ptr(lp), _np_ptr(bp), t, _np_ptr(st))
         if k < 0:
             raise TdecError("tdec_server_submit", k)
         return k, st
@@ -462,6 +467,15 @@ class Server:
             self._keep.pop(int(r.tag), None)
             out.append(d)
         return out
+
+    def discard(self, max_n=65536, wait_us=0) -> int:
+        """Drop up to max_n finished results without converting them (for
+        load generators that read the statistics only); returns the count.
+        Buffers passed with `keep` stay referenced."""
+        if getattr(self, "_rawbuf", None) is None or len(self._rawbuf) < max_n:
+            self._rawbuf = (ServeResult * max_n)()
+        return int(lib().tdec_server_poll(self._h, ct.cast(self._rawbuf, ct.c_void_p), max_n,
+                                          int(wait_us)))
 
     def drain(self, timeout_ms=60000):
         _check("tdec_server_drain", lib().tdec_server_drain(self._h, int(timeout_ms)))

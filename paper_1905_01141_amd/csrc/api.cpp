@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -38,6 +39,7 @@ struct PlanSlot {
     int n_items = 0, grid = 0, wg = 0, lds = 0;
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
+    int asm_words = 0;  // largest (B + 31) / 32 of the plan's transport blocks
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
@@ -68,6 +70,7 @@ struct tdec_ctx {
     uint64_t clock = 0;
     int32_t tuned_nw[kNumK] = {};  // autotuned window count per size (0 = default rule)
     uint32_t tune_gen = 0;         // bumped whenever tuned_nw changes (enters plan keys)
+    std::map<int64_t, int> occ_cache;  // resident decode work groups per CU by (threads, LDS)
     int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
 };
@@ -203,10 +206,17 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     }
     // persistent grid: as many work groups as can be resident
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(), wg, lds) !=
-            hipSuccess ||
-        occ < 1)
-        occ = std::max(1, kLdsPerCu / std::max(lds, 1));
+    const int64_t okey = (int64_t)wg << 32 | (uint32_t)lds;
+    auto oc = ctx->occ_cache.find(okey);
+    if (oc != ctx->occ_cache.end()) {
+        occ = oc->second;
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(), wg, lds) !=
+                hipSuccess ||
+            occ < 1)
+            occ = std::max(1, kLdsPerCu / std::max(lds, 1));
+        ctx->occ_cache[okey] = occ;
+    }
     int grid = std::min<int64_t>((int64_t)items.size(), (int64_t)occ * ctx->num_cus);
     if (ctx->grid_cap > 0) grid = std::min(grid, ctx->grid_cap);
     const int64_t fit = (int64_t)(ctx->scratch_bytes / (size_t)stride);
@@ -228,6 +238,8 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.n_items = (int)items.size();
     ps.n_cb = (int)cbl.size();
     ps.n_tb = (int)ntb;
+    ps.asm_words = 0;
+    for (size_t t = 0; t < ntb; ++t) ps.asm_words = std::max(ps.asm_words, ((*tbs)[t].B + 31) / 32);
     ps.grid = grid;
     ps.wg = wg;
     ps.lds = lds;
@@ -399,14 +411,17 @@ tdec_status make_tb_reqs(const tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
 // Decode + assemble launches of a transport block plan whose device copy is at d_plan.
 tdec_status launch_tb_plan(tdec_ctx *ctx, PlanSlot *ps, char *d_plan, const int16_t *d_llr,
                            const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
-                           hipStream_t st)
+                           hipStream_t st, hipEvent_t ev_start = nullptr,
+                           hipEvent_t ev_mid = nullptr)
 {
     PlanSlot v = *ps;
     v.d_buf = d_plan;
+    if (ev_start && hipEventRecord(ev_start, st) != hipSuccess) return TDEC_EDEVICE;
     tdec_status s = launch_plan(ctx, &v, d_llr, params, nullptr, ctx->d_ok, ctx->d_it, true, st);
     if (s != TDEC_OK) return s;
-    if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ctx->d_hard,
-                           ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
+    if (ev_mid && hipEventRecord(ev_mid, st) != hipSuccess) return TDEC_EDEVICE;
+    if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ps->asm_words,
+                           ctx->d_hard, ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }
@@ -544,7 +559,7 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
         return TDEC_EDEVICE;
     }
     c->num_cus = prop.multiProcessorCount;
-    const size_t tab_bytes = 2 * kCrcTabN * sizeof(uint32_t);
+    const size_t tab_bytes = kCrcTabWords * sizeof(uint32_t);
     c->flags_cap = 1 << 20;
     c->encbuf_bytes = 1 << 20;
     const size_t plan_bytes = (size_t)kPlanSlots * kPlanSlotBytes;
@@ -574,9 +589,10 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
              hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
     }
     if (ok) {
-        std::vector<uint32_t> tab(2 * kCrcTabN);
+        std::vector<uint32_t> tab(kCrcTabWords);
         crc_shift_table(kPoly24A, tab.data(), kCrcTabN);
         crc_shift_table(kPoly24B, tab.data() + kCrcTabN, kCrcTabN);
+        crc_x32_table(kPoly24A, tab.data() + 2 * kCrcTabN, kX32N);
         ok = hipMemcpy(c->d_crc_tab, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (ok) {
@@ -659,6 +675,18 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
                             const tdec_params *params, uint8_t *d_bits, tdec_tb_result *d_res,
                             void *stream)
 {
+    return tdec::tb_decode_batch_timed(ctx, n_tb, tbs, llr_off, bits_off, d_llr, params, d_bits,
+                                       d_res, stream, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+tdec_status tdec::tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                        const int64_t *llr_off, const int64_t *bits_off,
+                                        const int16_t *d_llr, const tdec_params *params,
+                                        uint8_t *d_bits, tdec_tb_result *d_res, void *stream,
+                                        void *ev_start, void *ev_mid)
+{
     if (!ctx || n_tb < 0 || !params_ok(params)) return TDEC_EINVAL;
     if (n_tb == 0) return TDEC_OK;
     if (!tbs || !llr_off || !d_llr || !d_res) return TDEC_EINVAL;
@@ -683,8 +711,11 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
             return s;
         }
     }
-    return launch_tb_plan(ctx, ps, ps->d_buf, d_llr, params, d_bits, d_res, st);
+    return launch_tb_plan(ctx, ps, ps->d_buf, d_llr, params, d_bits, d_res, st,
+                          (hipEvent_t)ev_start, (hipEvent_t)ev_mid);
 }
+
+extern "C" {
 
 tdec_status tb_decode(tdec_ctx *ctx, const int16_t *d_llr, int32_t tbs, const tdec_params *params,
                       uint8_t *d_bits, tdec_tb_result *d_res, void *stream)
@@ -803,21 +834,31 @@ tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t
         for (int32_t nw = 1; nw <= kMaxWgThreads / 2 && rs == TDEC_OK; ++nw) {
             if (K % nw || (K / nw) % kSeg || (nw > 1 && K / nw < min_W)) continue;
             const tdec_params p = {max_iters, 0, nw, 1};
-            float ms = 0.f, t = 0.f;
-            for (int rep = 0; rep < 4 && rs == TDEC_OK; ++rep) {
-                // the first launch builds and uploads the plan and is not timed
-                if (hipEventRecord(e0, st) != hipSuccess) rs = TDEC_EDEVICE;
-                tdec_status s =
-                    cb_decode_batch(ctx, (int32_t)n, desc.data(), d_llr, &p, nullptr, d_ok, d_it, st);
-                if (s == TDEC_ENOMEM) break;  // this shape does not fit the workspace
-                if (s != TDEC_OK) rs = s;
-                if (rs == TDEC_OK && (hipEventRecord(e1, st) != hipSuccess ||
-                                      hipEventSynchronize(e1) != hipSuccess ||
-                                      hipEventElapsedTime(&t, e0, e1) != hipSuccess))
-                    rs = TDEC_EDEVICE;
-                if (rep == 0) continue;
-                ms = (rep == 1 || t < ms) ? t : ms;
+            // one untimed launch builds and uploads the plan; then three
+            // launches between one pair of events (host clock as a fallback
+            // should the events report nothing)
+            tdec_status s =
+                cb_decode_batch(ctx, (int32_t)n, desc.data(), d_llr, &p, nullptr, d_ok, d_it, st);
+            if (s == TDEC_ENOMEM) continue;  // this shape does not fit the workspace
+            if (s != TDEC_OK || hipStreamSynchronize(st) != hipSuccess) {
+                rs = s != TDEC_OK ? s : TDEC_EDEVICE;
+                break;
             }
+            float ms = 0.f;
+            const auto h0 = std::chrono::steady_clock::now();
+            bool ev = hipEventRecord(e0, st) == hipSuccess;
+            for (int rep = 0; rep < 3 && rs == TDEC_OK; ++rep)
+                rs = cb_decode_batch(ctx, (int32_t)n, desc.data(), d_llr, &p, nullptr, d_ok, d_it, st);
+            if (rs != TDEC_OK) break;
+            ev = ev && hipEventRecord(e1, st) == hipSuccess;
+            if (hipStreamSynchronize(st) != hipSuccess) {
+                rs = TDEC_EDEVICE;
+                break;
+            }
+            const auto h1 = std::chrono::steady_clock::now();
+            if (!(ev && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.f))
+                ms = std::chrono::duration<float, std::milli>(h1 - h0).count();
+            ms /= 3.f;
             if (rs != TDEC_OK || ms <= 0.f) continue;
             const float ns_kbit = ms * 1e6f / ((float)n * (float)K / 1000.f);
             if (best < 0.f || ns_kbit < best) {

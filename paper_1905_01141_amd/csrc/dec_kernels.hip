@@ -782,6 +782,7 @@ struct TbRes {
     uint8_t cb_ok[64], cb_iters[64];
 };
 
+// a * b mod g over GF(2), 24-bit operands
 __device__ uint32_t gf_mulmod(uint32_t a, uint32_t b, uint32_t poly)
 {
     uint32_t r = 0;
@@ -793,25 +794,34 @@ __device__ uint32_t gf_mulmod(uint32_t a, uint32_t b, uint32_t poly)
     return r;
 }
 
-__device__ uint32_t gf_xpow(uint64_t n, uint32_t poly)
+// `n` bits (1..32) of a block's hard-decision words starting at bit `pos`,
+// left-aligned; reads one word past the last full one (every block keeps a
+// spare word for this).
+__device__ __forceinline__ uint32_t take_bits(const uint32_t *h, int pos, int n)
 {
-    uint32_t res = 1, base = 2;
-    while (n) {
-        if (n & 1) res = gf_mulmod(res, base, poly);
-        base = gf_mulmod(base, base, poly);
-        n >>= 1;
-    }
-    return res;
+    const int i = pos >> 5, sh = pos & 31;
+    uint32_t x = h[i] << sh;
+    if (sh) x |= h[i + 1] >> (32 - sh);
+    return n >= 32 ? x : (x & ~(0xFFFFFFFFu >> n));
 }
 
+// One work group per transport block.  The B = tbs + 24 reassembled bits
+// (every block's bits F..K-L-1, in block order) are gathered into LDS words;
+// the CRC24A remainder of that message, zero-padded to whole words, is the
+// XOR of each thread's word-chunk remainder times x^(32 * words after the
+// chunk) (table X32).  Padding multiplies the remainder by a power of x,
+// which is invertible modulo the generator (its constant term is 1), so the
+// padded remainder is zero exactly when the message's is.
 __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, const uint32_t *hard,
                                                           const uint8_t *crc_ok,
                                                           const uint8_t *iters, uint8_t *bits,
-                                                          TbRes *res)
+                                                          TbRes *res, const uint32_t *x32)
 {
-    __shared__ int64_t s_hoff[64];  // hard word offset of each block
-    __shared__ int32_t s_start[65]; // first TB bit of each block's payload
+    extern __shared__ uint32_t msg[];
+    __shared__ int64_t s_hoff[64];   // hard word offset of each block
+    __shared__ int32_t s_start[65];  // first message bit of each block
     __shared__ int32_t s_F[64];
+    __shared__ uint32_t s_t8[256];   // byte table of CRC24A
     __shared__ uint32_t s_crc;
     const TbItem tb = items[blockIdx.x];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -827,64 +837,92 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, c
             h += hard_words(K);
             st += K - F - tb.L;
         }
-        s_start[tb.C] = st;
+        s_start[tb.C] = st;  // = B
         s_crc = 0;
     }
+    {
+        // byte step of the MSB-first CRC: the remainder of t * x^24 after 8 shifts
+        uint32_t r = (uint32_t)tid << 16;
+        for (int k = 0; k < 8; ++k) r = ((r << 1) & 0xFFFFFFu) ^ ((r & 0x800000u) ? kPoly24A : 0u);
+        if (tid < 256) s_t8[tid] = r;
+    }
     __syncthreads();
-    auto bit_at = [&](int b) -> uint32_t {
-        int r = 0;
-        while (r + 1 < tb.C && s_start[r + 1] <= b) ++r;
-        const int pos = s_F[r] + (b - s_start[r]);
-        return (hard[s_hoff[r] + (pos >> 5)] >> (31 - (pos & 31))) & 1u;
-    };
-    // payload bytes
+    const int B = tb.B;
+    const int nwd = (B + 31) >> 5;
+    for (int w = tid; w < nwd; w += nthr) {
+        int b = w << 5;
+        // block holding message bit b: the last r with s_start[r] <= b
+        int lo = 0, hi = tb.C - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        int r = lo, got = 0;
+        uint32_t v = 0;
+        while (got < 32 && b < B) {
+            const int n = min(32 - got, s_start[r + 1] - b);
+            const uint32_t c = take_bits(hard + s_hoff[r], s_F[r] + (b - s_start[r]), n);
+            v |= c >> got;
+            got += n;
+            b += n;
+            ++r;
+        }
+        msg[w] = v;
+    }
+    __syncthreads();
+    // payload bytes (the first tbs bits)
     if (tb.bits_off >= 0 && bits) {
         const int nbytes = (tb.tbs + 7) >> 3;
         for (int q = tid; q < nbytes; q += nthr) {
-            uint32_t v = 0;
-            for (int k = 0; k < 8; ++k) {
-                const int b = 8 * q + k;
-                v = (v << 1) | (b < tb.tbs ? bit_at(b) : 0u);
-            }
+            uint32_t v = (msg[q >> 2] >> (24 - 8 * (q & 3))) & 0xFFu;
+            const int keep = tb.tbs - 8 * q;  // payload bits in this byte
+            if (keep < 8) v &= 0xFFu << (8 - keep);
             bits[tb.bits_off + q] = (uint8_t)v;
         }
     }
-    // CRC24A over the B reassembled bits: per-thread chunks, shifted into place
-    const int chunk = (tb.B + nthr - 1) / nthr;
-    const int b0 = tid * chunk, b1 = min(tb.B, b0 + chunk);
-    if (b0 < b1) {
+    // CRC24A over the zero-padded message: word chunks per thread
+    const int cw = (nwd + nthr - 1) / nthr;
+    const int w0 = tid * cw, w1 = min(nwd, w0 + cw);
+    if (w0 < w1) {
         uint32_t r = 0;
-        for (int b = b0; b < b1; ++b) {
-            const uint32_t top = ((r >> 23) ^ bit_at(b)) & 1u;
-            r = ((r << 1) & 0xFFFFFFu) ^ (top ? kPoly24A : 0u);
+        for (int w = w0; w < w1; ++w) {
+            const uint32_t v = msg[w];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t byte = (v >> (24 - 8 * k)) & 0xFFu;
+                r = ((r << 8) & 0xFFFFFFu) ^ s_t8[((r >> 16) ^ byte) & 0xFFu];
+            }
         }
-        if (r) r = gf_mulmod(r, gf_xpow((uint64_t)(tb.B - b1), kPoly24A), kPoly24A);
+        if (r) r = gf_mulmod(r, x32[nwd - w1], kPoly24A);
         if (r) atomicXor(&s_crc, r);
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < 64) {
         TbRes &o = res[tb.res_idx];
-        int mx = 0;
-        for (int r = 0; r < 64; ++r) {
-            o.cb_ok[r] = r < tb.C ? crc_ok[tb.cb_idx0 + r] : 0;
-            o.cb_iters[r] = r < tb.C ? iters[tb.cb_idx0 + r] : 0;
-            if (r < tb.C) mx = max(mx, (int)iters[tb.cb_idx0 + r]);
+        const int r = tid;
+        o.cb_ok[r] = r < tb.C ? crc_ok[tb.cb_idx0 + r] : 0;
+        o.cb_iters[r] = r < tb.C ? iters[tb.cb_idx0 + r] : 0;
+        int mx = r < tb.C ? (int)iters[tb.cb_idx0 + r] : 0;
+        // wave-wide maximum (the 64 threads are one wave)
+        for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+        if (tid == 0) {
+            o.tb_ok = s_crc == 0;
+            o.max_iters_used = mx;
+            o.C = tb.C;
+            o.rsv = 0;
         }
-        o.tb_ok = s_crc == 0;
-        o.max_iters_used = mx;
-        o.C = tb.C;
-        o.rsv = 0;
     }
 }
 
-int launch_tb_assemble(const TbItem *items, int n_tb, const uint32_t *hard, const uint8_t *crc_ok,
-                       const uint8_t *iters, const uint32_t *crc_tab, uint8_t *bits, void *res,
-                       void *stream)
+int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
+                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
+                       uint8_t *bits, void *res, void *stream)
 {
-    (void)crc_tab;
     if (n_tb <= 0) return 0;
-    hipLaunchKernelGGL(tb_assemble_kernel, dim3(n_tb), dim3(256), 0, (hipStream_t)stream, items,
-                       hard, crc_ok, iters, bits, (TbRes *)res);
+    hipLaunchKernelGGL(tb_assemble_kernel, dim3(n_tb), dim3(256), (size_t)max_words * 4,
+                       (hipStream_t)stream, items, hard, crc_ok, iters, bits, (TbRes *)res,
+                       crc_tab + 2 * kCrcTabN);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

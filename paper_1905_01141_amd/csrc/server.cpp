@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "tdec.h"
+#include "tdec_internal.h"
 #include "tdec_server.h"
 
 namespace {
@@ -113,6 +114,7 @@ struct tdec_server {
     hipStream_t copy_st = nullptr, dec_st = nullptr;
     hipEvent_t copy_ev[kCopyEvents] = {};
     hipEvent_t done_ev = nullptr;
+    hipEvent_t ev_s = nullptr, ev_m = nullptr;  // around the decode kernel (timing)
     uint64_t copy_seq = 0;  // events recorded so far
     uint8_t *d_bits = nullptr, *h_bits_stage = nullptr;
     size_t bits_cap = 0;
@@ -133,6 +135,7 @@ struct tdec_server {
     // statistics (under mu)
     tdec_serve_stats st{};
     int64_t batch_tbs_sum = 0, batch_cbs_sum = 0;
+    int64_t pre_sum = 0, coding_sum = 0, post_sum = 0;  // per-launch delays (ns)
     std::vector<int64_t> lat;
     bool stop = false;
     std::thread worker;
@@ -160,8 +163,11 @@ bool seg_of(int32_t tbs, Segm *o)
     return true;
 }
 
-// Run one launch over `b` on the device; fills per-block results.
-void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res)
+// Run one launch over `b` on the device; fills per-block results and the
+// launch's pre-processing (host: batch, plan, enqueue), coding (decode
+// kernel) and post-processing (assembly, copies back, copy-out) delays.
+void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
+                int64_t t0, int64_t lat[3])
 {
     const int n = (int)b.size();
     std::vector<int32_t> tbs(n);
@@ -176,14 +182,21 @@ void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server
         seq = std::max(seq, b[i].copy_seq);
     }
     bool ok = hipStreamWaitEvent(s->dec_st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
-    ok = ok && tb_decode_batch(s->ctx, n, tbs.data(), lo.data(), bo.data(), s->d_arena,
-                               &s->cfg.params, s->d_bits, s->d_res, s->dec_st) == TDEC_OK;
+    ok = ok && tdec::tb_decode_batch_timed(s->ctx, n, tbs.data(), lo.data(), bo.data(), s->d_arena,
+                                           &s->cfg.params, s->d_bits, s->d_res, s->dec_st,
+                                           s->ev_s, s->ev_m) == TDEC_OK;
+    const int64_t t_enq = mono_ns();
     ok = ok && hipMemcpyAsync(s->h_bits_stage, s->d_bits, (size_t)bytes, hipMemcpyDeviceToHost,
                               s->dec_st) == hipSuccess;
     ok = ok && hipMemcpyAsync(s->h_res, s->d_res, sizeof(tdec_tb_result) * (size_t)n,
                               hipMemcpyDeviceToHost, s->dec_st) == hipSuccess;
     ok = ok && hipEventRecord(s->done_ev, s->dec_st) == hipSuccess;
     ok = ok && hipEventSynchronize(s->done_ev) == hipSuccess;
+    float coding_ms = 0.f, post_ms = 0.f;
+    if (ok) {
+        (void)hipEventElapsedTime(&coding_ms, s->ev_s, s->ev_m);
+        (void)hipEventElapsedTime(&post_ms, s->ev_m, s->done_ev);
+    }
     for (int i = 0; i < n; ++i) {
         tdec_server_result &r = res[i];
         if (!ok) {
@@ -195,6 +208,9 @@ void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server
         r.tb_ok = s->h_res[i].tb_ok;
         r.max_iters_used = s->h_res[i].max_iters_used;
     }
+    lat[0] = t_enq - t0;
+    lat[1] = (int64_t)(coding_ms * 1e6f);
+    lat[2] = (int64_t)(post_ms * 1e6f);
 }
 
 void run_model(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
@@ -247,11 +263,13 @@ void worker_main(tdec_server *s)
             s->run_end_pred = t0 + s->dur(kb);
         }
         res.assign(b.size(), tdec_server_result{});
+        int64_t lat3[3] = {0, 0, 0};
         if (s->model)
             run_model(s, b, res, t0);
         else
-            run_device(s, b, res);
+            run_device(s, b, res, t0, lat3);
         const int64_t t1 = mono_ns();
+        if (s->model) lat3[1] = t1 - t0;
         {
             std::lock_guard<std::mutex> lk(s->mu);
             for (size_t i = 0; i < b.size(); ++i) {
@@ -278,8 +296,13 @@ void worker_main(tdec_server *s)
             s->batch_tbs_sum += (int64_t)b.size();
             s->batch_cbs_sum += cbs;
             s->st.busy_ns += t1 - t0;
+            s->pre_sum += lat3[0];
+            s->coding_sum += lat3[1];
+            s->post_sum += lat3[2];
             // service model update: the regime the prediction was in learns
-            const double d = (double)(t1 - t0);
+            // one observation moves the model by at most a factor of 4 (a
+            // cold first launch must not stall admission for long)
+            const double d = std::min((double)(t1 - t0), 4.0 * (double)s->dur(kb));
             if (s->m_npk * (double)kb / 1000.0 < s->m_lat)
                 s->m_lat = 0.8 * s->m_lat + 0.2 * d;
             else
@@ -302,6 +325,8 @@ void free_device(tdec_server *s)
     for (auto &e : s->copy_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+    if (s->ev_s) (void)hipEventDestroy(s->ev_s);
+    if (s->ev_m) (void)hipEventDestroy(s->ev_m);
     if (s->copy_st) (void)hipStreamDestroy(s->copy_st);
     if (s->dec_st) (void)hipStreamDestroy(s->dec_st);
 }
@@ -355,7 +380,8 @@ tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_s
                             hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&s->dec_st, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) == hipSuccess;
+              hipEventCreate(&s->done_ev) == hipSuccess && hipEventCreate(&s->ev_s) == hipSuccess &&
+              hipEventCreate(&s->ev_m) == hipSuccess;
     for (auto &e : s->copy_ev)
         ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     // every copy event starts recorded, so that a wait on it never blocks on nothing
@@ -389,9 +415,9 @@ tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
     return TDEC_OK;
 }
 
-int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
+static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
                            const int16_t *const *h_llr, uint8_t *const *h_bits,
-                           int64_t t_arrive_ns, int32_t *status)
+                           int64_t t_arrive_ns, int32_t *status, bool dev)
 {
     if (!s || n < 0) return TDEC_EINVAL;
     if (n == 0) return 0;
@@ -399,6 +425,9 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
     if (!s->model && hipSetDevice(s->device) != hipSuccess) return TDEC_EDEVICE;
     int32_t admitted = 0;
     bool copied = false;
+    tdec::GatherArgs ga;
+    ga.n = 0;
+    ga.dst_base = s->d_arena;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const int64_t now = mono_ns();
@@ -434,7 +463,11 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 } else {
                     pred = start + s->queued_dur_ns + s->dur(g.kbits);
                 }
-                if (pred > limit) {
+                // an idle server always admits: the prediction only judges
+                // the wait behind other work (and an overestimating model
+                // must still see launches to correct itself)
+                const bool busy = s->run_end_pred != 0 || !s->queue.empty();
+                if (busy && pred > limit) {
                     why = TDEC_SERVE_REJ_DEADLINE;
                     s->arena.release(off, bytes);
                 }
@@ -453,9 +486,21 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 s->done.push_back(r);
                 continue;
             }
-            if (!s->model &&
-                hipMemcpyAsync(s->d_arena + off / 2, h_llr[i], (size_t)bytes,
-                               hipMemcpyHostToDevice, s->copy_st) != hipSuccess) {
+            bool cp_ok = true;
+            if (!s->model && !dev) {
+                cp_ok = hipMemcpyAsync(s->d_arena + off / 2, h_llr[i], (size_t)bytes,
+                                       hipMemcpyHostToDevice, s->copy_st) == hipSuccess;
+            } else if (!s->model) {
+                // device sources: batched into gather launches
+                ga.it[ga.n].src = h_llr[i];
+                ga.it[ga.n].dst_blk = (uint32_t)(off / 256);
+                ga.it[ga.n].n = (uint32_t)(bytes / 2);
+                if (++ga.n == tdec::kGatherMax) {
+                    cp_ok = tdec::launch_gather(ga, s->copy_st) == 0;
+                    ga.n = 0;
+                }
+            }
+            if (!cp_ok) {
                 s->arena.release(off, bytes);
                 if (status) status[i] = TDEC_SERVE_ERROR;
                 tdec_server_result r{};
@@ -468,7 +513,7 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 continue;
             }
             copied = !s->model;
-            Pending p;
+            Pending p{};
             p.tag = tags[i];
             p.tbs = tbs[i];
             p.C = g.C;
@@ -478,15 +523,16 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
             p.h_bits = h_bits ? h_bits[i] : nullptr;
             p.t_arrive = t_arrive_ns;
             p.copy_seq = s->copy_seq + 1;
+            p.pred_dur = s->cfg.mode == TDEC_SERVE_PER_TB ? s->dur(g.kbits) : 0;
             s->queue.push_back(p);
             s->queued_kbits += g.kbits;
             s->queued_cbs += g.C;
-            p.pred_dur = s->cfg.mode == TDEC_SERVE_PER_TB ? s->dur(g.kbits) : 0;
             s->queued_dur_ns += p.pred_dur;
             ++s->inflight;
             ++s->st.admitted;
             ++admitted;
         }
+        if (ga.n && tdec::launch_gather(ga, s->copy_st) != 0) return TDEC_EDEVICE;
         if (copied) {
             // record after this call's copies; the worker waits for it before
             // it launches any of these blocks
@@ -498,6 +544,20 @@ int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, cons
     s->cv_work.notify_one();
     s->cv_done.notify_all();
     return admitted;
+}
+
+int32_t tdec_server_submit(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
+                           const int16_t *const *h_llr, uint8_t *const *h_bits,
+                           int64_t t_arrive_ns, int32_t *status)
+{
+    return submit_impl(s, n, tags, tbs, h_llr, h_bits, t_arrive_ns, status, false);
+}
+
+int32_t tdec_server_submit_dev(tdec_server *s, int32_t n, const uint64_t *tags,
+                               const int32_t *tbs, const int16_t *const *d_llr,
+                               uint8_t *const *h_bits, int64_t t_arrive_ns, int32_t *status)
+{
+    return submit_impl(s, n, tags, tbs, d_llr, h_bits, t_arrive_ns, status, true);
 }
 
 int32_t tdec_server_poll(tdec_server *s, tdec_server_result *out, int32_t max, int32_t wait_us)
@@ -538,6 +598,11 @@ tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out)
         out->slots_peak_bytes = s->arena.peak();
         out->mean_batch_tbs = s->st.batches ? (double)s->batch_tbs_sum / s->st.batches : 0.0;
         out->mean_batch_cbs = s->st.batches ? (double)s->batch_cbs_sum / s->st.batches : 0.0;
+        if (s->st.batches) {
+            out->mean_pre_ns = s->pre_sum / s->st.batches;
+            out->mean_coding_ns = s->coding_sum / s->st.batches;
+            out->mean_post_ns = s->post_sum / s->st.batches;
+        }
     }
     if (!v.empty()) {
         std::sort(v.begin(), v.end());
@@ -566,6 +631,7 @@ void tdec_server_reset_stats(tdec_server *s)
     s->st = tdec_serve_stats{};
     s->lat.clear();
     s->batch_tbs_sum = s->batch_cbs_sum = 0;
+    s->pre_sum = s->coding_sum = s->post_sum = 0;
     s->arena.reset_peak();
 }
 

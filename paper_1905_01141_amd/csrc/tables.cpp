@@ -106,4 +106,17 @@ void crc_shift_table(uint32_t poly, uint32_t *out, int n)
     }
 }
 
+void crc_x32_table(uint32_t poly, uint32_t *out, int n)
+{
+    // x^(32(j+1)) = x^32 * x^(32j) mod g: 32 reduced shifts per entry
+    uint32_t v = 1;
+    for (int j = 0; j < n; ++j) {
+        out[j] = v;
+        for (int k = 0; k < 32; ++k) {
+            v <<= 1;
+            if (v & 0x1000000u) v = (v ^ poly) & 0xFFFFFFu;
+        }
+    }
+}
+
 }  // namespace tdec

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tdec.h"
+
 namespace tdec {
 
 constexpr int kNumK = 188;
@@ -12,6 +14,10 @@ constexpr int kKmax = 6144;
 constexpr int kLlrMax = 2047;
 // x^n mod g for n = 0 .. kCrcTabN-1 (covers every shift a code block needs)
 constexpr int kCrcTabN = kKmax + 32;
+// x^(32 j) mod g24A for j = 0 .. kX32N-1 (transport blocks of up to 64 blocks)
+constexpr int kX32N = 64 * kKmax / 32 + 2;
+// layout of the CRC table in device memory: [x^m mod g24A][x^m mod g24B][x^(32j) mod g24A]
+constexpr int kCrcTabWords = 2 * kCrcTabN + kX32N;
 constexpr uint32_t kPoly24A = 0x864CFBu;  // D^24+D^23+D^18+D^17+D^14+D^11+D^10+D^7+D^6+D^5+D^4+D^3+D+1
 constexpr uint32_t kPoly24B = 0x800063u;  // D^24+D^23+D^6+D^5+D+1
 constexpr int kMaxSlotsPerWg = 64;        // code blocks per work group
@@ -24,6 +30,7 @@ int32_t k_of_index(int i);          // size of table entry i
 void qpp_coeffs(int i, int32_t *f1, int32_t *f2);
 int segment(int32_t tbs, int32_t seg[8]);  // B C L K+ K- C+ C- F; 0 ok, -1 range
 void crc_shift_table(uint32_t poly, uint32_t *out, int n);  // out[m] = x^m mod g
+void crc_x32_table(uint32_t poly, uint32_t *out, int n);    // out[j] = x^(32 j) mod g
 
 // One work item of the decode kernel: `ncb` code blocks of the same size K,
 // each cut into `nw` windows of W steps; lane l < ncb*nw of the work group
@@ -101,12 +108,36 @@ struct EncCb {
     int8_t rsv;
 };
 
+// Device-to-device staging of the serving loop: up to kGatherMax copies per
+// launch, passed by value (kernel arguments stay under 4 KB).
+constexpr int kGatherMax = 200;
+struct GatherItem {
+    const int16_t *src;  // caller's device LLRs
+    uint32_t dst_blk;    // destination offset in 256-byte units from dst_base
+    uint32_t n;          // int16 elements
+};
+struct GatherArgs {
+    int32_t n;
+    int16_t *dst_base;
+    GatherItem it[kGatherMax];
+};
+int launch_gather(const GatherArgs &g, void *stream);
+
+// tb_decode_batch that also records ev_start (hipEvent_t, may be null) just
+// before the decode kernel and ev_mid between it and the assembly kernel.
+tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                  const int64_t *llr_off, const int64_t *bits_off,
+                                  const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
+                                  tdec_tb_result *d_res, void *stream, void *ev_start,
+                                  void *ev_mid);
+
 // Launchers (dec_kernels.hip / enc_kernels.hip).
 const void *decode_kernel_address();
 int launch_decode(const DecArgs &a, int grid, int wg_threads, int lds_bytes, void *stream);
-int launch_tb_assemble(const TbItem *items, int n_tb, const uint32_t *hard, const uint8_t *crc_ok,
-                       const uint8_t *iters, const uint32_t *crc_tab, uint8_t *bits, void *res,
-                       void *stream);
+// max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
+int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
+                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
+                       uint8_t *bits, void *res, void *stream);
 int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
                   const uint32_t *crc_tab, void *stream);
 int launch_tb_crc_attach(const uint8_t *payload, int32_t tbs, uint8_t *stream_bits,

@@ -73,6 +73,8 @@ def check_cb_parity(dev, cbs, mod, esn0, p, cfg, stream=0, tag=""):
     (6144, 0, O.CRC24B, 32, 0, 0, 6),
     (5824, 0, O.CRC24B, 1, 0, 0, 2),
     (3136, 15, O.CRC24B, 14, 1, 1, 8),
+    (6144, 0, O.CRC24B, 96, 1, 1, 6),    # 256-thread work groups (more than 64 windows)
+    (1024, 0, O.CRC24B, 128, 1, 0, 4),   # 128 windows of 8 steps
 ])
 def test_cb_parity_noisy(dev, K, F, crc, nw, win_init, es, iters):
     cbs = [(K, F, crc)] * 6

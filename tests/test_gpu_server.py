@@ -28,18 +28,20 @@ def dev():
     return T, T.Decoder(0), torch
 
 
-def run_server(dev, mode, tbs_list, llr, lo, p, groups):
+def run_server(dev, mode, tbs_list, llr, lo, p, groups, device=False):
     T, D, torch = dev
     pinned = torch.empty(llr.size, dtype=torch.int16, pin_memory=True)
     pinned.numpy()[:] = llr
-    base = pinned.data_ptr()
+    src = pinned.cuda() if device else pinned
+    torch.cuda.synchronize()
+    base = src.data_ptr()
     out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
     srv = T.Server(D, T.server_cfg(p, deadline_us=10_000_000, mode=mode))
     try:
         idx = np.array_split(np.arange(len(tbs_list)), groups)
         for g in idx:
             srv.submit(g.tolist(), [tbs_list[i] for i in g], [base + 2 * int(lo[i]) for i in g],
-                       [out[i].ctypes.data for i in g])
+                       [out[i].ctypes.data for i in g], device=device)
             time.sleep(0.0005)
         srv.drain(60000)
         res, t0 = [], time.monotonic()
@@ -51,19 +53,20 @@ def run_server(dev, mode, tbs_list, llr, lo, p, groups):
     return out, {r["tag"]: r for r in res}, st
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_server_matches_oracle(dev, mode):
+@pytest.mark.parametrize("mode,device", [(0, False), (1, False), (0, True)])
+def test_server_matches_oracle(dev, mode, device):
     T = dev[0]
     g = wl.rng(7, 1)
     tbs_list = [int(x) for x in wl.tbs_log_uniform(g, 10)] + [40, 6120, 6121, 20000]
     tbs_list = [min(t, 30000) for t in tbs_list]
     esn0 = np.linspace(0.0, 5.0, len(tbs_list))
-    say(f"[server] mode={mode} tbs={tbs_list}")
+    say(f"[server] mode={mode} device={device} tbs={tbs_list}")
     llr, pays, lo, bo = tb_batch(tbs_list, "16qam", esn0, 7)
-    out, res, st = run_server(dev, mode, tbs_list, llr, lo, T.params(6, 1, 1, 0), 3)
+    out, res, st = run_server(dev, mode, tbs_list, llr, lo, T.params(6, 1, 1, 0), 3, device)
     assert st["completed"] == len(tbs_list) and st["rej_budget"] == 0
     if mode == 1:
         assert st["batches"] == len(tbs_list)
+    assert st["mean_coding_ns"] > 0 and st["mean_pre_ns"] > 0
     p = O.params(6, 1, 1, 0)
     for i, tbs in enumerate(tbs_list):
         ob, ores = O.tb_decode(llr[lo[i]:lo[i] + O.tb_llr_count(tbs)], tbs, p)
