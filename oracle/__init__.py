@@ -91,6 +91,8 @@ def lib():
         L.or_cb_decode_batch.argtypes = [ct.c_int32, ct.c_void_p, ct.c_void_p, P(Params),
                                          ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.or_tb_decode.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p, P(TbResult)]
+        L.or_win_len.argtypes = [ct.c_int32, ct.c_int32]
+        L.or_win_len.restype = ct.c_int32
         L.or_tb_decode_w.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p,
                                      ct.c_void_p, P(TbResult)]
         _lib = L
@@ -242,6 +244,11 @@ def cb_decode_batch(descs, llr, p: Params, n_bits_bytes: int):
                                 _ptr(bits), _ptr(ok), _ptr(it)):
         raise ValueError("bad batch arguments")
     return bits[:n_bits_bytes], ok[:n], it[:n]
+
+
+def win_len(K: int, nw: int) -> int:
+    """Length of all but the last window (0: the count leaves a window empty)."""
+    return int(lib().or_win_len(int(K), int(nw)))
 
 
 def tb_decode(llr, tbs: int, p: Params):

@@ -325,23 +325,37 @@ static void or_tail_beta(const int64_t tail[6], int64_t out[8])
     memcpy(out, bn, sizeof bn);
 }
 
+/* Window partition of a K-step trellis into nw windows of W = 8 ceil(K / (8 nw))
+ * steps: window w covers steps [w W, min(K, (w+1) W)), so only the last one
+ * may be shorter (when 8 nw divides K every window has K / nw steps).  One
+ * window is the whole trellis.  Returns W, or 0 when some window would be
+ * empty. */
+int32_t or_win_len(int32_t K, int32_t nw)
+{
+    if (K < 1 || nw < 1) return 0;
+    if (nw == 1) return K;
+    const int32_t W = 8 * ((K + 8 * nw - 1) / (8 * nw));
+    if ((int64_t)(nw - 1) * W >= K) return 0;
+    return W;
+}
+
 int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64_t tail[6],
                    int32_t nw, const int64_t *a_in, const int64_t *b_in,
                    int64_t *a_out, int64_t *b_out, int64_t *le)
 {
-    if (K < 1 || nw < 1 || K % nw) return -1;
     if (nw > 1 && (!a_in || !b_in)) return -1;
-    const int32_t W = K / nw;
+    const int32_t W = or_win_len(K, nw);
+    if (!W) return -1;
     int64_t(*A)[8] = malloc(sizeof(int64_t[8]) * (W + 1));
     int64_t(*Bt)[8] = malloc(sizeof(int64_t[8]) * (W + 1));
     int64_t btail[8];
     or_tail_beta(tail, btail);
     for (int32_t w = 0; w < nw; ++w) {
-        const int32_t lo = w * W;
+        const int32_t lo = w * W, n = w == nw - 1 ? K - lo : W;
         /* forward recursion */
         for (int s = 0; s < 8; ++s)
             A[0][s] = w == 0 ? (s == 0 ? 0 : OR_NEG) : a_in[w * 8 + s];
-        for (int32_t i = 0; i < W; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             const int32_t k = lo + i;
             int64_t nx[8];
             int have[8] = {0};
@@ -355,10 +369,10 @@ int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64
             memcpy(A[i + 1], nx, sizeof nx);
         }
         if (a_out && w < nw - 1)
-            for (int s = 0; s < 8; ++s) a_out[(w + 1) * 8 + s] = A[W][s];
+            for (int s = 0; s < 8; ++s) a_out[(w + 1) * 8 + s] = A[n][s];
         /* backward recursion */
-        for (int s = 0; s < 8; ++s) Bt[W][s] = w == nw - 1 ? btail[s] : b_in[w * 8 + s];
-        for (int32_t i = W - 1; i >= 0; --i) {
+        for (int s = 0; s < 8; ++s) Bt[n][s] = w == nw - 1 ? btail[s] : b_in[w * 8 + s];
+        for (int32_t i = n - 1; i >= 0; --i) {
             const int32_t k = lo + i;
             for (int s = 0; s < 8; ++s) {
                 int64_t best = 0;
@@ -373,7 +387,7 @@ int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64
         if (b_out && w > 0)
             for (int s = 0; s < 8; ++s) b_out[(w - 1) * 8 + s] = Bt[0][s];
         /* extrinsic */
-        for (int32_t i = 0; i < W; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             const int32_t k = lo + i;
             int64_t m[2] = {0, 0};
             int have[2] = {0, 0};
@@ -431,9 +445,9 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
                      int32_t nw, const int64_t *a_in, const int64_t *b_in,
                      int64_t *a_out, int64_t *b_out, int64_t *le, int64_t *sat)
 {
-    if (K < 1 || nw < 1 || K % nw) return -1;
     if (nw > 1 && (!a_in || !b_in)) return -1;
-    const int32_t W = K / nw;
+    const int32_t W = or_win_len(K, nw);
+    if (!W) return -1;
     int16_t(*A)[8] = malloc(sizeof(int16_t[8]) * (W + 1));
     int16_t(*Bt)[8] = malloc(sizeof(int16_t[8]) * (W + 1));
     int64_t bt64[8];
@@ -446,13 +460,13 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
     for (int32_t k = 0; k < K; ++k)
         if (lsa[k] < -4094 || lsa[k] > 4094 || lp[k] < -2047 || lp[k] > 2047) ++nsat;
     for (int32_t w = 0; w < nw; ++w) {
-        const int32_t lo = w * W;
+        const int32_t lo = w * W, n = w == nw - 1 ? K - lo : W;
         for (int s = 0; s < 8; ++s) {
             if (w == 0) A[0][s] = s == 0 ? 0 : -32768;
             else A[0][s] = or_sat16((int32_t)a_in[w * 8 + s], &clip), nsat += clip;
         }
         if (w > 0) or16_normalise(A[0]);
-        for (int32_t i = 0; i < W; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             const int32_t k = lo + i;
             const int16_t Ls = (int16_t)lsa[k], Lp = (int16_t)lp[k];
             int16_t nx[8];
@@ -481,16 +495,16 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
         }
         if (a_out && w < nw - 1) {
             int16_t t[8];
-            memcpy(t, A[W], sizeof t);
+            memcpy(t, A[n], sizeof t);
             or16_normalise(t);
             for (int s = 0; s < 8; ++s) a_out[(w + 1) * 8 + s] = t[s];
         }
         for (int s = 0; s < 8; ++s) {
-            if (w == nw - 1) Bt[W][s] = btail[s];
-            else Bt[W][s] = or_sat16((int32_t)b_in[w * 8 + s], &clip), nsat += clip;
+            if (w == nw - 1) Bt[n][s] = btail[s];
+            else Bt[n][s] = or_sat16((int32_t)b_in[w * 8 + s], &clip), nsat += clip;
         }
-        if (w < nw - 1) or16_normalise(Bt[W]);
-        for (int32_t i = W - 1; i >= 0; --i) {
+        if (w < nw - 1) or16_normalise(Bt[n]);
+        for (int32_t i = n - 1; i >= 0; --i) {
             const int32_t k = lo + i;
             const int16_t Ls = (int16_t)lsa[k], Lp = (int16_t)lp[k];
             int16_t cand[8][2];
@@ -526,7 +540,7 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
                 int32_t e = ecand[s][0] > ecand[s][1] ? ecand[s][0] : ecand[s][1];
                 if ((int32_t)nb[s] != e) ++nsat;
             }
-            if (or16_norm_step(W - i)) or16_normalise(nb);
+            if (or16_norm_step(n - i)) or16_normalise(nb);
             memcpy(Bt[i], nb, sizeof nb);
         }
         if (b_out && w > 0) {
@@ -561,7 +575,8 @@ static int or_params_ok(const or_params *p, int32_t K)
 {
     if (!p) return 0;
     if (p->max_iters < 1 || p->max_iters > 16) return 0;
-    if (p->n_windows < 1 || K % p->n_windows || K / p->n_windows < 8) return 0;
+    const int32_t W = or_win_len(K, p->n_windows);
+    if (!W || W < 8 || K - (p->n_windows - 1) * W < 8) return 0;
     return 1;
 }
 

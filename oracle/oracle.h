@@ -117,6 +117,10 @@ typedef struct {
  *   a_out, b_out : the values this pass computes at the same boundaries;
  *   le[k]        : extrinsic output.
  * a_in/b_in/a_out/b_out may be NULL when nw == 1.  Returns 0 or -1. */
+/* Window partition: windows of W = 8 ceil(K / (8 nw)) steps (K for one
+ * window), window w covering [w W, min(K, (w+1) W)), so that only the last
+ * may be shorter.  Returns W, or 0 when a window would be empty. */
+int32_t or_win_len(int32_t K, int32_t nw);
 int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64_t tail[6],
                    int32_t nw, const int64_t *a_in, const int64_t *b_in,
                    int64_t *a_out, int64_t *b_out, int64_t *le);

@@ -40,6 +40,7 @@ struct PlanSlot {
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
     int asm_words = 0;  // largest (B + 31) / 32 of the plan's transport blocks
+    int state_slots = 1;  // most blocks of any item
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
@@ -165,7 +166,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     std::vector<DecItem> items;
     std::vector<DecCb> cbl;
     cbl.reserve(reqs.size());
-    int lds = 0;
+    int lds = 0, max_n = 1;
     int64_t stride = 0;
     size_t i = 0;
     while (i < order.size()) {
@@ -199,11 +200,13 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         it.ncb = n;
         items.push_back(it);
         lds = std::max(lds, n * sb);
+        max_n = std::max(max_n, n);
         const int lanes = n * nw;
         const int64_t need = (int64_t)n * K * 8 + (int64_t)(W / kSeg) * lanes * 16 +
                              (int64_t)4 * lanes * 16 + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
+    lds += lds_state_bytes(max_n);
     // persistent grid: as many work groups as can be resident
     int occ = 0;
     const int64_t okey = (int64_t)wg << 32 | (uint32_t)lds;
@@ -243,6 +246,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.grid = grid;
     ps.wg = wg;
     ps.lds = lds;
+    ps.state_slots = max_n;
     ps.stride = stride;
     return TDEC_OK;
 }
@@ -298,6 +302,7 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.max_iters = p->max_iters;
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
+    a.state_slots = ps->state_slots;
     if (launch_decode(a, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
     return TDEC_OK;
 }

@@ -494,11 +494,15 @@ __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, 
 
 __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
 {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ uint32_t s_crc[kMaxSlotsPerWg];
-    __shared__ int s_done[kMaxSlotsPerWg];
-    __shared__ int s_iters[kMaxSlotsPerWg];
-    __shared__ int s_ok[kMaxSlotsPerWg];
+    // dynamic LDS: per-slot state (CRC, done, iterations, ok) for the most
+    // blocks an item of this launch holds, then the blocks' extrinsic arrays
+    extern __shared__ __align__(16) char lds_all[];
+    const int ss = a.state_slots;
+    uint32_t *s_crc = (uint32_t *)lds_all;
+    int *s_done = (int *)(lds_all + 4 * ss);
+    int *s_iters = (int *)(lds_all + 8 * ss);
+    int *s_ok = (int *)(lds_all + 12 * ss);
+    char *lds = lds_all + lds_state_bytes(ss);
 
     const int tid = threadIdx.x, nthr = blockDim.x, half = nthr >> 1;
     const bool bwd_first = tid >= half;       // wave-uniform role

@@ -72,6 +72,7 @@ struct DecArgs {
     // k = w * W + 4 * t4 + j, j = 0..3, relative to the block's slot
     const uint16_t *qtab;
     int32_t max_iters, early_stop, win_init;
+    int32_t state_slots;  // most blocks of any item (size of the per-slot LDS state)
 };
 
 // One transport block for the assembly kernel (after the code blocks are decoded).
@@ -94,6 +95,8 @@ __host__ __device__ inline int64_t hard_words(int32_t K) { return (K + 31) / 32 
 __host__ __device__ inline int32_t epad(int32_t j) { return j + ((j >> 6) << 3); }
 __host__ __device__ inline int32_t lds_e_bytes(int32_t K) { return ((epad(K - 1) + 1) * 2 + 15) & ~15; }
 __host__ __device__ inline int32_t lds_slot_bytes(int32_t K) { return (lds_e_bytes(K) + 63) & ~63; }
+// LDS bytes of the per-slot state that precedes the extrinsic arrays.
+__host__ __device__ inline int32_t lds_state_bytes(int32_t slots) { return (16 * slots + 63) & ~63; }
 // Split point of a window of W steps between its forward-first lane
 // (steps [0, M)) and its backward-first lane (steps [M, W)).
 __host__ __device__ inline int32_t win_split(int32_t W) { return (W / 16) * 8; }

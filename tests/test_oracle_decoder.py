@@ -82,7 +82,8 @@ def test_constituent_bruteforce_extremes(orc):
 # ------------------------------------------------------------------ windows
 
 
-@pytest.mark.parametrize("K,nw", [(64, 4), (192, 8), (6144, 32), (40, 5)])
+@pytest.mark.parametrize("K,nw", [(64, 4), (192, 8), (6144, 32), (40, 5),
+                                  (488, 8), (6144, 31), (200, 3)])  # uneven: last window shorter
 def test_window_boundaries_converge_to_full_length(orc, K, nw):
     rng = np.random.default_rng(K + nw)
     lsa = rng.integers(-4094, 4095, K)
@@ -100,6 +101,26 @@ def test_window_boundaries_converge_to_full_length(orc, K, nw):
     assert np.array_equal(le, full)
     # with zero boundaries the windows really are cut
     assert nw == 1 or not np.array_equal(first, full) or K < 64
+
+
+def test_window_partition_rule(orc):
+    """Windows of W = 8*ceil(K/(8n)) steps, only the last one shorter; the
+    even partition W = K/n whenever 8n divides K; a count that would leave a
+    window empty is refused."""
+    assert orc.win_len(6144, 32) == 192 and orc.win_len(40, 5) == 8
+    assert orc.win_len(488, 8) == 64          # 7 windows of 64, the last of 40
+    assert orc.win_len(6144, 31) == 200       # 30 of 200, the last of 144
+    assert orc.win_len(200, 3) == 72          # 72, 72, 56
+    assert orc.win_len(16, 3) == 0            # 8, 8 and an empty third
+    assert orc.win_len(11, 1) == 11
+    for K in (40, 488, 1000, 6144):
+        for n in range(2, 129):
+            W = orc.win_len(K, n)
+            if W:
+                last = K - (n - 1) * W
+                assert 0 < last <= W and W % 8 == 0
+                if K % (8 * n) == 0:
+                    assert W == K // n and last == W
 
 
 def test_single_window_is_full_length(orc):
@@ -125,7 +146,8 @@ def _adversarial_sets(rng, K):
     yield rng.integers(-60, 61, K), rng.integers(-60, 61, K), rng.integers(-60, 61, 6)
 
 
-@pytest.mark.parametrize("K,nw", [(40, 1), (192, 1), (192, 8), (6144, 32), (1056, 11)])
+@pytest.mark.parametrize("K,nw", [(40, 1), (192, 1), (192, 8), (6144, 32), (1056, 11),
+                                  (488, 8), (6144, 31)])
 def test_int16_twin_equals_exact_constituent(orc, K, nw):
     rng = np.random.default_rng(K * 7 + nw)
     for lsa, lp, tail in _adversarial_sets(rng, K):
@@ -169,7 +191,8 @@ def _encode(orc, K, F, rng, crc):
     return c, orc.turbo_encode_cb(c).reshape(-1)
 
 
-@pytest.mark.parametrize("K,F,nw", [(40, 0, 1), (40, 8, 5), (6144, 0, 32), (3136, 15, 1)])
+@pytest.mark.parametrize("K,F,nw", [(40, 0, 1), (40, 8, 5), (6144, 0, 32), (3136, 15, 1),
+                                    (488, 0, 8)])
 def test_noiseless_round_trip(orc, K, F, nw):
     rng = np.random.default_rng(K + F)
     c, d = _encode(orc, K, F, rng, orc.CRC24B)
@@ -180,7 +203,8 @@ def test_noiseless_round_trip(orc, K, F, nw):
         assert np.array_equal(r["bits"][F:], c[F:])
 
 
-@pytest.mark.parametrize("K,F,nw,win_init", [(104, 0, 1, 0), (512, 9, 4, 1), (6144, 0, 32, 1)])
+@pytest.mark.parametrize("K,F,nw,win_init", [(104, 0, 1, 0), (512, 9, 4, 1), (6144, 0, 32, 1),
+                                             (488, 5, 8, 1)])
 def test_codeword_translation_symmetry(orc, K, F, nw, win_init):
     """Flipping the LLR signs on the 1-positions of any codeword flips the
     decoder's a-posteriori values exactly on that codeword's 1-positions."""
