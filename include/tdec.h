@@ -25,8 +25,10 @@
  *     become a-priori values of the other decoder;
  *   - hard decision: bit = 1 iff the decoder-2 a-posteriori value is > 0;
  *   - windowed decoding: a code block of K bits is cut into n_windows
- *     windows of W = K / n_windows trellis steps that run concurrently; a
- *     window starts its forward (backward) recursion from all-zero metrics,
+ *     windows that run concurrently, each of W = 8*ceil(K/(8*n_windows))
+ *     trellis steps but the last, which takes the rest (W = K/n_windows when
+ *     8*n_windows divides K); a window starts its forward (backward)
+ *     recursion from all-zero metrics,
  *     or, with win_init = 1 and from the second iteration on, from the metric
  *     its left (right) neighbour computed at the shared boundary in the
  *     previous iteration of the same constituent decoder; window 0 always
@@ -76,8 +78,10 @@ typedef struct {
     int32_t max_iters;  /* 1..16 full iterations (decoder 1 + decoder 2) */
     int32_t early_stop; /* 0: run exactly max_iters; 1: stop after the first
                            iteration whose CRC passes (blocks without CRC never stop early) */
-    int32_t n_windows;  /* windows per code block: must divide K with K/n a multiple of 8;
-                           0 = the library's tuned choice for each K (tdec_pick_windows) */
+    int32_t n_windows;  /* windows per code block, 1..128: every window but the last has
+                           W = 8*ceil(K/(8n)) steps (K for n = 1), the last the rest, which
+                           must be non-empty; 0 = the library's choice for each K
+                           (tdec_pick_windows) */
     int32_t win_init;   /* 0: windows start from zero metrics every iteration;
                            1: from the neighbours' previous-iteration boundary metrics */
 } tdec_params;
@@ -214,10 +218,12 @@ void tdec_graph_destroy(tdec_graph *g);
  * K in Ks (host array of n_k table sizes), time a batch of
  * max(1, batch_bits / K) blocks (at most 16384) at max_iters iterations
  * without early stop (the decode time does not depend on the LLR values
- * then, so the batch holds zeros) for every window count n with K % n == 0,
- * K/n a multiple of 8, K/n >= min_W (n = 1 always qualifies) and n <= 128,
- * and keep the fastest per decoded bit.  min_W (>= 8) is the error-rate
- * floor: shorter windows decode worse.  The choice becomes what n_windows = 0 and tdec_pick_windows use on
+ * then, so the batch holds zeros) for the window counts n <= 128 whose
+ * windows come closest above min_W, 1.5, 2, 3 and 4 times min_W, plus n = 1
+ * and the built-in choice, and keep the fastest per decoded bit.  min_W
+ * (>= 8) is the error-rate floor: shorter windows decode worse (the last
+ * window of an uneven partition may be shorter; it starts from the known
+ * termination).  The choice becomes what n_windows = 0 and tdec_pick_windows use on
  * this context; out_nw / out_ns_per_kbit (host, n_k entries, each may be
  * NULL) receive the choice and its time in ns per 1000 code block bits.
  * Runs on `stream` and synchronises it; allocates and frees temporary
@@ -227,6 +233,47 @@ tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t
                           float *out_ns_per_kbit, void *stream);
 /* Forget every tuned choice (back to the built-in rule). */
 void tdec_autotune_reset(tdec_ctx *ctx);
+
+/* ---------------------------------------------------------------- rate matching */
+/* TS 36.212 5.1.4.1: the three coded streams of a block go through the
+ * 32-column sub-block interleaver into a circular buffer of
+ * Kw = 3 * 32 * ceil((K+4)/32) entries; redundancy version rv sends E bits
+ * read circularly over the first Ncb entries from k0 = R (2 ceil(Ncb/8R) rv + 2)
+ * (R = ceil((K+4)/32)), skipping the <NULL> entries (the dummy bits and the
+ * filler bits of streams 0 and 1).  E below the buffer's non-<NULL> count
+ * punctures (the paper's "puncturing procedure", Sec. IV-B), above it repeats.
+ *
+ * The receiver adds each of the E soft values to the block's [3][K+4] int16
+ * soft buffer -- the decoder's input -- at the position its bit was taken
+ * from, saturating at +-32767 and in transmission order.  Keeping that buffer
+ * resident between transmissions is HARQ combining: a block that fails is
+ * decoded again after the next redundancy version has been added (the paper's
+ * retransmission of data that could not be decoded, Sec. V). */
+typedef struct {
+    int64_t e_off;    /* element offset of the block's E values in d_e */
+    int64_t soft_off; /* element offset of its [3][K+4] soft buffer (receiver) or
+                         coded bits (transmitter) */
+    int32_t K;        /* one of the 188 sizes */
+    int16_t F;        /* filler bits, 0 <= F < K */
+    int8_t rv;        /* redundancy version 0..3 */
+    int8_t rsv;
+    int32_t E;        /* values sent, >= 0 */
+    int32_t Ncb;      /* circular buffer length used, 1..Kw; 0 = Kw */
+} tdec_rm_desc;
+
+/* Receiver.  d_e: soft values (device), int8 (e_bytes = 1) or int16
+ * (e_bytes = 2), units of 1/8 nat, positive = 1.  d_soft: int16 soft buffers
+ * (device).  combine = 0 clears each block's buffer first (a first
+ * transmission), 1 adds to it (a retransmission).  The buffers can be passed
+ * to cb_decode_batch / tb_decode as they are (the decoder clamps to +-2047).
+ * EINVAL for a bad descriptor; ENOMEM when the context's table arena is full. */
+tdec_status tdec_derate_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc, const void *d_e,
+                              int32_t e_bytes, int16_t *d_soft, int32_t combine, void *stream);
+
+/* Transmitter: the E bits (one per byte, 0/1) that rv sends, from coded
+ * bits in the [3][K+4] layout of cb_encode_batch (at soft_off). */
+tdec_status tdec_rate_match_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc,
+                                  const uint8_t *d_coded, uint8_t *d_e, void *stream);
 
 /* ---------------------------------------------------------------- encoding */
 /* The rate-1/3 turbo encoder of the paper's encoding function (Sec. IV-B,

@@ -91,6 +91,16 @@ def lib():
         L.or_cb_decode_batch.argtypes = [ct.c_int32, ct.c_void_p, ct.c_void_p, P(Params),
                                          ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.or_tb_decode.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p, P(TbResult)]
+        L.or_subblock_perm.argtypes = [ct.c_void_p]
+        L.or_subblock_perm.restype = None
+        L.or_rm_kw.argtypes = [ct.c_int32]
+        L.or_rm_kw.restype = ct.c_int32
+        L.or_rm_k0.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
+        L.or_rm_k0.restype = ct.c_int32
+        L.or_rate_match.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
+                                    ct.c_int32, ct.c_void_p]
+        L.or_derate_match.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32,
+                                      ct.c_int32, ct.c_int32, ct.c_void_p]
         L.or_win_len.argtypes = [ct.c_int32, ct.c_int32]
         L.or_win_len.restype = ct.c_int32
         L.or_tb_decode_w.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p,
@@ -244,6 +254,39 @@ def cb_decode_batch(descs, llr, p: Params, n_bits_bytes: int):
                                 _ptr(bits), _ptr(ok), _ptr(it)):
         raise ValueError("bad batch arguments")
     return bits[:n_bits_bytes], ok[:n], it[:n]
+
+
+def subblock_perm() -> np.ndarray:
+    out = np.zeros(32, np.int32)
+    lib().or_subblock_perm(_ptr(out))
+    return out
+
+
+def rm_kw(K: int) -> int:
+    return int(lib().or_rm_kw(int(K)))
+
+
+def rm_k0(K: int, ncb: int, rv: int) -> int:
+    return int(lib().or_rm_k0(int(K), int(ncb), int(rv)))
+
+
+def rate_match(d, K: int, F: int, E: int, rv: int, ncb: int | None = None) -> np.ndarray:
+    """The E coded bits that redundancy version rv sends (one per byte)."""
+    d = np.ascontiguousarray(d, np.uint8)
+    e = np.zeros(max(E, 1), np.uint8)
+    if lib().or_rate_match(_ptr(d), K, F, E, rv, rm_kw(K) if ncb is None else ncb, _ptr(e)):
+        raise ValueError("bad rate matching arguments")
+    return e[:E]
+
+
+def derate_match(e, K: int, F: int, rv: int, soft=None, ncb: int | None = None) -> np.ndarray:
+    """Add soft values e into a [3][K+4] int16 soft buffer (new if None)."""
+    e = np.ascontiguousarray(e, np.int16)
+    out = np.zeros(3 * (K + 4), np.int16) if soft is None else np.array(soft, np.int16)
+    if lib().or_derate_match(_ptr(e), e.size, K, F, rv, rm_kw(K) if ncb is None else ncb,
+                             _ptr(out)):
+        raise ValueError("bad de-rate-matching arguments")
+    return out
 
 
 def win_len(K: int, nw: int) -> int:

@@ -734,3 +734,103 @@ int or_tb_decode_w(const int16_t *llr, int32_t tbs, const or_params *p, const in
     free(b);
     return 0;
 }
+
+/* ---- rate matching (TS 36.212 5.1.4.1) --------------------------------- */
+
+/* Inter-column permutation of the 32-column sub-block interleaver. */
+static const int32_t OR_SB_PERM[32] = {0,  16, 8,  24, 4,  20, 12, 28, 2,  18, 10,
+                                       26, 6,  22, 14, 30, 1,  17, 9,  25, 5,  21,
+                                       13, 29, 3,  19, 11, 27, 7,  23, 15, 31};
+
+void or_subblock_perm(int32_t out[32])
+{
+    for (int i = 0; i < 32; ++i) out[i] = OR_SB_PERM[i];
+}
+
+int32_t or_rm_kw(int32_t K) { return 3 * 32 * ((K + 4 + 31) / 32); }
+
+/* The circular buffer w of a code block, as indices into its [3][K+4] array
+ * (stream * (K+4) + k), -1 for a <NULL>: the dummy bits that pad each
+ * stream to R x 32 in front, and the filler positions of streams 0 and 1.
+ * Streams 0 and 1 go through the column-permuted matrix read column by
+ * column; stream 2 through pi(k) = (P[k / R] + 32 (k mod R) + 1) mod (32 R);
+ * w = v0, then v1 and v2 interlaced. */
+static void or_rm_buffer(int32_t K, int32_t F, int32_t *w)
+{
+    const int32_t D = K + 4, R = (D + 31) / 32, KP = 32 * R, ND = KP - D;
+    for (int32_t i = 0; i < 3; ++i)
+        for (int32_t k = 0; k < KP; ++k) {
+            int32_t y; /* position in y (row-major matrix of R x 32) */
+            if (i < 2) {
+                const int32_t col = k / R, row = k % R;
+                y = row * 32 + OR_SB_PERM[col];
+            } else {
+                y = (OR_SB_PERM[k / R] + 32 * (k % R) + 1) % KP;
+            }
+            int32_t idx = -1;
+            if (y >= ND) {
+                const int32_t dk = y - ND; /* index into d(i) */
+                if (!(i < 2 && dk < F)) idx = i * D + dk;
+            }
+            const int32_t pos = i == 0 ? k : KP + 2 * k + (i - 1);
+            w[pos] = idx;
+        }
+}
+
+int32_t or_rm_k0(int32_t K, int32_t Ncb, int32_t rv)
+{
+    const int32_t R = (K + 4 + 31) / 32;
+    return R * (2 * ((Ncb + 8 * R - 1) / (8 * R)) * rv + 2);
+}
+
+/* Bit selection: the E positions (indices into [3][K+4]) that rv transmits,
+ * in transmission order, reading the buffer circularly from k0 over its
+ * first Ncb entries and skipping <NULL>s.  Returns 0, -1 on bad arguments. */
+static int or_rm_select(int32_t K, int32_t F, int32_t E, int32_t rv, int32_t Ncb, int32_t *sel)
+{
+    const int32_t Kw = or_rm_kw(K);
+    if (or_k_index(K) < 0 || F < 0 || F >= K || E < 0 || rv < 0 || rv > 3 || Ncb < 1 ||
+        Ncb > Kw)
+        return -1;
+    int32_t *w = malloc(sizeof(int32_t) * Kw);
+    or_rm_buffer(K, F, w);
+    int32_t nn = 0;
+    for (int32_t j = 0; j < Ncb; ++j) nn += w[j] >= 0;
+    if (nn == 0 && E > 0) {
+        free(w);
+        return -1;
+    }
+    const int32_t k0 = or_rm_k0(K, Ncb, rv);
+    for (int32_t k = 0, j = 0; k < E; ++j) {
+        const int32_t v = w[(k0 + j) % Ncb];
+        if (v >= 0) sel[k++] = v;
+    }
+    free(w);
+    return 0;
+}
+
+int or_rate_match(const uint8_t *d, int32_t K, int32_t F, int32_t E, int32_t rv, int32_t Ncb,
+                  uint8_t *e)
+{
+    int32_t *sel = malloc(sizeof(int32_t) * (E > 0 ? E : 1));
+    const int rc = or_rm_select(K, F, E, rv, Ncb, sel);
+    if (rc == 0)
+        for (int32_t k = 0; k < E; ++k) e[k] = d[sel[k]];
+    free(sel);
+    return rc;
+}
+
+int or_derate_match(const int16_t *e, int32_t E, int32_t K, int32_t F, int32_t rv, int32_t Ncb,
+                    int16_t *soft)
+{
+    int32_t *sel = malloc(sizeof(int32_t) * (E > 0 ? E : 1));
+    const int rc = or_rm_select(K, F, E, rv, Ncb, sel);
+    if (rc == 0)
+        for (int32_t k = 0; k < E; ++k) {
+            /* soft combining in transmission order, saturating at int16 */
+            int32_t v = (int32_t)soft[sel[k]] + e[k];
+            soft[sel[k]] = (int16_t)(v > 32767 ? 32767 : v < -32767 ? -32767 : v);
+        }
+    free(sel);
+    return rc;
+}

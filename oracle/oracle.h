@@ -177,6 +177,26 @@ int or_tb_decode(const int16_t *llr, int32_t tbs, const or_params *p, uint8_t *b
 int or_tb_decode_w(const int16_t *llr, int32_t tbs, const or_params *p, const int32_t *nw,
                    uint8_t *bits, or_tb_result *res);
 
+/* ---- rate matching (TS 36.212 5.1.4.1; the paper's puncturing, Sec. IV-B
+ * "Encoding function", and the soft bits that a retransmission adds to,
+ * Sec. V) ------------------------------------------------------------------ */
+/* The sub-block interleaver's inter-column permutation (32 entries). */
+void or_subblock_perm(int32_t out[32]);
+/* Circular buffer length 3 * 32 * ceil((K+4)/32). */
+int32_t or_rm_kw(int32_t K);
+/* Start of redundancy version rv in a buffer of Ncb entries. */
+int32_t or_rm_k0(int32_t K, int32_t Ncb, int32_t rv);
+/* Transmitter: the E bits (one per byte) that redundancy version rv sends
+ * from a block's [3][K+4] coded bits d (F filler bits); Ncb <= or_rm_kw(K). */
+int or_rate_match(const uint8_t *d, int32_t K, int32_t F, int32_t E, int32_t rv, int32_t Ncb,
+                  uint8_t *e);
+/* Receiver: add the E soft values e (same order) into soft, the block's
+ * [3][K+4] int16 soft buffer (HARQ combining; clear it first for a first
+ * transmission), saturating at +-32767; positions never sent stay as they
+ * are.  Returns 0, or -1 on bad arguments. */
+int or_derate_match(const int16_t *e, int32_t E, int32_t K, int32_t F, int32_t rv, int32_t Ncb,
+                    int16_t *soft);
+
 #ifdef __cplusplus
 }
 #endif

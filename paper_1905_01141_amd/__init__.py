@@ -26,7 +26,7 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_server_drain", "tdec_server_stats", "tdec_server_reset_stats",
            "tdec_server_destroy", "tdec_graph_cb_decode", "tdec_graph_tb_decode",
            "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
-           "tdec_server_submit_dev")
+           "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch")
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -79,6 +79,29 @@ class ServeStats(ct.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class RmDesc(ct.Structure):
+    _fields_ = [("e_off", ct.c_int64), ("soft_off", ct.c_int64), ("K", ct.c_int32),
+                ("F", ct.c_int16), ("rv", ct.c_int8), ("rsv", ct.c_int8), ("E", ct.c_int32),
+                ("Ncb", ct.c_int32)]
+
+
+def rm_kw(K: int) -> int:
+    """Circular buffer length of rate matching: 3 * 32 * ceil((K+4)/32)."""
+    return 3 * 32 * ((int(K) + 4 + 31) // 32)
+
+
+def make_rm_descs(blocks):
+    """blocks: [(K, F, rv, E)] -> (descs, total E, soft elements), laid out
+    back to back."""
+    d = (RmDesc * len(blocks))()
+    eo = so = 0
+    for i, (K, F, rv, E) in enumerate(blocks):
+        d[i].e_off, d[i].soft_off, d[i].K, d[i].F, d[i].rv, d[i].E, d[i].Ncb = eo, so, K, F, rv, E, 0
+        eo += E
+        so += 3 * (K + 4)
+    return d, eo, so
+
+
 # tdec_cb_desc as a numpy record (same layout) for vectorised checks
 DESC_DTYPE = np.dtype([("llr_off", "<i8"), ("bits_off", "<i8"), ("K", "<i4"), ("F", "<i2"),
                        ("crc", "i1"), ("rsv", "i1")])
@@ -122,6 +145,8 @@ def lib():
         L.tdec_autotune.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.tdec_autotune_reset.argtypes = [vp]
         L.tdec_autotune_reset.restype = None
+        L.tdec_derate_batch.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp]
+        L.tdec_rate_match_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         L.tdec_now_ns.restype = i64
         L.tdec_now_ns.argtypes = []
         L.tdec_server_create.argtypes = [vp, P(ServerCfg), P(vp)]
@@ -349,6 +374,33 @@ class Decoder:
 
     def autotune_reset(self):
         lib().tdec_autotune_reset(self._h)
+
+    def derate_batch(self, descs, e, soft, combine: int, stream=None):
+        """e: int8 or int16 CUDA tensor of soft values; soft: int16 CUDA
+        tensor of [3][K+4] soft buffers (HARQ state)."""
+        if len(descs) == 0:
+            return
+        ne = max(int(d.e_off) + int(d.E) for d in descs)
+        ns = max(int(d.soft_off) + 3 * (int(d.K) + 4) for d in descs)
+        eb = {"torch.int8": 1, "torch.int16": 2}.get(str(e.dtype))
+        if eb is None:
+            raise ValueError("e: int8 or int16 tensor expected")
+        _need(e, str(e.dtype)[6:], ne, "e")
+        _need(soft, "int16", ns, "soft")
+        _check("tdec_derate_batch",
+               lib().tdec_derate_batch(self._h, len(descs), ct.cast(descs, ct.c_void_p), _dptr(e),
+                                       eb, _dptr(soft), int(combine), _stream(stream)))
+
+    def rate_match_batch(self, descs, coded, e, stream=None):
+        if len(descs) == 0:
+            return
+        ne = max(int(d.e_off) + int(d.E) for d in descs)
+        nc = max(int(d.soft_off) + 3 * (int(d.K) + 4) for d in descs)
+        _need(coded, "uint8", nc, "coded")
+        _need(e, "uint8", ne, "e")
+        _check("tdec_rate_match_batch",
+               lib().tdec_rate_match_batch(self._h, len(descs), ct.cast(descs, ct.c_void_p),
+                                           _dptr(coded), _dptr(e), _stream(stream)))
 
     def cb_encode_batch(self, descs, payload, coded, stream=None):
         n_llr, n_bits = _desc_extent(descs)

@@ -28,6 +28,7 @@ constexpr int kPlanSlots = 8;
 constexpr size_t kPlanSlotBytes = 8u << 20;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr size_t kQtabEntries = 4u << 20;  // QPP table arena (8 MiB): every size at ~11 window counts
+constexpr size_t kRmEntries = 8u << 20;    // rate matching table arena (16 MiB, >= 450 tables)
 
 struct PlanSlot {
     std::string key;
@@ -41,6 +42,7 @@ struct PlanSlot {
     int n_cb = 0, n_tb = 0;
     int asm_words = 0;  // largest (B + 31) / 32 of the plan's transport blocks
     int state_slots = 1;  // most blocks of any item
+    bool uneven = false;  // some item's last window is shorter
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
@@ -72,6 +74,15 @@ struct tdec_ctx {
     int32_t tuned_nw[kNumK] = {};  // autotuned window count per size (0 = default rule)
     uint32_t tune_gen = 0;         // bumped whenever tuned_nw changes (enters plan keys)
     std::map<int64_t, int> occ_cache;  // resident decode work groups per CU by (threads, LDS)
+    // rate matching rank tables by (K, F, Ncb), appended like the QPP tables
+    struct RmTab {
+        int64_t off;
+        int32_t n_valid, r0[4];
+    };
+    uint16_t *d_rmtab = nullptr;
+    uint16_t *h_rmtab = nullptr;
+    size_t rm_cap = 0, rm_used = 0;
+    std::map<int64_t, RmTab> rm_tabs;
     int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
 };
@@ -104,7 +115,9 @@ int32_t ctx_windows(const tdec_ctx *ctx, int32_t K)
 
 bool windows_ok(int32_t K, int32_t nw)
 {
-    return nw >= 1 && nw <= kMaxWgThreads / 2 && K % nw == 0 && (K / nw) % kSeg == 0;
+    if (nw < 1 || nw > kMaxWgThreads / 2) return false;
+    const int32_t W = win_len(K, nw);
+    return W > 0 && W % kSeg == 0 && (K - (nw - 1) * W) % kSeg == 0;
 }
 
 struct CbReq {
@@ -112,18 +125,59 @@ struct CbReq {
     DecCb cb;
 };
 
+// Rank table of (K, F, Ncb): the [3][K+4] index of every non-<NULL> entry
+// among the first Ncb of the circular buffer, in buffer order, and for each
+// redundancy version the rank at which its reading starts.  Added (upload
+// on `st`) on first use; null when the arena is full.
+const tdec_ctx::RmTab *rm_get(tdec_ctx *ctx, int32_t K, int32_t F, int32_t Ncb, hipStream_t st)
+{
+    const int64_t key = ((int64_t)K << 40) | ((int64_t)F << 20) | Ncb;
+    auto f = ctx->rm_tabs.find(key);
+    if (f != ctx->rm_tabs.end()) return &f->second;
+    std::vector<int32_t> w(3 * 32 * ((K + 4 + 31) / 32));
+    rm_buffer(K, F, w.data());
+    size_t n = 0;
+    for (int32_t j = 0; j < Ncb; ++j) n += w[j] >= 0;
+    const size_t na = (n + 7) & ~(size_t)7;
+    if (n == 0 || ctx->rm_used + na > ctx->rm_cap) return nullptr;
+    tdec_ctx::RmTab t;
+    t.off = (int64_t)ctx->rm_used;
+    t.n_valid = (int32_t)n;
+    uint16_t *h = ctx->h_rmtab + t.off;
+    int32_t r = 0;
+    for (int32_t j = 0; j < Ncb; ++j)
+        if (w[j] >= 0) h[r++] = (uint16_t)w[j];
+    const int32_t R = (K + 4 + 31) / 32;
+    for (int rv = 0; rv < 4; ++rv) {
+        const int32_t k0 = (R * (2 * ((Ncb + 8 * R - 1) / (8 * R)) * rv + 2)) % Ncb;
+        int32_t c = 0;
+        for (int32_t j = 0; j < k0; ++j) c += w[j] >= 0;
+        t.r0[rv] = c % t.n_valid;
+    }
+    if (hipMemcpyAsync(ctx->d_rmtab + t.off, h, n * 2, hipMemcpyHostToDevice, st) != hipSuccess)
+        return nullptr;
+    ctx->rm_used += na;
+    return &(ctx->rm_tabs[key] = t);
+}
+
 // Fill the QPP address table of shape (K, nw) into dst: unit u = t4 * nw + w
 // holds the LDS byte offsets 2 * epad(pi(k)) of steps k = w * W + 4 * t4 + j.
+// Units past K (the pad of a shorter last window) hold 0 and are never read.
 void qtab_fill(int32_t K, int32_t nw, uint16_t *dst)
 {
-    const int32_t W = K / nw;
+    const int32_t W = win_len(K, nw);
     std::vector<int32_t> pi(K);
     tdec_qpp(K, pi.data(), nullptr, nullptr);
-    for (int u = 0; u < K / 4; ++u) {
+    for (int u = 0; u < nw * W / 4; ++u) {
         const int t4 = u / nw, w = u % nw;
-        for (int j = 0; j < 4; ++j) dst[4 * u + j] = (uint16_t)(2 * epad(pi[w * W + 4 * t4 + j]));
+        for (int j = 0; j < 4; ++j) {
+            const int k = w * W + 4 * t4 + j;
+            dst[4 * u + j] = k < K ? (uint16_t)(2 * epad(pi[k])) : 0;
+        }
     }
 }
+
+size_t qtab_entries(int32_t K, int32_t nw) { return (size_t)nw * win_len(K, nw); }
 
 // Element offset of the (K, nw) table in the context's table arena, adding
 // it (upload enqueued on `st`) on first use; -1 when the arena is full.
@@ -132,11 +186,11 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
     const int64_t key = (int64_t)K * 1024 + nw;
     auto f = ctx->qtab_off.find(key);
     if (f != ctx->qtab_off.end()) return f->second;
-    const size_t n = ((size_t)K + 7) & ~(size_t)7;
+    const size_t ne = qtab_entries(K, nw), n = (ne + 7) & ~(size_t)7;
     if (ctx->qtab_used + n > ctx->qtab_cap) return -1;
     const int64_t off = (int64_t)ctx->qtab_used;
     qtab_fill(K, nw, ctx->h_qtab + off);
-    if (hipMemcpyAsync(ctx->d_qtab + off, ctx->h_qtab + off, (size_t)K * 2, hipMemcpyHostToDevice,
+    if (hipMemcpyAsync(ctx->d_qtab + off, ctx->h_qtab + off, ne * 2, hipMemcpyHostToDevice,
                        st) != hipSuccess)
         return -1;
     ctx->qtab_used += n;
@@ -167,11 +221,12 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     std::vector<DecCb> cbl;
     cbl.reserve(reqs.size());
     int lds = 0, max_n = 1;
+    bool uneven = false;
     int64_t stride = 0;
     size_t i = 0;
     while (i < order.size()) {
         const CbReq &r0 = reqs[order[i]];
-        const int K = r0.K, nw = r0.nw, W = K / nw;
+        const int K = r0.K, nw = r0.nw, W = win_len(K, nw);
         const int sb = lds_slot_bytes(K);
         int cap = std::min(half / nw, kMaxSlotsPerWg);
         cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
@@ -199,22 +254,24 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         }
         it.ncb = n;
         items.push_back(it);
+        uneven = uneven || (int64_t)nw * W != K;
         lds = std::max(lds, n * sb);
         max_n = std::max(max_n, n);
         const int lanes = n * nw;
-        const int64_t need = (int64_t)n * K * 8 + (int64_t)(W / kSeg) * lanes * 16 +
+        const int64_t need = (int64_t)lanes * W * 8 + (int64_t)(W / kSeg) * lanes * 16 +
                              (int64_t)4 * lanes * 16 + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
     lds += lds_state_bytes(max_n);
     // persistent grid: as many work groups as can be resident
     int occ = 0;
-    const int64_t okey = (int64_t)wg << 32 | (uint32_t)lds;
+    const int64_t okey = (int64_t)wg << 33 | (int64_t)uneven << 32 | (uint32_t)lds;
     auto oc = ctx->occ_cache.find(okey);
     if (oc != ctx->occ_cache.end()) {
         occ = oc->second;
     } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(), wg, lds) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(uneven), wg,
+                                                         lds) !=
                 hipSuccess ||
             occ < 1)
             occ = std::max(1, kLdsPerCu / std::max(lds, 1));
@@ -247,6 +304,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.wg = wg;
     ps.lds = lds;
     ps.state_slots = max_n;
+    ps.uneven = uneven;
     ps.stride = stride;
     return TDEC_OK;
 }
@@ -303,7 +361,7 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
     a.state_slots = ps->state_slots;
-    if (launch_decode(a, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
+    if (launch_decode(a, ps->uneven, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
     return TDEC_OK;
 }
 
@@ -569,8 +627,9 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
     c->encbuf_bytes = 1 << 20;
     const size_t plan_bytes = (size_t)kPlanSlots * kPlanSlotBytes;
     c->qtab_cap = kQtabEntries;
-    const size_t fixed =
-        tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes + c->qtab_cap * 2;
+    c->rm_cap = kRmEntries;
+    const size_t fixed = tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes +
+                         c->qtab_cap * 2 + c->rm_cap * 2;
     if (c->budget < fixed + (16u << 20)) {
         delete c;
         return TDEC_ENOMEM;
@@ -587,7 +646,9 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
               hipMalloc(&c->d_counter, 64) == hipSuccess &&
               hipMemset(c->d_counter, 0, 64) == hipSuccess &&
               hipMalloc(&c->d_qtab, c->qtab_cap * 2) == hipSuccess &&
-              hipHostMalloc(&c->h_qtab, c->qtab_cap * 2, hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc(&c->h_qtab, c->qtab_cap * 2, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc(&c->d_rmtab, c->rm_cap * 2) == hipSuccess &&
+              hipHostMalloc(&c->h_rmtab, c->rm_cap * 2, hipHostMallocDefault) == hipSuccess;
     for (auto &s : c->slots) {
         ok = ok && hipMalloc(&s.d_buf, kPlanSlotBytes) == hipSuccess &&
              hipHostMalloc(&s.h_buf, kPlanSlotBytes, hipHostMallocDefault) == hipSuccess &&
@@ -607,7 +668,7 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
             const int64_t off = (int64_t)c->qtab_used;
             qtab_fill(K, nw, c->h_qtab + off);
             c->qtab_off[(int64_t)K * 1024 + nw] = off;
-            c->qtab_used += ((size_t)K + 7) & ~(size_t)7;
+            c->qtab_used += (qtab_entries(K, nw) + 7) & ~(size_t)7;
         }
         ok = hipMemcpy(c->d_qtab, c->h_qtab, c->qtab_used * 2, hipMemcpyHostToDevice) == hipSuccess;
     }
@@ -633,6 +694,8 @@ void tdec_destroy(tdec_ctx *c)
     (void)hipFree(c->d_counter);
     if (c->d_qtab) (void)hipFree(c->d_qtab);
     if (c->h_qtab) (void)hipHostFree(c->h_qtab);
+    if (c->d_rmtab) (void)hipFree(c->d_rmtab);
+    if (c->h_rmtab) (void)hipHostFree(c->h_rmtab);
     for (auto &s : c->slots) {
         if (s.d_buf) (void)hipFree(s.d_buf);
         if (s.h_buf) (void)hipHostFree(s.h_buf);
@@ -836,8 +899,20 @@ tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t
         }
         int32_t best_nw = pick_windows(K);
         float best = -1.f;
-        for (int32_t nw = 1; nw <= kMaxWgThreads / 2 && rs == TDEC_OK; ++nw) {
-            if (K % nw || (K / nw) % kSeg || (nw > 1 && K / nw < min_W)) continue;
+        // candidates: full length, the built-in rule, and the counts whose
+        // windows come closest above min_W, 1.5, 2, 3 and 4 times min_W
+        std::vector<int32_t> cand = {1, pick_windows(K)};
+        for (int f2 : {2, 3, 4, 6, 8}) {
+            const int32_t target = std::max(8, min_W * f2 / 2);
+            int32_t nw = std::max(1, K / target);
+            while (nw > 1 && (!windows_ok(K, nw) || win_len(K, nw) < min_W)) --nw;
+            cand.push_back(nw);
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        for (int32_t nw : cand) {
+            if (rs != TDEC_OK) break;
+            if (!windows_ok(K, nw) || (nw > 1 && win_len(K, nw) < min_W)) continue;
             const tdec_params p = {max_iters, 0, nw, 1};
             // one untimed launch builds and uploads the plan; then three
             // launches between one pair of events (host clock as a fallback
@@ -891,6 +966,83 @@ void tdec_autotune_reset(tdec_ctx *ctx)
     if (!ctx) return;
     for (auto &v : ctx->tuned_nw) v = 0;
     ++ctx->tune_gen;
+}
+
+
+// ---------------------------------------------------------------- rate matching
+
+static tdec_status rm_plan(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc, char tag,
+                           hipStream_t st, PlanSlot **out)
+{
+    std::string key(1, tag);
+    key.append((const char *)desc, sizeof(tdec_rm_desc) * (size_t)n);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (!hit) {
+        if (sizeof(RmItem) * (size_t)n > kPlanSlotBytes) return TDEC_ENOMEM;
+        std::vector<char> blob(sizeof(RmItem) * (size_t)n);
+        RmItem *items = (RmItem *)blob.data();
+        for (int32_t i = 0; i < n; ++i) {
+            const tdec_rm_desc &d = desc[i];
+            const int32_t kw = 3 * 32 * ((d.K + 4 + 31) / 32);
+            if (k_index(d.K) < 0 || d.F < 0 || d.F >= d.K || d.rv < 0 || d.rv > 3 || d.E < 0 ||
+                d.Ncb < 0 || d.Ncb > kw || d.e_off < 0 || d.soft_off < 0)
+                return TDEC_EINVAL;
+            const int32_t ncb = d.Ncb ? d.Ncb : kw;
+            const tdec_ctx::RmTab *t = rm_get(ctx, d.K, d.F, ncb, st);
+            if (!t) return TDEC_ENOMEM;
+            items[i].e_off = d.e_off;
+            items[i].soft_off = d.soft_off;
+            items[i].tab_off = t->off;
+            items[i].K = d.K;
+            items[i].E = d.E;
+            items[i].n_valid = t->n_valid;
+            items[i].r0 = t->r0[d.rv];
+        }
+        ps->n_cb = n;
+        ps->off_items = 0;
+        tdec_status s = upload(ctx, ps, key, blob, st);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+    }
+    *out = ps;
+    return TDEC_OK;
+}
+
+tdec_status tdec_derate_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc, const void *d_e,
+                              int32_t e_bytes, int16_t *d_soft, int32_t combine, void *stream)
+{
+    if (!ctx || n < 0 || (e_bytes != 1 && e_bytes != 2) || (combine != 0 && combine != 1))
+        return TDEC_EINVAL;
+    if (n == 0) return TDEC_OK;
+    if (!desc || !d_e || !d_soft) return TDEC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    PlanSlot *ps;
+    tdec_status s = rm_plan(ctx, n, desc, 'D', st, &ps);
+    if (s != TDEC_OK) return s;
+    return launch_derate((const RmItem *)ps->d_buf, n, d_e, e_bytes, d_soft, ctx->d_rmtab, combine,
+                         st)
+               ? TDEC_EDEVICE
+               : TDEC_OK;
+}
+
+tdec_status tdec_rate_match_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc,
+                                  const uint8_t *d_coded, uint8_t *d_e, void *stream)
+{
+    if (!ctx || n < 0) return TDEC_EINVAL;
+    if (n == 0) return TDEC_OK;
+    if (!desc || !d_coded || !d_e) return TDEC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    PlanSlot *ps;
+    tdec_status s = rm_plan(ctx, n, desc, 'M', st, &ps);
+    if (s != TDEC_OK) return s;
+    return launch_rate_match((const RmItem *)ps->d_buf, n, d_coded, d_e, ctx->d_rmtab, st)
+               ? TDEC_EDEVICE
+               : TDEC_OK;
 }
 
 static tdec_status encode_list(tdec_ctx *ctx, std::vector<EncCb> &list, const std::string &key,

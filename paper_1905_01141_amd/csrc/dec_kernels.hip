@@ -492,7 +492,12 @@ __device__ uint32_t crc_shift(uint32_t r, int n, const uint32_t *T)
 
 __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, min(kLlrMax, v)); }
 
-__global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
+// At most 168 VGPRs: three waves per SIMD (the hot loops fit without spills;
+// a few spills remain in the phase-1 loop heads).  UNEVEN: some item's last
+// window is shorter than the others, so window lengths are per lane; the
+// even instantiation keeps them uniform (scalar loop bounds).
+template <bool UNEVEN>
+__global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs a)
 {
     // dynamic LDS: per-slot state (CRC, done, iterations, ok) for the most
     // blocks an item of this launch holds, then the blocks' extrinsic arrays
@@ -520,9 +525,10 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
         const int lanes = ncb * nw;
         // global scratch of this item: restaged inputs of both decoders,
         // checkpoints, window boundary metrics
-        uint32_t *R1 = (uint32_t *)scr;                          // ncb*K int32
-        uint32_t *R2 = R1 + (int64_t)ncb * K;                    // ncb*K int32
-        uint4 *ck = (uint4 *)(R2 + (int64_t)ncb * K);            // (W/S)*lanes
+        const int64_t rsz = (int64_t)lanes * W;                  // padded steps of the item
+        uint32_t *R1 = (uint32_t *)scr;                          // rsz int32
+        uint32_t *R2 = R1 + rsz;                                 // rsz int32
+        uint4 *ck = (uint4 *)(R2 + rsz);                         // (W/S)*lanes
         uint4 *bnd = ck + (int64_t)(W / S) * lanes;              // [4][lanes]
 
         // ---- restage the channel LLRs, clear LDS.  One unit = 4 trellis
@@ -531,7 +537,9 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
         // keeps 4 units of loads in flight.
         {
             const int esz = lds_e_bytes(K);
-            const int units = K >> 2;
+            // nw * W/4 units: the last window may be shorter than W, and the
+            // units past K (pad of the last window) are written as zeros
+            const int units = (nw * W) >> 2;
             const uint2 *qt = (const uint2 *)(a.qtab + it.qtab);
             uint4 *R1v = (uint4 *)R1, *R2v = (uint4 *)R2;
             for (int cs = 0; cs < ncb; ++cs) {
@@ -551,7 +559,9 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
                         const int p = ww * W + 4 * t4;
                         pos[m] = p;
                         q[m] = qt[u];
-                        if (aligned) {
+                        if (p >= K) {  // pad of a shorter last window: no input
+                            v[m][0] = v[m][1] = v[m][2] = make_uint2(0u, 0u);
+                        } else if (aligned) {
                             v[m][0] = *(const uint2 *)(src + p);
                             v[m][1] = *(const uint2 *)(src + N + p);
                             v[m][2] = *(const uint2 *)(src + 2 * N + p);
@@ -616,8 +626,9 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
         const int w = active ? wi - cs * nw : 0;
         const DecCb cb = a.cbs[it.cb0 + cs];
         Win c;
-        c.W = W;
-        c.M = win_split(W);
+        // every window has W steps but the last, which has the rest of K
+        c.W = (UNEVEN && w == nw - 1) ? K - (nw - 1) * W : W;
+        c.M = win_split(c.W);
         c.lo = w * W;
         c.wi = wi;
         c.lanes = lanes;
@@ -703,7 +714,7 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
             }
             const bool check = run && !bwd_first && cb.crc != 0 && (a.early_stop || iter == a.max_iters);
             if (check) {
-                const int b0 = max((int)cb.F, c.lo), b1 = c.lo + W;
+                const int b0 = max((int)cb.F, c.lo), b1 = c.lo + c.W;
                 uint32_t r = b0 < b1 ? crc_range(c.E, b0, b1, poly) : 0u;
                 r = crc_shift(r, K - b1, T);
                 if (r) atomicXor(&s_crc[cs], r);
@@ -768,12 +779,20 @@ __global__ void __launch_bounds__(kMaxWgThreads) turbo_decode_kernel(DecArgs a)
     }
 }
 
-const void *decode_kernel_address() { return (const void *)turbo_decode_kernel; }
-
-int launch_decode(const DecArgs &a, int grid, int wg_threads, int lds_bytes, void *stream)
+const void *decode_kernel_address(bool uneven)
 {
-    hipLaunchKernelGGL(turbo_decode_kernel, dim3(grid), dim3(wg_threads), lds_bytes,
-                       (hipStream_t)stream, a);
+    return uneven ? (const void *)turbo_decode_kernel<true> : (const void *)turbo_decode_kernel<false>;
+}
+
+int launch_decode(const DecArgs &a, bool uneven, int grid, int wg_threads, int lds_bytes,
+                  void *stream)
+{
+    if (uneven)
+        hipLaunchKernelGGL(turbo_decode_kernel<true>, dim3(grid), dim3(wg_threads), lds_bytes,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(turbo_decode_kernel<false>, dim3(grid), dim3(wg_threads), lds_bytes,
+                           (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -119,4 +119,32 @@ void crc_x32_table(uint32_t poly, uint32_t *out, int n)
     }
 }
 
+// Rate matching circular buffer (TS 36.212 5.1.4.1).  Each of the three
+// streams (D = K + 4 bits) is written row by row into an R x 32 matrix after
+// 32R - D leading <NULL>s; streams 0 and 1 are read column by column in the
+// column order given by 5-bit bit reversal, stream 2 through
+// (col(k / R) + 32 (k mod R) + 1) mod 32R.  The buffer holds stream 0, then
+// streams 1 and 2 alternating.  Filler bits of streams 0 and 1 are <NULL>.
+static int32_t bitrev5(int32_t c)
+{
+    int32_t r = 0;
+    for (int b = 0; b < 5; ++b) r |= ((c >> b) & 1) << (4 - b);
+    return r;
+}
+
+int32_t rm_buffer(int32_t K, int32_t F, int32_t *w)
+{
+    const int32_t D = K + 4, rows = (D + 31) / 32, cols = 32, kp = rows * cols, pad = kp - D;
+    for (int32_t k = 0; k < kp; ++k) {
+        const int32_t col = k / rows, row = k - col * rows;
+        const int32_t m01 = row * cols + bitrev5(col);               // streams 0 and 1
+        const int32_t m2 = (bitrev5(col) + cols * row + 1) % kp;     // stream 2
+        const int32_t j01 = m01 - pad, j2 = m2 - pad;
+        w[k] = (j01 >= F) ? j01 : -1;                                  // j01 < 0 is a dummy
+        w[kp + 2 * k] = (j01 >= F) ? D + j01 : -1;
+        w[kp + 2 * k + 1] = (j2 >= 0) ? 2 * D + j2 : -1;
+    }
+    return 3 * kp;
+}
+
 }  // namespace tdec

@@ -36,7 +36,7 @@ void crc_x32_table(uint32_t poly, uint32_t *out, int n);    // out[j] = x^(32 j)
 // each cut into `nw` windows of W steps; lane l < ncb*nw of the work group
 // runs window l % nw of block slot l / nw.
 struct DecItem {
-    int32_t K, nw, W, ncb;
+    int32_t K, nw, W, ncb;  // W: length of every window but the last (win_len)
     int32_t cb0;     // first entry of this item in the code block list
     int32_t f1, f2;  // QPP coefficients
     int32_t lds_slot;  // LDS bytes per code block slot (extrinsic array)
@@ -90,13 +90,25 @@ struct TbItem {
 __host__ __device__ inline int64_t hard_words(int32_t K) { return (K + 31) / 32 + 1; }
 
 // LDS layout of one code block slot of the decode kernel: the extrinsic
-// array (int16, padded with 8 entries after every 64 so that windows start in
-// different banks).  After decoder 2 its low bits hold the hard decisions.
-__host__ __device__ inline int32_t epad(int32_t j) { return j + ((j >> 6) << 3); }
+// array (int16, padded with 8 entries after every 128 so that windows start in
+// different banks; a K = 6144 slot is 13 KB, and 12 fit a CU beside their
+// state).  After decoder 2 its low bits hold the hard decisions.
+__host__ __device__ inline int32_t epad(int32_t j) { return j + ((j >> 7) << 3); }
 __host__ __device__ inline int32_t lds_e_bytes(int32_t K) { return ((epad(K - 1) + 1) * 2 + 15) & ~15; }
 __host__ __device__ inline int32_t lds_slot_bytes(int32_t K) { return (lds_e_bytes(K) + 63) & ~63; }
 // LDS bytes of the per-slot state that precedes the extrinsic arrays.
 __host__ __device__ inline int32_t lds_state_bytes(int32_t slots) { return (16 * slots + 63) & ~63; }
+// Window length of K steps cut into nw windows: all windows but the last
+// have W = 8 ceil(K / (8 nw)) steps (K for one window), the last the rest;
+// 0 when some window would be empty.
+__host__ __device__ inline int32_t win_len(int32_t K, int32_t nw)
+{
+    if (K < 1 || nw < 1) return 0;
+    if (nw == 1) return K;
+    const int32_t W = 8 * ((K + 8 * nw - 1) / (8 * nw));
+    return (int64_t)(nw - 1) * W < K ? W : 0;
+}
+
 // Split point of a window of W steps between its forward-first lane
 // (steps [0, M)) and its backward-first lane (steps [M, W)).
 __host__ __device__ inline int32_t win_split(int32_t W) { return (W / 16) * 8; }
@@ -110,6 +122,23 @@ struct EncCb {
     int8_t crc;
     int8_t rsv;
 };
+
+// One code block of a rate matching launch.
+struct RmItem {
+    int64_t e_off;     // element offset of its E transmitted values
+    int64_t soft_off;  // element offset of its [3][K+4] soft buffer / coded bits
+    int64_t tab_off;   // offset of its rank table in the context's table arena
+    int32_t K, E;
+    int32_t n_valid;   // non-<NULL> entries among the first Ncb of the circular buffer
+    int32_t r0;        // rank of the first non-<NULL> entry at or after k0(rv)
+};
+int launch_derate(const RmItem *items, int n, const void *e, int e_bytes, int16_t *soft,
+                  const uint16_t *tab, int combine, void *stream);
+int launch_rate_match(const RmItem *items, int n, const uint8_t *coded, uint8_t *e,
+                      const uint16_t *tab, void *stream);
+// Host: the circular buffer of a block as [3][K+4] indices, -1 for <NULL>
+// (tables.cpp); returns its length 3 * 32 * ceil((K+4)/32).
+int32_t rm_buffer(int32_t K, int32_t F, int32_t *w);
 
 // Device-to-device staging of the serving loop: up to kGatherMax copies per
 // launch, passed by value (kernel arguments stay under 4 KB).
@@ -135,8 +164,10 @@ tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tb
                                   void *ev_mid);
 
 // Launchers (dec_kernels.hip / enc_kernels.hip).
-const void *decode_kernel_address();
-int launch_decode(const DecArgs &a, int grid, int wg_threads, int lds_bytes, void *stream);
+// uneven: some item's windows are not all of equal length (per-lane lengths)
+const void *decode_kernel_address(bool uneven);
+int launch_decode(const DecArgs &a, bool uneven, int grid, int wg_threads, int lds_bytes,
+                  void *stream);
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,

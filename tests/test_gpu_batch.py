@@ -111,13 +111,14 @@ def test_autotuned_windows_decode_like_the_oracle(dev):
     T, _, torch = dev
     D2 = T.Decoder(0)
     try:
-        Ks = [40, 1056, 3136, 6144]
+        Ks = [40, 488, 1056, 3136, 6144]  # 488: only uneven windows reach W >= 64
         say(f"[autotune] {Ks}")
         choice = D2.autotune(Ks, min_W=64, max_iters=2, batch_bits=2_000_000)
         say(f"[autotune] choice {choice}")
         for K in Ks:
             nw, ns = choice[K]
-            assert K % nw == 0 and (K // nw) % 8 == 0 and (nw == 1 or K // nw >= 64)
+            W = O.win_len(K, nw)  # the oracle's partition rule
+            assert W > 0 and W % 8 == 0 and (nw == 1 or W >= 64)
             assert ns > 0
             assert D2.pick_windows(K) == nw
         cbs = [(K, 0, O.CRC24B) for K in Ks] * 2

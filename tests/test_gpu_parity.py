@@ -75,6 +75,11 @@ def check_cb_parity(dev, cbs, mod, esn0, p, cfg, stream=0, tag=""):
     (3136, 15, O.CRC24B, 14, 1, 1, 8),
     (6144, 0, O.CRC24B, 96, 1, 1, 6),    # 256-thread work groups (more than 64 windows)
     (1024, 0, O.CRC24B, 128, 1, 0, 4),   # 128 windows of 8 steps
+    (488, 0, O.CRC24B, 8, 1, 1, 8),      # uneven: 7 windows of 64, the last of 40
+    (6144, 0, O.CRC24B, 31, 1, 0, 6),    # uneven: 30 of 200, the last of 144
+    (200, 0, O.CRC_NONE, 3, 0, 0, 4),    # uneven: 72, 72, 56
+    (40, 8, O.CRC24B, 3, 1, 1, 8),       # uneven with filler: 16, 16, 8
+    (6144, 0, O.CRC24B, 70, 1, 1, 6),    # uneven, 256-thread groups: 69 of 88, the last of 72
 ])
 def test_cb_parity_noisy(dev, K, F, crc, nw, win_init, es, iters):
     cbs = [(K, F, crc)] * 6
