@@ -6,6 +6,8 @@
 // 1056..2048 step 32, 2112..6144 step 64); f1/f2 are listed per table row.
 // Segmentation: TS 36.212 5.1.2 (Z = 6144), which is the rule behind the
 // paper's Algorithm 1 cap of 6120 payload bits per code block.
+#include <algorithm>
+
 #include "tdec_internal.h"
 
 namespace tdec {
@@ -73,11 +75,17 @@ int segment(int32_t tbs, int32_t seg[8])
         C = (B + Z - L - 1) / (Z - L);
     }
     const int32_t Bp = B + C * L;
-    // smallest table size K+ with C * K+ >= B'
-    int ip = 0;
-    while (ip < kNumK && (int64_t)C * k_of_index(ip) < Bp) ++ip;
-    if (ip == kNumK) return -1;
-    const int32_t Kp = k_of_index(ip);
+    // smallest table size K+ with C * K+ >= B': round ceil(B' / C) up to the
+    // table's step at that size
+    const int32_t t = (Bp + C - 1) / C;
+    int32_t Kp;
+    if (t <= 40) Kp = 40;
+    else if (t <= 512) Kp = (t + 7) & ~7;
+    else if (t <= 1024) Kp = std::max(528, (t + 15) & ~15);
+    else if (t <= 2048) Kp = std::max(1056, (t + 31) & ~31);
+    else if (t <= 6144) Kp = std::max(2112, (t + 63) & ~63);
+    else return -1;
+    const int ip = k_index(Kp);
     int32_t Km = 0, Cm = 0, Cp = 1;
     if (C > 1) {
         Km = k_of_index(ip - 1);

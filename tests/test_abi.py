@@ -57,3 +57,24 @@ def test_binding_rejects_oversized_descriptors():
     with pytest.raises(ValueError):
         T._need(torch.zeros(n_llr, dtype=torch.int32), "int16", n_llr, "llr")
     T._need(torch.zeros(n_llr, dtype=torch.int16), "int16", n_llr, "llr")
+
+
+def test_segmentation_matches_oracle_for_every_size(orc):
+    """The library's segmentation (closed-form K+) equals the oracle's for
+    every transport block size 1..2^20."""
+    L = T.lib()
+    OL = orc.lib()
+    s1 = T.Seg()
+
+    class OSeg(ct.Structure):
+        _fields_ = [(n, ct.c_int32) for n in ("B", "C", "L", "Kplus", "Kminus", "Cplus",
+                                               "Cminus", "F")]
+    s2 = OSeg()
+    OL.or_segment.argtypes = [ct.c_int32, ct.c_void_p]
+    bad = 0
+    for tbs in range(1, (1 << 20) + 1):
+        r1 = L.tdec_segment(tbs, ct.byref(s1))
+        r2 = OL.or_segment(tbs, ct.byref(s2))
+        if (r1 == 0) != (r2 == 0) or (r1 == 0 and bytes(s1) != bytes(s2)):
+            bad += 1
+    assert bad == 0
