@@ -56,7 +56,8 @@ OPS_PER_KBIT_ITER = 178
 # packed int16 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 halves x 2.4 GHz
 PEAK_INT16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "turbo_decode_k6144x4096_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1905_01141_amd", "csrc", "dec_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1905_01141_amd", "csrc", f)
+              for f in ("dec_kernels.hip", "tdec_internal.h")]
 
 
 def log(*a):
@@ -64,8 +65,12 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the decode kernel's sources (the traffic figures hold for it only)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
