@@ -103,3 +103,38 @@ def test_server_auto_windows_matches_direct_call(dev):
         # at 14 dB 64QAM every TB decodes
         assert res[i]["tb_ok"] == 1
         assert np.array_equal(np.unpackbits(out[i])[:tbs], pays[i])
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3, 8])
+def test_device_submission_any_source_alignment(dev, shift):
+    """Device submission copies each block's LLRs into the server's slots in
+    16 KB chunks: sources 16-byte aligned, 4-byte aligned and 2-byte aligned
+    (shift in int16 elements), blocks of one partial chunk and of many (the
+    75376-bit maximum is 28 chunks and a tail) all decode like the oracle."""
+    T, D, torch = dev
+    tbs_list = [75376, 40, 6121, 20000, 8192 - 24]
+    say(f"[server] device alignment shift={shift} tbs={tbs_list}")
+    llr, pays, lo, bo = tb_batch(tbs_list, "16qam", 6.0, 9)
+    buf = torch.zeros(llr.size + 16, dtype=torch.int16)
+    buf[shift:shift + llr.size] = torch.from_numpy(llr)
+    d = buf.cuda()
+    torch.cuda.synchronize()
+    base = d.data_ptr() + 2 * shift
+    out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+    srv = T.Server(D, T.server_cfg(T.params(6, 1, 1, 0), deadline_us=10_000_000, mode=0))
+    try:
+        srv.submit(list(range(len(tbs_list))), tbs_list, [base + 2 * int(o) for o in lo],
+                   [o.ctypes.data for o in out], device=True)
+        srv.drain(60000)
+        res, t0 = [], time.monotonic()
+        while len(res) < len(tbs_list) and time.monotonic() - t0 < 30:
+            res += srv.poll(64, 100000)
+    finally:
+        srv.close()
+    res = {r["tag"]: r for r in res}
+    p = O.params(6, 1, 1, 0)
+    for i, tbs in enumerate(tbs_list):
+        ob, ores = O.tb_decode(llr[lo[i]:lo[i] + O.tb_llr_count(tbs)], tbs, p)
+        assert res[i]["status"] == T.SERVE_DONE
+        assert res[i]["tb_ok"] == ores["tb_ok"] == 1, i
+        assert np.array_equal(out[i], ob), (i, tbs)
