@@ -145,8 +145,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(code blocks, transport blocks and cells are independent; see DESIGN.md)",
+        print("bench.py measures one GPU only: there is no multi-GPU path (code blocks, "
+              "transport blocks and cells are independent, so GPUs would shard by cell)",
               file=sys.stderr)
         sys.exit(2)
 

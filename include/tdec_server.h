@@ -97,6 +97,18 @@ typedef struct {
     double mean_batch_tbs, mean_batch_cbs;
 } tdec_serve_stats;
 
+/* One launch of the serving loop, as the paper's performance captor
+ * (Sec. IV-D) records a processed subframe: when the worker took the batch,
+ * the three delays, and what the batch held. */
+typedef struct {
+    int64_t t_start_ns;     /* worker took the batch (tdec_now_ns clock) */
+    int64_t t_end_ns;       /* results in host memory */
+    int64_t pre_ns, coding_ns, post_ns; /* as in tdec_serve_stats */
+    int64_t oldest_wait_ns; /* t_start_ns minus the arrival of the batch's oldest TB */
+    int32_t n_tb, n_cb;
+    int64_t cb_bits;        /* sum of K over the batch's code blocks */
+} tdec_launch_rec;
+
 typedef struct tdec_server tdec_server;
 
 /* CLOCK_MONOTONIC in nanoseconds: the time base of arrivals and completions. */
@@ -144,6 +156,11 @@ tdec_status tdec_server_drain(tdec_server *s, int32_t timeout_ms);
  * the last reset). */
 tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out);
 void tdec_server_reset_stats(tdec_server *s);
+
+/* Copy the records of the most recent launches, oldest first, into out
+ * (at most max; the server keeps the last 4096 since creation or the last
+ * tdec_server_reset_stats).  Returns the count, or a negative tdec_status. */
+int32_t tdec_server_launches(tdec_server *s, tdec_launch_rec *out, int32_t max);
 
 /* Drain, stop the worker and free the server's device memory. */
 void tdec_server_destroy(tdec_server *s);

@@ -26,7 +26,8 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_server_drain", "tdec_server_stats", "tdec_server_reset_stats",
            "tdec_server_destroy", "tdec_graph_cb_decode", "tdec_graph_tb_decode",
            "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
-           "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch")
+           "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch",
+           "tdec_server_launches")
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -77,6 +78,12 @@ class ServeStats(ct.Structure):
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class LaunchRec(ct.Structure):
+    _fields_ = [(n, ct.c_int64) for n in (
+        "t_start_ns", "t_end_ns", "pre_ns", "coding_ns", "post_ns", "oldest_wait_ns")] + [
+        ("n_tb", ct.c_int32), ("n_cb", ct.c_int32), ("cb_bits", ct.c_int64)]
 
 
 class RmDesc(ct.Structure):
@@ -160,6 +167,7 @@ def lib():
         L.tdec_server_reset_stats.restype = None
         L.tdec_server_destroy.argtypes = [vp]
         L.tdec_server_destroy.restype = None
+        L.tdec_server_launches.argtypes = [vp, vp, i32]
         _lib = L
     return _lib
 
@@ -528,6 +536,15 @@ class Server:
             self._rawbuf = (ServeResult * max_n)()
         return int(lib().tdec_server_poll(self._h, ct.cast(self._rawbuf, ct.c_void_p), max_n,
                                           int(wait_us)))
+
+    def launches(self, max_n=4096) -> list[dict]:
+        """Records of the most recent launches, oldest first (the server
+        keeps the last 4096)."""
+        buf = (LaunchRec * max_n)()
+        k = lib().tdec_server_launches(self._h, ct.cast(buf, ct.c_void_p), max_n)
+        if k < 0:
+            raise TdecError("tdec_server_launches", k)
+        return [{n: getattr(r, n) for n, _ in LaunchRec._fields_} for r in buf[:k]]
 
     def drain(self, timeout_ms=60000):
         _check("tdec_server_drain", lib().tdec_server_drain(self._h, int(timeout_ms)))

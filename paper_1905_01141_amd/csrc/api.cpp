@@ -203,13 +203,33 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
                               std::vector<char> &blob, const std::vector<TbItem> *tbs,
                               hipStream_t st)
 {
-    // group by (K, nw), biggest blocks first
+    // group by (K, nw), biggest blocks first, request order within a group:
+    // a counting sort over the size table (a size has one window count per
+    // plan; mixed counts for one size fall back to a comparison sort)
     std::vector<int> order(reqs.size());
-    for (size_t i = 0; i < reqs.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (reqs[a].K != reqs[b].K) return reqs[a].K > reqs[b].K;
-        return reqs[a].nw < reqs[b].nw;
-    });
+    {
+        int cnt[kNumK + 1] = {}, nw_of[kNumK];
+        bool mixed = false;
+        for (const CbReq &r : reqs) {
+            const int ki = k_index(r.K);
+            if (cnt[ki + 1]++ == 0) nw_of[ki] = r.nw;
+            else mixed = mixed || nw_of[ki] != r.nw;
+        }
+        if (!mixed) {
+            int pos[kNumK], at = 0;
+            for (int ki = kNumK - 1; ki >= 0; --ki) {
+                pos[ki] = at;
+                at += cnt[ki + 1];
+            }
+            for (size_t i = 0; i < reqs.size(); ++i) order[pos[k_index(reqs[i].K)]++] = (int)i;
+        } else {
+            for (size_t i = 0; i < reqs.size(); ++i) order[i] = (int)i;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                if (reqs[a].K != reqs[b].K) return reqs[a].K > reqs[b].K;
+                return reqs[a].nw < reqs[b].nw;
+            });
+        }
+    }
     int max_nw = 1;
     for (auto &r : reqs) max_nw = std::max(max_nw, r.nw);
     // two lanes per window, in two halves of the work group (forward-first
@@ -224,28 +244,34 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     bool uneven = false;
     int64_t stride = 0;
     size_t i = 0;
+    items.reserve(reqs.size());
+    // per-size constants, computed once per run of equal (K, nw)
+    DecItem proto{};
+    int cap = 0, gK = -1, gnw = -1;
     while (i < order.size()) {
         const CbReq &r0 = reqs[order[i]];
-        const int K = r0.K, nw = r0.nw, W = win_len(K, nw);
-        const int sb = lds_slot_bytes(K);
-        int cap = std::min(half / nw, kMaxSlotsPerWg);
-        cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
-        cap = std::min(cap, 65536 / sb);  // decoder 2 keeps 16-bit LDS addresses
-        DecItem it;
-        it.K = K;
-        it.nw = nw;
-        it.W = W;
-        it.cb0 = (int)cbl.size();
-        int32_t f1, f2;
-        qpp_coeffs(k_index(K), &f1, &f2);
-        it.f1 = f1;
-        it.f2 = f2;
-        it.lds_slot = sb;
-        {
-            const int64_t off = qtab_get(ctx, K, nw, st);
+        if (r0.K != gK || r0.nw != gnw) {
+            gK = r0.K;
+            gnw = r0.nw;
+            const int sb = lds_slot_bytes(gK);
+            cap = std::min(half / gnw, kMaxSlotsPerWg);
+            cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
+            cap = std::min(cap, 65536 / sb);  // decoder 2 keeps 16-bit LDS addresses
+            proto.K = gK;
+            proto.nw = gnw;
+            proto.W = win_len(gK, gnw);
+            int32_t f1, f2;
+            qpp_coeffs(k_index(gK), &f1, &f2);
+            proto.f1 = f1;
+            proto.f2 = f2;
+            proto.lds_slot = sb;
+            const int64_t off = qtab_get(ctx, gK, gnw, st);
             if (off < 0) return TDEC_ENOMEM;
-            it.qtab = (int32_t)off;
+            proto.qtab = (int32_t)off;
         }
+        const int K = gK, nw = gnw, W = proto.W, sb = proto.lds_slot;
+        DecItem it = proto;
+        it.cb0 = (int)cbl.size();
         int n = 0;
         while (i < order.size() && n < cap && reqs[order[i]].K == K && reqs[order[i]].nw == nw) {
             cbl.push_back(reqs[order[i]].cb);
@@ -426,6 +452,7 @@ tdec_status make_tb_reqs(const tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
 {
     tbl.assign((size_t)n_tb, TbItem{});
     reqs.clear();
+    reqs.reserve((size_t)n_tb * 2);
     int64_t hard = 0;
     int32_t cbi = 0;
     for (int32_t t = 0; t < n_tb; ++t) {

@@ -100,6 +100,7 @@ struct Pending {
 };
 
 constexpr int kCopyEvents = 64;
+constexpr int64_t kLaunchRing = 4096;  // launch records kept
 
 }  // namespace
 
@@ -137,6 +138,8 @@ struct tdec_server {
     int64_t batch_tbs_sum = 0, batch_cbs_sum = 0;
     int64_t pre_sum = 0, coding_sum = 0, post_sum = 0;  // per-launch delays (ns)
     std::vector<int64_t> lat;
+    std::vector<tdec_launch_rec> ring;  // last kLaunchRing launches
+    int64_t ring_n = 0;                 // launches recorded since the last reset
     bool stop = false;
     std::thread worker;
 
@@ -299,6 +302,21 @@ void worker_main(tdec_server *s)
             s->pre_sum += lat3[0];
             s->coding_sum += lat3[1];
             s->post_sum += lat3[2];
+            {
+                tdec_launch_rec lr{};
+                lr.t_start_ns = t0;
+                lr.t_end_ns = t1;
+                lr.pre_ns = lat3[0];
+                lr.coding_ns = lat3[1];
+                lr.post_ns = lat3[2];
+                int64_t oldest = t0;
+                for (const Pending &p : b) oldest = std::min(oldest, p.t_arrive);
+                lr.oldest_wait_ns = t0 - oldest;
+                lr.n_tb = (int32_t)b.size();
+                lr.n_cb = (int32_t)cbs;
+                lr.cb_bits = kb;
+                s->ring[(size_t)(s->ring_n++ % kLaunchRing)] = lr;
+            }
             // service model update: the regime the prediction was in learns
             // one observation moves the model by at most a factor of 4 (a
             // cold first launch must not stall admission for long)
@@ -346,6 +364,7 @@ tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
     s->m_lat = (double)(cfg->model_lat_ns ? cfg->model_lat_ns : 300000);
     s->m_npk = (double)(cfg->model_ns_per_kbit ? cfg->model_ns_per_kbit : 50);
     s->lat.reserve(1 << 16);
+    s->ring.resize((size_t)kLaunchRing);
     return TDEC_OK;
 }
 
@@ -632,7 +651,19 @@ void tdec_server_reset_stats(tdec_server *s)
     s->lat.clear();
     s->batch_tbs_sum = s->batch_cbs_sum = 0;
     s->pre_sum = s->coding_sum = s->post_sum = 0;
+    s->ring_n = 0;
     s->arena.reset_peak();
+}
+
+int32_t tdec_server_launches(tdec_server *s, tdec_launch_rec *out, int32_t max)
+{
+    if (!s || max < 0 || (max > 0 && !out)) return TDEC_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t kept = std::min<int64_t>(s->ring_n, kLaunchRing);
+    const int64_t n = std::min<int64_t>(kept, max);
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = s->ring[(size_t)((s->ring_n - n + i) % kLaunchRing)];
+    return (int32_t)n;
 }
 
 void tdec_server_destroy(tdec_server *s)

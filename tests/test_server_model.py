@@ -215,3 +215,55 @@ def test_per_tb_mode_deadline_admission_bounds_the_queue():
     assert len(done) == s["completed"] > 0
     late = sum(r["t_done_ns"] - r["t_arrive_ns"] > 3_000_000 for r in done)
     assert late <= 0.2 * len(done)
+
+
+def test_launch_records_account_for_every_block():
+    """The per-launch record (the paper's performance captor, Sec. IV-D):
+    launches in time order, their TB and code block counts add up to what
+    completed, each covers its coding delay, and a reset empties the ring."""
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000, model_lat_ns=500_000)
+    srv = T.Server.model(cfg, 500_000, 0)
+    try:
+        tbs = [40, 6120, 6121, 20000, 75376]
+        for tti in range(4):
+            _submit(srv, list(range(tti * 5, tti * 5 + 5)), tbs)
+            time.sleep(0.0007)
+        srv.drain(10000)
+        _collect(srv, 20)
+        recs = srv.launches()
+        s = srv.stats()
+        srv.reset_stats()
+        after = srv.launches()
+    finally:
+        srv.close()
+    assert len(recs) == s["batches"] and after == []
+    assert sum(r["n_tb"] for r in recs) == 20
+    cbs = sum(T.segment(t)["C"] for t in tbs) * 4
+    assert sum(r["n_cb"] for r in recs) == cbs
+    bits = sum(T.segment(t)["Cplus"] * T.segment(t)["Kplus"] +
+               T.segment(t)["Cminus"] * T.segment(t)["Kminus"] for t in tbs) * 4
+    assert sum(r["cb_bits"] for r in recs) == bits
+    for a, b in zip(recs, recs[1:]):
+        assert b["t_start_ns"] >= a["t_end_ns"]
+    for r in recs:
+        assert r["t_end_ns"] - r["t_start_ns"] >= 500_000
+        assert r["coding_ns"] == r["t_end_ns"] - r["t_start_ns"]
+        assert r["oldest_wait_ns"] >= 0
+
+
+def test_launch_ring_keeps_the_most_recent():
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=10_000_000, mode=T.SERVE_PER_TB)
+    srv = T.Server.model(cfg, 1000, 0)
+    try:
+        n = 4200
+        _submit(srv, list(range(n)), [40] * n)
+        srv.drain(60000)
+        recs = srv.launches(5000)
+        last = srv.launches(3)
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert s["batches"] == n and len(recs) == 4096
+    assert all(r["n_tb"] == 1 and r["n_cb"] == 1 and r["cb_bits"] == 64 for r in recs)
+    assert last == recs[-3:]
+    assert all(b["t_start_ns"] >= a["t_end_ns"] for a, b in zip(recs, recs[1:]))
