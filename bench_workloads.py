@@ -7,6 +7,7 @@ an LTE cell (100 PRB, FDD, 1 ms TTI).
 """
 from __future__ import annotations
 
+import gc
 import json
 import sys
 import time
@@ -248,6 +249,11 @@ def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admis
     rng = np.random.default_rng(seed)
     tag = 0
     late_max = 0  # how far behind its TTI clock this generator submitted
+    sub_t = []    # duration of each measured submit call (s)
+    # no collector pauses in the generator while it keeps the TTI clock
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     try:
         t_next = T.now_ns() + TTI_NS
         for tti in range(warm + n_ttis):
@@ -263,8 +269,11 @@ def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admis
             if tti >= warm:
                 late_max = max(late_max, T.now_ns() - t_next)
             if len(idx):
+                ts = time.perf_counter()
                 srv.submit(np.arange(tag, tag + len(idx)), pool_tbs[idx], pool_llr_ptr[idx],
                            None, t_next, device=True)
+                if tti >= warm:
+                    sub_t.append(time.perf_counter() - ts)
                 tag += len(idx)
             if tti % 16 == 0:
                 srv.discard()
@@ -276,10 +285,33 @@ def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admis
         s = srv.stats()
         s["launches"] = srv.launches()
     finally:
+        gc.enable()
+        gc.unfreeze()
         srv.close()
     s["wall_s"] = (t_end - t_begin) / 1e9
     s["gen_late_max_ms"] = late_max / 1e6
+    s["submit_ms"] = [round(1e3 * float(np.mean(sub_t)), 3) if sub_t else 0.0,
+                      round(1e3 * float(np.max(sub_t)), 3) if sub_t else 0.0]
     return s
+
+
+def log_slowest(recs, tag, k=3):
+    """Log the longest launches and the longest waits of a trial's launch
+    records (where a latency tail came from)."""
+    if not recs:
+        return
+    t0 = recs[0]["t_start_ns"]
+    dur = [r["t_end_ns"] - r["t_start_ns"] for r in recs]
+    for name, key in (("longest", lambda i: -dur[i]), ("longest wait", lambda i: -recs[i]["oldest_wait_ns"])):
+        for i in sorted(range(len(recs)), key=key)[:k]:
+            r = recs[i]
+            gap = (r["t_start_ns"] - recs[i - 1]["t_end_ns"]) / 1e3 if i else 0.0
+            log(f"[{tag}]   {name}: launch {i} at {(r['t_start_ns'] - t0) / 1e6:.2f} ms, "
+                f"{dur[i] / 1e3:.0f} us (pre {r['pre_ns'] / 1e3:.0f} coding "
+                f"{r['coding_ns'] / 1e3:.0f} post {r['post_ns'] / 1e3:.0f} of which copies "
+                f"{r['copy_ns'] / 1e3:.0f}), idle before "
+                f"{gap:.0f} us, oldest waited {r['oldest_wait_ns'] / 1e3:.0f} us, "
+                f"{r['n_tb']} TBs / {r['n_cb']} CBs")
 
 
 GEN_LATE_MS = 1.0  # a trial whose load generator fell this far behind is repeated
@@ -354,7 +386,8 @@ def run_serving(args):
                                              round(s["mean_coding_ns"] / 1e3, 1),
                                              round(s["mean_post_ns"] / 1e3, 1)],
                "gen_late_max_ms": round(s["gen_late_max_ms"], 3),
-               "gen_stall_repeats": s["gen_stall_repeats"]}
+               "gen_stall_repeats": s["gen_stall_repeats"],
+               "submit_ms_mean_max": s["submit_ms"]}
         log(f"[serving] {row}")
         rows.append(row)
     top = rows[-1]
@@ -411,6 +444,8 @@ def run_cells(args):
             f"busy {s['busy_ns'] / 1e9 / s['wall_s']:.2f}, batch {s['mean_batch_tbs']:.1f} TBs, "
             f"pre/coding/post {s['mean_pre_ns'] / 1e3:.0f}/{s['mean_coding_ns'] / 1e3:.0f}/"
             f"{s['mean_post_ns'] / 1e3:.0f} us -> {'ok' if okk else 'over'}")
+        if not okk:
+            log_slowest(s["launches"], "cells")
         return okk, s
 
     lo_n, hi_n, best = 1, 512, None

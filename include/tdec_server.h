@@ -104,6 +104,7 @@ typedef struct {
     int64_t t_start_ns;     /* worker took the batch (tdec_now_ns clock) */
     int64_t t_end_ns;       /* results in host memory */
     int64_t pre_ns, coding_ns, post_ns; /* as in tdec_serve_stats */
+    int64_t copy_ns;        /* part of post_ns spent in the copies back to host memory */
     int64_t oldest_wait_ns; /* t_start_ns minus the arrival of the batch's oldest TB */
     int32_t n_tb, n_cb;
     int64_t cb_bits;        /* sum of K over the batch's code blocks */

@@ -82,7 +82,8 @@ class ServeStats(ct.Structure):
 
 class LaunchRec(ct.Structure):
     _fields_ = [(n, ct.c_int64) for n in (
-        "t_start_ns", "t_end_ns", "pre_ns", "coding_ns", "post_ns", "oldest_wait_ns")] + [
+        "t_start_ns", "t_end_ns", "pre_ns", "coding_ns", "post_ns", "copy_ns",
+        "oldest_wait_ns")] + [
         ("n_tb", ct.c_int32), ("n_cb", ct.c_int32), ("cb_bits", ct.c_int64)]
 
 

@@ -20,6 +20,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -36,55 +37,72 @@ int64_t mono_ns()
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
 
-// First-fit allocator over [0, cap) bytes with coalescing of free extents;
-// extents are 256-byte aligned.
+// Best-fit allocator over [0, cap) bytes with coalescing of free extents;
+// extents are 256-byte aligned.  Free extents are indexed by offset (for
+// coalescing) and by (size, offset) (for the fit), so both calls are
+// O(log extents) however fragmented the arena gets.
 class Arena {
 public:
     void init(int64_t cap)
     {
         cap_ = cap;
-        free_.clear();
-        if (cap > 0) free_[0] = cap;
+        by_off_.clear();
+        by_size_.clear();
+        if (cap > 0) add(0, cap);
         used_ = peak_ = 0;
     }
     int64_t alloc(int64_t n)
     {
         n = (n + 255) & ~(int64_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second >= n) {
-                const int64_t off = it->first, rest = it->second - n;
-                free_.erase(it);
-                if (rest) free_[off + n] = rest;
-                used_ += n;
-                peak_ = std::max(peak_, used_);
-                return off;
-            }
-        return -1;
+        auto f = by_size_.lower_bound({n, (int64_t)-1});
+        if (f == by_size_.end()) return -1;
+        const int64_t off = f->second, size = f->first;
+        remove(off, size);
+        if (size > n) add(off + n, size - n);
+        used_ += n;
+        peak_ = std::max(peak_, used_);
+        return off;
     }
     void release(int64_t off, int64_t n)
     {
         n = (n + 255) & ~(int64_t)255;
         used_ -= n;
-        auto nx = free_.lower_bound(off);
-        if (nx != free_.end() && off + n == nx->first) {
-            n += nx->second;
-            nx = free_.erase(nx);
+        auto nx = by_off_.lower_bound(off);
+        if (nx != by_off_.end() && off + n == nx->first) {
+            const int64_t o = nx->first, z = nx->second;
+            remove(o, z);
+            n += z;
         }
-        if (nx != free_.begin()) {
+        nx = by_off_.lower_bound(off);
+        if (nx != by_off_.begin()) {
             auto pv = std::prev(nx);
             if (pv->first + pv->second == off) {
-                pv->second += n;
-                return;
+                const int64_t o = pv->first, z = pv->second;
+                remove(o, z);
+                off = o;
+                n += z;
             }
         }
-        free_[off] = n;
+        add(off, n);
     }
     int64_t used() const { return used_; }
     int64_t peak() const { return peak_; }
     void reset_peak() { peak_ = used_; }
+    size_t extents() const { return by_off_.size(); }
 
 private:
-    std::map<int64_t, int64_t> free_;
+    void add(int64_t off, int64_t n)
+    {
+        by_off_[off] = n;
+        by_size_.insert({n, off});
+    }
+    void remove(int64_t off, int64_t n)
+    {
+        by_off_.erase(off);
+        by_size_.erase({n, off});
+    }
+    std::map<int64_t, int64_t> by_off_;             // offset -> size
+    std::set<std::pair<int64_t, int64_t>> by_size_;  // (size, offset)
     int64_t cap_ = 0, used_ = 0, peak_ = 0;
 };
 
@@ -116,11 +134,13 @@ struct tdec_server {
     hipEvent_t copy_ev[kCopyEvents] = {};
     hipEvent_t done_ev = nullptr;
     hipEvent_t ev_s = nullptr, ev_m = nullptr;  // around the decode kernel (timing)
+    hipEvent_t ev_c = nullptr;                  // before the copies back (timing)
     uint64_t copy_seq = 0;  // events recorded so far
     uint8_t *d_bits = nullptr, *h_bits_stage = nullptr;
     size_t bits_cap = 0;
     tdec_tb_result *d_res = nullptr, *h_res = nullptr;
     int32_t res_cap = 0;
+    std::mutex submit_mu;  // serialises submitters (held across their copies)
     // queue state (under mu)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -170,7 +190,7 @@ bool seg_of(int32_t tbs, Segm *o)
 // launch's pre-processing (host: batch, plan, enqueue), coding (decode
 // kernel) and post-processing (assembly, copies back, copy-out) delays.
 void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
-                int64_t t0, int64_t lat[3])
+                int64_t t0, int64_t lat[4])
 {
     const int n = (int)b.size();
     std::vector<int32_t> tbs(n);
@@ -189,16 +209,18 @@ void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server
                                            &s->cfg.params, s->d_bits, s->d_res, s->dec_st,
                                            s->ev_s, s->ev_m) == TDEC_OK;
     const int64_t t_enq = mono_ns();
+    ok = ok && hipEventRecord(s->ev_c, s->dec_st) == hipSuccess;
     ok = ok && hipMemcpyAsync(s->h_bits_stage, s->d_bits, (size_t)bytes, hipMemcpyDeviceToHost,
                               s->dec_st) == hipSuccess;
     ok = ok && hipMemcpyAsync(s->h_res, s->d_res, sizeof(tdec_tb_result) * (size_t)n,
                               hipMemcpyDeviceToHost, s->dec_st) == hipSuccess;
     ok = ok && hipEventRecord(s->done_ev, s->dec_st) == hipSuccess;
     ok = ok && hipEventSynchronize(s->done_ev) == hipSuccess;
-    float coding_ms = 0.f, post_ms = 0.f;
+    float coding_ms = 0.f, post_ms = 0.f, copy_ms = 0.f;
     if (ok) {
         (void)hipEventElapsedTime(&coding_ms, s->ev_s, s->ev_m);
         (void)hipEventElapsedTime(&post_ms, s->ev_m, s->done_ev);
+        (void)hipEventElapsedTime(&copy_ms, s->ev_c, s->done_ev);
     }
     for (int i = 0; i < n; ++i) {
         tdec_server_result &r = res[i];
@@ -214,6 +236,7 @@ void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server
     lat[0] = t_enq - t0;
     lat[1] = (int64_t)(coding_ms * 1e6f);
     lat[2] = (int64_t)(post_ms * 1e6f);
+    lat[3] = (int64_t)(copy_ms * 1e6f);
 }
 
 void run_model(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
@@ -266,23 +289,26 @@ void worker_main(tdec_server *s)
             s->run_end_pred = t0 + s->dur(kb);
         }
         res.assign(b.size(), tdec_server_result{});
-        int64_t lat3[3] = {0, 0, 0};
+        int64_t lat3[4] = {0, 0, 0, 0};
         if (s->model)
             run_model(s, b, res, t0);
         else
             run_device(s, b, res, t0, lat3);
         const int64_t t1 = mono_ns();
         if (s->model) lat3[1] = t1 - t0;
+        for (size_t i = 0; i < b.size(); ++i) {
+            tdec_server_result &r = res[i];
+            r.tag = b[i].tag;
+            r.tbs = b[i].tbs;
+            r.C = b[i].C;
+            r.batch_tbs = (int32_t)b.size();
+            r.t_arrive_ns = b[i].t_arrive;
+            r.t_done_ns = t1;
+        }
         {
             std::lock_guard<std::mutex> lk(s->mu);
             for (size_t i = 0; i < b.size(); ++i) {
-                tdec_server_result &r = res[i];
-                r.tag = b[i].tag;
-                r.tbs = b[i].tbs;
-                r.C = b[i].C;
-                r.batch_tbs = (int32_t)b.size();
-                r.t_arrive_ns = b[i].t_arrive;
-                r.t_done_ns = t1;
+                const tdec_server_result &r = res[i];
                 s->arena.release(b[i].slot_off, b[i].slot_bytes);
                 if (r.status == TDEC_SERVE_DONE) {
                     ++s->st.completed;
@@ -309,6 +335,7 @@ void worker_main(tdec_server *s)
                 lr.pre_ns = lat3[0];
                 lr.coding_ns = lat3[1];
                 lr.post_ns = lat3[2];
+                lr.copy_ns = lat3[3];
                 int64_t oldest = t0;
                 for (const Pending &p : b) oldest = std::min(oldest, p.t_arrive);
                 lr.oldest_wait_ns = t0 - oldest;
@@ -345,6 +372,7 @@ void free_device(tdec_server *s)
     if (s->done_ev) (void)hipEventDestroy(s->done_ev);
     if (s->ev_s) (void)hipEventDestroy(s->ev_s);
     if (s->ev_m) (void)hipEventDestroy(s->ev_m);
+    if (s->ev_c) (void)hipEventDestroy(s->ev_c);
     if (s->copy_st) (void)hipStreamDestroy(s->copy_st);
     if (s->dec_st) (void)hipStreamDestroy(s->dec_st);
 }
@@ -400,7 +428,7 @@ tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_s
               hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&s->dec_st, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreate(&s->done_ev) == hipSuccess && hipEventCreate(&s->ev_s) == hipSuccess &&
-              hipEventCreate(&s->ev_m) == hipSuccess;
+              hipEventCreate(&s->ev_m) == hipSuccess && hipEventCreate(&s->ev_c) == hipSuccess;
     for (auto &e : s->copy_ev)
         ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     // every copy event starts recorded, so that a wait on it never blocks on nothing
@@ -434,6 +462,12 @@ tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
     return TDEC_OK;
 }
 
+// Submission runs in three steps so that the worker never waits behind the
+// copies: (1) under the server mutex, admission and slot allocation (the
+// admitted blocks already count in the queue's totals); (2) under the
+// submitters' own mutex only, the copies into the slots and the event that
+// covers them; (3) under the server mutex again, the blocks join the queue,
+// each naming that event, so the worker can only launch them behind it.
 static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
                            const int16_t *const *h_llr, uint8_t *const *h_bits,
                            int64_t t_arrive_ns, int32_t *status, bool dev)
@@ -442,11 +476,22 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
     if (n == 0) return 0;
     if (!tags || !tbs || !h_llr) return TDEC_EINVAL;
     if (!s->model && hipSetDevice(s->device) != hipSuccess) return TDEC_EDEVICE;
-    int32_t admitted = 0;
-    bool copied = false;
-    tdec::GatherArgs ga;
-    ga.n = 0;
-    ga.dst_base = s->d_arena;
+    std::lock_guard<std::mutex> sub(s->submit_mu);
+    std::vector<Pending> adm;
+    std::vector<int32_t> idx;  // caller index of each admitted block
+    adm.reserve((size_t)n);
+    idx.reserve((size_t)n);
+    auto reject = [&](int32_t i, int32_t why, int32_t C) {
+        if (status) status[i] = why;
+        tdec_server_result r{};
+        r.tag = tags[i];
+        r.tbs = tbs[i];
+        r.status = why;
+        r.C = C;
+        r.t_arrive_ns = r.t_done_ns = t_arrive_ns;
+        s->done.push_back(r);
+    };
+    // (1) admission
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const int64_t now = mono_ns();
@@ -476,62 +521,33 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                            (launches - 1) * (int64_t)s->m_lat;
                     // joining the same launch as the oldest waiting block
                     // must not push that block past its own deadline
-                    if (launches == 1 && !s->queue.empty())
-                        limit = std::min(limit, s->queue.front().t_arrive +
-                                                    (int64_t)s->cfg.deadline_us * 1000);
+                    // (submitters are serialised, so the waiting blocks
+                    // are the queue's, then this call's)
+                    const bool waiting = !s->queue.empty() || !adm.empty();
+                    const int64_t oldest =
+                        !s->queue.empty() ? s->queue.front().t_arrive : t_arrive_ns;
+                    if (launches == 1 && waiting)
+                        limit = std::min(limit, oldest + (int64_t)s->cfg.deadline_us * 1000);
                 } else {
                     pred = start + s->queued_dur_ns + s->dur(g.kbits);
                 }
                 // an idle server always admits: the prediction only judges
                 // the wait behind other work (and an overestimating model
                 // must still see launches to correct itself)
-                const bool busy = s->run_end_pred != 0 || !s->queue.empty();
+                const bool busy = s->run_end_pred != 0 || !s->queue.empty() || !adm.empty();
                 if (busy && pred > limit) {
                     why = TDEC_SERVE_REJ_DEADLINE;
                     s->arena.release(off, bytes);
                 }
             }
-            if (status) status[i] = why;
             if (why != TDEC_SERVE_DONE) {
                 if (why == TDEC_SERVE_REJ_BUDGET) ++s->st.rej_budget;
                 if (why == TDEC_SERVE_REJ_DEADLINE) ++s->st.rej_deadline;
                 if (why == TDEC_SERVE_REJ_INVALID) ++s->st.rej_invalid;
-                tdec_server_result r{};
-                r.tag = tags[i];
-                r.tbs = tbs[i];
-                r.status = why;
-                r.C = g.C;
-                r.t_arrive_ns = r.t_done_ns = t_arrive_ns;
-                s->done.push_back(r);
+                reject(i, why, g.C);
                 continue;
             }
-            bool cp_ok = true;
-            if (!s->model && !dev) {
-                cp_ok = hipMemcpyAsync(s->d_arena + off / 2, h_llr[i], (size_t)bytes,
-                                       hipMemcpyHostToDevice, s->copy_st) == hipSuccess;
-            } else if (!s->model) {
-                // device sources: batched into gather launches
-                ga.it[ga.n].src = h_llr[i];
-                ga.it[ga.n].dst_blk = (uint32_t)(off / 256);
-                ga.it[ga.n].n = (uint32_t)(bytes / 2);
-                if (++ga.n == tdec::kGatherMax) {
-                    cp_ok = tdec::launch_gather(ga, s->copy_st) == 0;
-                    ga.n = 0;
-                }
-            }
-            if (!cp_ok) {
-                s->arena.release(off, bytes);
-                if (status) status[i] = TDEC_SERVE_ERROR;
-                tdec_server_result r{};
-                r.tag = tags[i];
-                r.tbs = tbs[i];
-                r.status = TDEC_SERVE_ERROR;
-                r.C = g.C;
-                r.t_arrive_ns = r.t_done_ns = t_arrive_ns;
-                s->done.push_back(r);
-                continue;
-            }
-            copied = !s->model;
+            if (status) status[i] = TDEC_SERVE_DONE;
             Pending p{};
             p.tag = tags[i];
             p.tbs = tbs[i];
@@ -541,23 +557,68 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
             p.slot_bytes = bytes;
             p.h_bits = h_bits ? h_bits[i] : nullptr;
             p.t_arrive = t_arrive_ns;
-            p.copy_seq = s->copy_seq + 1;
             p.pred_dur = s->cfg.mode == TDEC_SERVE_PER_TB ? s->dur(g.kbits) : 0;
-            s->queue.push_back(p);
             s->queued_kbits += g.kbits;
             s->queued_cbs += g.C;
             s->queued_dur_ns += p.pred_dur;
             ++s->inflight;
+            adm.push_back(p);
+            idx.push_back(i);
+        }
+    }
+    // (2) copies: host sources one asynchronous copy each, device sources
+    // batched into gather launches; fail[k] marks blocks whose copy failed
+    std::vector<char> fail(adm.size(), 0);
+    uint64_t seq = 0;
+    if (!s->model && !adm.empty()) {
+        tdec::GatherArgs ga;
+        ga.n = 0;
+        ga.dst_base = s->d_arena;
+        size_t g0 = 0;  // first block of the pending gather
+        for (size_t k = 0; k < adm.size(); ++k) {
+            const Pending &p = adm[k];
+            const int32_t i = idx[k];
+            if (!dev) {
+                fail[k] = hipMemcpyAsync(s->d_arena + p.slot_off / 2, h_llr[i],
+                                         (size_t)p.slot_bytes, hipMemcpyHostToDevice,
+                                         s->copy_st) != hipSuccess;
+                continue;
+            }
+            ga.it[ga.n].src = h_llr[i];
+            ga.it[ga.n].dst_blk = (uint32_t)(p.slot_off / 256);
+            ga.it[ga.n].n = (uint32_t)(p.slot_bytes / 2);
+            if (++ga.n == tdec::kGatherMax || k + 1 == adm.size()) {
+                if (tdec::launch_gather(ga, s->copy_st) != 0)
+                    for (size_t q = g0; q <= k; ++q) fail[q] = 1;
+                ga.n = 0;
+                g0 = k + 1;
+            }
+        }
+        // record after this call's copies; the worker waits for it before
+        // it launches any of these blocks
+        seq = ++s->copy_seq;
+        if (hipEventRecord(s->copy_ev[seq % kCopyEvents], s->copy_st) != hipSuccess)
+            std::fill(fail.begin(), fail.end(), 1);
+    }
+    // (3) queue
+    int32_t admitted = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t k = 0; k < adm.size(); ++k) {
+            Pending &p = adm[k];
+            if (fail[k]) {
+                s->arena.release(p.slot_off, p.slot_bytes);
+                s->queued_kbits -= p.kbits;
+                s->queued_cbs -= p.C;
+                s->queued_dur_ns -= p.pred_dur;
+                --s->inflight;
+                reject(idx[k], TDEC_SERVE_ERROR, p.C);
+                continue;
+            }
+            p.copy_seq = seq;
+            s->queue.push_back(p);
             ++s->st.admitted;
             ++admitted;
-        }
-        if (ga.n && tdec::launch_gather(ga, s->copy_st) != 0) return TDEC_EDEVICE;
-        if (copied) {
-            // record after this call's copies; the worker waits for it before
-            // it launches any of these blocks
-            ++s->copy_seq;
-            if (hipEventRecord(s->copy_ev[s->copy_seq % kCopyEvents], s->copy_st) != hipSuccess)
-                return TDEC_EDEVICE;
         }
     }
     s->cv_work.notify_one();

@@ -267,3 +267,33 @@ def test_launch_ring_keeps_the_most_recent():
     assert all(r["n_tb"] == 1 and r["n_cb"] == 1 and r["cb_bits"] == 64 for r in recs)
     assert last == recs[-3:]
     assert all(b["t_start_ns"] >= a["t_end_ns"] for a, b in zip(recs, recs[1:]))
+
+
+def test_slot_arena_coalesces_after_churn():
+    """Many arrivals of mixed sizes, released batch by batch in completion
+    order, fragment the slot arena; once everything has completed the free
+    extents have merged back, so a request for the whole budget fits."""
+    budget = 6 * SLOT_MAX
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=1_000_000, slot_budget_bytes=budget)
+    srv = T.Server.model(cfg, 20_000, 0)
+    g = np.random.default_rng(3)
+    try:
+        tag, n_rej = 0, 0
+        for tti in range(60):
+            tbs = [int(x) for x in np.exp(g.uniform(np.log(16), np.log(MAX_TB), 12))]
+            k, st = _submit(srv, list(range(tag, tag + len(tbs))), tbs)
+            n_rej += int((st == T.SERVE_REJ_BUDGET).sum())
+            tag += len(tbs)
+            if tti % 3 == 2:
+                time.sleep(0.0005)
+        srv.drain(20000)
+        _collect(srv, tag, 20.0)
+        s = srv.stats()
+        assert s["slots_in_use_bytes"] == 0 and s["rej_budget"] == n_rej
+        assert s["slots_peak_bytes"] <= budget
+        k, st = _submit(srv, list(range(tag, tag + 6)), [MAX_TB] * 6)
+        assert k == 6 and (st == T.SERVE_DONE).all()
+        srv.drain(10000)
+        _collect(srv, 6)
+    finally:
+        srv.close()
