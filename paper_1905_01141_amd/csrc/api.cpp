@@ -61,7 +61,7 @@ struct tdec_ctx {
     size_t flags_cap = 0;
     uint8_t *d_encbuf = nullptr;
     size_t encbuf_bytes = 0;
-    uint32_t *d_counter = nullptr;  // work distribution counter of the decode kernel
+    uint32_t *d_counter = nullptr;  // work distribution counters of the decode kernel (kCtrBytes)
     // QPP LDS-address tables, one per (K, windows) shape, appended on first
     // use and kept for the context's lifetime; the pinned mirror is never
     // rewritten, so its asynchronous uploads need no synchronisation
@@ -670,8 +670,8 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
               hipMalloc(&c->d_ok, c->flags_cap) == hipSuccess &&
               hipMalloc(&c->d_it, c->flags_cap) == hipSuccess &&
               hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess &&
-              hipMalloc(&c->d_counter, 64) == hipSuccess &&
-              hipMemset(c->d_counter, 0, 64) == hipSuccess &&
+              hipMalloc(&c->d_counter, kCtrBytes) == hipSuccess &&
+              hipMemset(c->d_counter, 0, kCtrBytes) == hipSuccess &&
               hipMalloc(&c->d_qtab, c->qtab_cap * 2) == hipSuccess &&
               hipHostMalloc(&c->h_qtab, c->qtab_cap * 2, hipHostMallocDefault) == hipSuccess &&
               hipMalloc(&c->d_rmtab, c->rm_cap * 2) == hipSuccess &&

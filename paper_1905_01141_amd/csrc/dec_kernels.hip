@@ -357,6 +357,9 @@ __device__ void ph2_fwd(const Win &c, s2 A[4])
             if (bwd_norm(i0, t, c.W)) normalise(B);
         }
     }
+    // two segments per trip: the hand-over of the next segment's values
+    // (inputs, gammas, recomputed metrics) becomes register renaming
+#pragma unroll 2
     for (; i0 < last; i0 += S) {
         const int i1 = i0 + S;
         load_seg(c, min(i1 + S, last), rnn);
@@ -421,6 +424,9 @@ __device__ void ph2_bwd(const Win &c, s2 B[4])
             fwd_post(A, i0, t, c.first);
         }
     }
+    // two segments per trip: the hand-over of the next segment's values
+    // (inputs, gammas, recomputed metrics) becomes register renaming
+#pragma unroll 2
     for (; i0 > 0; i0 -= S) {
         const int i1 = i0 - S;
         load_seg(c, max(i1 - S, 0), rnn);
@@ -496,6 +502,53 @@ __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, 
 // a few spills remain in the phase-1 loop heads).  UNEVEN: some item's last
 // window is shorter than the others, so window lengths are per lane; the
 // even instantiation keeps them uniform (scalar loop bounds).
+// Four consecutive int16 LLRs (8 bytes); the address is 8-byte aligned when
+// the block's offset is a multiple of 4 elements.
+__device__ __forceinline__ uint2 load4(const int16_t *p, bool aligned)
+{
+    if (aligned) return *(const uint2 *)p;
+    return make_uint2((uint16_t)p[0] | ((uint32_t)(uint16_t)p[1] << 16),
+                      (uint16_t)p[2] | ((uint32_t)(uint16_t)p[3] << 16));
+}
+
+// One restaged unit: 4 steps starting at natural position pos, from the
+// systematic, parity 1 and parity 2 LLRs v[0..2] (4 int16 each) and the two
+// QPP address pairs q.  Clamps to +-2047, overrides filler positions (known
+// zeros: -2047 on systematic and parity 1), and writes decoder 1's word
+// Lp1 | Ls << 16 and decoder 2's word Lp2 | LDS address << 16 per step.
+__device__ __forceinline__ void restage_unit(const uint2 v[3], uint2 q, int pos, int F,
+                                             uint32_t so2, uint4 *r1, uint4 *r2)
+{
+    const s2 lo = (s2){(short)-kLlrMax, (short)-kLlrMax};
+    const s2 hi = (s2){(short)kLlrMax, (short)kLlrMax};
+    uint32_t ls[2], lp[2], z[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        ls[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[0].y : v[0].x), hi), lo));
+        lp[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[1].y : v[1].x), hi), lo));
+        z[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[2].y : v[2].x), hi), lo));
+    }
+    if (pos < F) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (pos + j < F) {
+                const uint32_t msk = 0xFFFFu << (16 * (j & 1));
+                const uint32_t neg = 0xF801F801u & msk;  // -2047 in that half
+                ls[j >> 1] = (ls[j >> 1] & ~msk) | neg;
+                lp[j >> 1] = (lp[j >> 1] & ~msk) | neg;
+            }
+    }
+    const uint32_t qa0 = q.x + so2, qa1 = q.y + so2;
+    *r1 = make_uint4(__builtin_amdgcn_perm(ls[0], lp[0], 0x05040100u),
+                     __builtin_amdgcn_perm(ls[0], lp[0], 0x07060302u),
+                     __builtin_amdgcn_perm(ls[1], lp[1], 0x05040100u),
+                     __builtin_amdgcn_perm(ls[1], lp[1], 0x07060302u));
+    *r2 = make_uint4(__builtin_amdgcn_perm(qa0, z[0], 0x05040100u),
+                     __builtin_amdgcn_perm(qa0, z[0], 0x07060302u),
+                     __builtin_amdgcn_perm(qa1, z[1], 0x05040100u),
+                     __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
+}
+
 template <bool UNEVEN>
 __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs a)
 {
@@ -515,9 +568,20 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
     char *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
 
     // Items are handed out dynamically: every work group starts with item
-    // blockIdx.x and then takes the next unclaimed one from a counter, so
-    // blocks that stop early free their work group for more work.  The last
-    // work group to finish resets the counter for the next launch.
+    // blockIdx.x and then claims the next unclaimed one, so blocks that stop
+    // early free their work group for more work.  The claims are spread over
+    // nset = min(8, grid) counters (one per XCD under round-robin dispatch),
+    // each on its own 256-byte line: work group b belongs to set
+    // xc = b % nset, whose items are xc, xc + nset, xc + 2 nset, ...; the
+    // first gx of them start the set's gx work groups, the rest are claimed.
+    // A single counter serialised the claims of all work groups, which all
+    // finish their first item at about the same time.  The last work group
+    // of a set to finish resets that set's counters for the next launch.
+    const int nset = min((int)gridDim.x, kCtrSets);
+    const int xc = (int)blockIdx.x % nset;
+    const int gx = ((int)gridDim.x - xc + nset - 1) / nset;
+    uint32_t *ctr_item = a.counter + xc * kCtrStride;
+    uint32_t *ctr_done = a.counter + (kCtrSets + xc) * kCtrStride;
     __shared__ int s_next;
     for (int item_i = blockIdx.x; item_i < a.n_items; item_i = s_next) {
         const DecItem it = a.items[item_i];
@@ -532,16 +596,20 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         uint4 *bnd = ck + (int64_t)(W / S) * lanes;              // [4][lanes]
 
         // ---- restage the channel LLRs, clear LDS.  One unit = 4 trellis
-        // steps of one window; consecutive threads take consecutive windows,
-        // so every 16-byte store is part of a contiguous run; each thread
-        // keeps 4 units of loads in flight.
+        // steps of one window, written as one 16-byte word per decoder at
+        // [t/4][window] so that the iterations read it coalesced.
         {
             const int esz = lds_e_bytes(K);
-            // nw * W/4 units: the last window may be shorter than W, and the
-            // units past K (pad of the last window) are written as zeros
-            const int units = (nw * W) >> 2;
             const uint2 *qt = (const uint2 *)(a.qtab + it.qtab);
             uint4 *R1v = (uint4 *)R1, *R2v = (uint4 *)R2;
+            // Tiled form: a chunk of 4R steps of every window and stream is
+            // read with contiguous loads into LDS (the item's extrinsic slots,
+            // unused until the iterations), then turned into units with
+            // consecutive threads on consecutive windows.  Rows of R uint2
+            // plus one of padding; R is a power of two that fits.
+            const int maxR = (ncb * it.lds_slot) / (24 * nw) - 1;
+            int R = 0;
+            for (int r = 1; r <= 32 && r <= maxR && 4 * r <= W; r <<= 1) R = r;
             for (int cs = 0; cs < ncb; ++cs) {
                 const DecCb cb = a.cbs[it.cb0 + cs];
                 const int16_t *src = a.llr + cb.llr_off;
@@ -549,67 +617,74 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 const bool aligned = (cb.llr_off & 3) == 0;
                 const uint32_t so = (uint32_t)(cs * it.lds_slot);
                 const uint32_t so2 = so | (so << 16);
-                for (int u0 = tid; u0 < units; u0 += 4 * nthr) {
-                    uint2 v[4][3], q[4];
-                    int pos[4];
+                if (R > 0) {
+                    uint2 *tile = (uint2 *)lds;
+                    const int lg = __builtin_ctz((unsigned)R), rs = R + 1, nl = nw * R;
+                    for (int c0 = 0; c0 < W; c0 += 4 * R) {
+                        const int Rc = min(R, (W - c0) >> 2);
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int u = min(u0 + m * nthr, units - 1);
-                        const int t4 = u / nw, ww = u - t4 * nw;
-                        const int p = ww * W + 4 * t4;
-                        pos[m] = p;
-                        q[m] = qt[u];
-                        if (p >= K) {  // pad of a shorter last window: no input
-                            v[m][0] = v[m][1] = v[m][2] = make_uint2(0u, 0u);
-                        } else if (aligned) {
-                            v[m][0] = *(const uint2 *)(src + p);
-                            v[m][1] = *(const uint2 *)(src + N + p);
-                            v[m][2] = *(const uint2 *)(src + 2 * N + p);
-                        } else {
+                        for (int st = 0; st < 3; ++st) {
+                            for (int e0 = tid; e0 < nl; e0 += 4 * nthr) {
+                                uint2 v[4];
 #pragma unroll
-                            for (int st = 0; st < 3; ++st) {
-                                const int16_t *s0 = src + st * N + p;
-                                v[m][st] = make_uint2((uint16_t)s0[0] | ((uint32_t)(uint16_t)s0[1] << 16),
-                                                      (uint16_t)s0[2] | ((uint32_t)(uint16_t)s0[3] << 16));
+                                for (int m = 0; m < 4; ++m) {
+                                    const int e = e0 + m * nthr;
+                                    const int ww = e >> lg, j = e & (R - 1);
+                                    const int p = ww * W + c0 + 4 * j;
+                                    v[m] = make_uint2(0u, 0u);
+                                    if (e < nl && j < Rc && p < K)
+                                        v[m] = load4(src + st * N + p, aligned);
+                                }
+#pragma unroll
+                                for (int m = 0; m < 4; ++m) {
+                                    const int e = e0 + m * nthr;
+                                    const int ww = e >> lg, j = e & (R - 1);
+                                    if (e < nl && j < Rc) tile[(st * nw + ww) * rs + j] = v[m];
+                                }
                             }
                         }
+                        __syncthreads();
+                        for (int e = tid; e < nw * Rc; e += nthr) {
+                            const int jj = e / nw, ww = e - jj * nw;
+                            const int t4 = (c0 >> 2) + jj;
+                            const uint2 v[3] = {tile[ww * rs + jj], tile[(nw + ww) * rs + jj],
+                                                tile[(2 * nw + ww) * rs + jj]};
+                            restage_unit(v, qt[t4 * nw + ww], ww * W + 4 * t4, cb.F, so2,
+                                         R1v + (size_t)t4 * lanes + cs * nw + ww,
+                                         R2v + (size_t)t4 * lanes + cs * nw + ww);
+                        }
+                        __syncthreads();
                     }
+                } else {
+                    // direct form (items too small for a tile): consecutive
+                    // threads take consecutive windows; 4 units of loads in flight
+                    const int units = (nw * W) >> 2;
+                    for (int u0 = tid; u0 < units; u0 += 4 * nthr) {
+                        uint2 v[4][3], q[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int u = u0 + m * nthr;
-                        if (u >= units) break;
-                        const int t4 = u / nw, ww = u - t4 * nw;
-                        const s2 lo = (s2){(short)-kLlrMax, (short)-kLlrMax};
-                        const s2 hi = (s2){(short)kLlrMax, (short)kLlrMax};
-                        uint32_t ls[2], lp[2], z[2];
+                        for (int m = 0; m < 4; ++m) {
+                            const int u = min(u0 + m * nthr, units - 1);
+                            const int t4 = u / nw, ww = u - t4 * nw;
+                            const int p = ww * W + 4 * t4;
+                            q[m] = qt[u];
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            ls[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][0].y : v[m][0].x), hi), lo));
-                            lp[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][1].y : v[m][1].x), hi), lo));
-                            z[h] = as_u(vmax(__builtin_elementwise_min(as_s2(h ? v[m][2].y : v[m][2].x), hi), lo));
+                            for (int st = 0; st < 3; ++st)
+                                v[m][st] = p < K ? load4(src + st * N + p, aligned) : make_uint2(0u, 0u);
                         }
-                        if (pos[m] < cb.F) {  // filler: systematic and parity 1 are known zeros
 #pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                if (pos[m] + j < cb.F) {
-                                    const uint32_t msk = 0xFFFFu << (16 * (j & 1));
-                                    const uint32_t neg = 0xF801F801u & msk;  // -2047 in that half
-                                    ls[j >> 1] = (ls[j >> 1] & ~msk) | neg;
-                                    lp[j >> 1] = (lp[j >> 1] & ~msk) | neg;
-                                }
+                        for (int m = 0; m < 4; ++m) {
+                            const int u = u0 + m * nthr;
+                            if (u >= units) break;
+                            const int t4 = u / nw, ww = u - t4 * nw;
+                            restage_unit(v[m], q[m], ww * W + 4 * t4, cb.F, so2,
+                                         R1v + (size_t)t4 * lanes + cs * nw + ww,
+                                         R2v + (size_t)t4 * lanes + cs * nw + ww);
                         }
-                        const uint32_t qa0 = q[m].x + so2, qa1 = q[m].y + so2;
-                        const size_t o = (size_t)t4 * lanes + cs * nw + ww;
-                        R1v[o] = make_uint4(__builtin_amdgcn_perm(ls[0], lp[0], 0x05040100u),
-                                            __builtin_amdgcn_perm(ls[0], lp[0], 0x07060302u),
-                                            __builtin_amdgcn_perm(ls[1], lp[1], 0x05040100u),
-                                            __builtin_amdgcn_perm(ls[1], lp[1], 0x07060302u));
-                        R2v[o] = make_uint4(__builtin_amdgcn_perm(qa0, z[0], 0x05040100u),
-                                            __builtin_amdgcn_perm(qa0, z[0], 0x07060302u),
-                                            __builtin_amdgcn_perm(qa1, z[1], 0x05040100u),
-                                            __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
                     }
                 }
+            }
+            __syncthreads();  // the tile's last reads come before the clear
+            for (int cs = 0; cs < ncb; ++cs) {
                 uint32_t *slot = (uint32_t *)(lds + (int64_t)cs * it.lds_slot);
                 for (int q = tid; q < esz / 4; q += nthr) slot[q] = 0;
             }
@@ -767,15 +842,15 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             }
         }
         __syncthreads();
-        if (tid == 0) s_next = (int)gridDim.x + (int)atomicAdd(&a.counter[0], 1u);
+        if (tid == 0) s_next = xc + nset * (gx + (int)atomicAdd(ctr_item, 1u));
         __syncthreads();
     }
-    if (tid == 0) {
-        __threadfence();
-        if (atomicAdd(&a.counter[1], 1u) == gridDim.x - 1) {
-            atomicExch(&a.counter[0], 0u);
-            atomicExch(&a.counter[1], 0u);
-        }
+    // Every claim of this work group has returned (its last one ended the
+    // loop) before it counts itself done, so the last of the set resets the
+    // set's counters after all of the set's claims.
+    if (tid == 0 && atomicAdd(ctr_done, 1u) == (uint32_t)gx - 1) {
+        atomicExch(ctr_item, 0u);
+        atomicExch(ctr_done, 0u);
     }
 }
 

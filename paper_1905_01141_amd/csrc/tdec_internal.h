@@ -54,6 +54,13 @@ struct DecCb {
     int8_t rsv;
 };
 
+// Work distribution counters of the decode kernel: kCtrSets sets of work
+// groups, a claim counter and a done counter per set, each on its own
+// 256-byte line.
+constexpr int kCtrSets = 8;
+constexpr int kCtrStride = 64;  // uint32 words
+constexpr int kCtrBytes = 2 * kCtrSets * kCtrStride * 4;
+
 struct DecArgs {
     const DecItem *items;
     int32_t n_items;
@@ -66,7 +73,8 @@ struct DecArgs {
     const uint32_t *crc_tab;  // [2][kCrcTabN]: 24A then 24B
     char *scratch;
     int64_t scratch_stride;   // bytes of global scratch per work group
-    uint32_t *counter;        // [2]: next item, finished work groups (zero between launches)
+    uint32_t *counter;        // kCtrSets claim counters then kCtrSets done counters, one
+                              // per kCtrStride words (zero between launches)
     // QPP address tables, one per (K, windows) shape: for unit u = t4 * nw + w
     // (4 trellis steps of window w) the LDS byte offsets 2 * epad(pi(k)),
     // k = w * W + 4 * t4 + j, j = 0..3, relative to the block's slot
