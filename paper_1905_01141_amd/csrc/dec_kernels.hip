@@ -466,8 +466,15 @@ __device__ void ph2_bwd(const Win &c, s2 B[4])
     }
 }
 
-// Hard decision of natural position j: the low bit of E after decoder 2.
-__device__ __forceinline__ uint32_t hard_bit(const short *E, int j) { return (uint32_t)E[epad(j)] & 1u; }
+// Hard decisions (the low bit of E after decoder 2) of the 8 positions g..g+7 (g a multiple of 8, g + 7 < K),
+// MSB first, from one 16-byte LDS read: position g + 2i is the low half of
+// word i, g + 2i + 1 its high half.
+__device__ __forceinline__ uint32_t hard8(const short *E, int g)
+{
+    const uint4 v = *(const uint4 *)(E + epad(g));
+    return ((v.x & 1u) << 7) | ((v.x >> 10) & 0x40u) | ((v.y & 1u) << 5) | ((v.y >> 12) & 0x10u) |
+           ((v.z & 1u) << 3) | ((v.z >> 14) & 0x04u) | ((v.w & 1u) << 1) | ((v.w >> 16) & 0x01u);
+}
 
 // CRC (LFSR form, MSB first) of natural bits [b0, b1) of a block.
 __device__ uint32_t crc_range(const short *E, int b0, int b1, uint32_t poly)
@@ -487,12 +494,17 @@ __device__ uint32_t crc_range(const short *E, int b0, int b1, uint32_t poly)
     return r;
 }
 
-// r(x) * x^n mod g from the table T[m] = x^m mod g.
+// r(x) * x^n mod g from the table T[m] = x^m mod g (n + 23 < kCrcTabN).
+// All 24 entries are loaded unconditionally, so the loads go out together
+// instead of one round trip per set bit of r.
 __device__ uint32_t crc_shift(uint32_t r, int n, const uint32_t *T)
 {
+    uint32_t t[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) t[i] = T[n + i];
     uint32_t o = 0;
-    for (int i = 0; i < 24; ++i)
-        if ((r >> i) & 1u) o ^= T[n + i];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) o ^= ((r >> i) & 1u) ? t[i] : 0u;
     return o;
 }
 
@@ -818,21 +830,27 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 const int nbytes = (nbits + 7) >> 3;
                 uint8_t *out = a.bits + cb.bits_off;
                 for (int bb = w; bb < nbytes; bb += nw) {
+                    // positions pos .. pos + valid - 1 (all < K - L)
                     const int pos = cb.F + 8 * bb;
                     const int valid = min(8, nbits - 8 * bb);
-                    uint32_t byte = 0;
-                    for (int k = 0; k < 8; ++k)
-                        byte = (byte << 1) | (k < valid ? hard_bit(c.E, pos + k) : 0u);
-                    out[bb] = (uint8_t)byte;
+                    const int g = pos & ~7, o = pos & 7;
+                    uint32_t byte = hard8(c.E, g);
+                    if (o) {
+                        const uint32_t nx = o + valid > 8 ? hard8(c.E, g + 8) : 0u;
+                        byte = ((byte << 8) | nx) >> (8 - o);
+                    }
+                    out[bb] = (uint8_t)(byte & (0xFFu << (8 - valid)));
                 }
             }
             if (cb.hard_off >= 0 && a.hard) {
                 uint32_t *h = a.hard + cb.hard_off;
                 const int hw = (int)hard_words(K);
                 for (int q = w; q < hw; q += nw) {
+                    // K is a multiple of 8: a group of 8 is all inside or all past K
                     uint32_t v = 0;
-                    for (int k = 0; k < 32; ++k)
-                        v = (v << 1) | (32 * q + k < K ? hard_bit(c.E, 32 * q + k) : 0u);
+#pragma unroll
+                    for (int k = 0; k < 32; k += 8)
+                        v = (v << 8) | (32 * q + k < K ? hard8(c.E, 32 * q + k) : 0u);
                     h[q] = v;
                 }
             }
