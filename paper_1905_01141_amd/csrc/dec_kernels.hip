@@ -26,9 +26,13 @@
 //     LDS addresses of the QPP permutation precomputed once per block;
 //   * the channel LLRs are restaged once per block into a window-interleaved
 //     layout in global scratch (one 16-byte load = 4 trellis steps of one
-//     lane, the lanes of a wave reading consecutive 16-byte pieces);
-//   * hard decisions are OR-ed into an LDS bitmap, the CRC is a per-window
-//     LFSR combined across windows with x^n mod g tables.
+//     lane, the lanes of a wave reading consecutive 16-byte pieces), through
+//     an LDS tile so that the planar input is read contiguously too;
+//   * hard decisions ride in the low bit of decoder 2's output in the LDS
+//     array; the CRC is a per-window LFSR combined across windows with
+//     x^n mod g tables;
+//   * a persistent grid takes work items dynamically, the claims spread over
+//     one counter per set of work groups.
 //
 // Metric layouts: "P" = {(m0,m4),(m1,m5),(m2,m6),(m3,m7)},
 // "Q" = {(m0,m1),(m2,m3),(m4,m5),(m6,m7)} with state s = 4 a_{k-1} +
