@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--ttis", type=int, default=3000, help="serving/cells: measured TTIs")
     ap.add_argument("--mode", default="continuous", choices=["continuous", "per-tb"],
                     help="serving: batching form")
+    ap.add_argument("--min-w", type=int, default=0,
+                    help="mixed/serving/cells: shortest window the autotuner may choose, in steps "
+                         "(0: 32 for the mixed TTIs, 64 for serving and cells)")
     ap.add_argument("--windows", default="tuned", choices=["tuned", "rule"],
                     help="serving/cells: autotuned window counts (latency objective) or the "
                          "library's built-in rule")

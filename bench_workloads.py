@@ -156,7 +156,7 @@ def run_mixed(args):
     log(f"[mixed] {n_tti} TTIs x {ues} UEs: {n_cb / n_tti:.1f} CBs and "
         f"{kbits / n_tti / 1e3:.0f} kbit per TTI, {len(Ks)} sizes; autotuning")
     t0 = time.perf_counter()
-    choice = D.autotune(Ks, min_W=64, max_iters=8, batch_bits=0)
+    choice = D.autotune(Ks, min_W=min_w(args, 32), max_iters=8, batch_bits=0)
     tune_s = time.perf_counter() - t0
     x = torch.from_numpy(llr).cuda()
     p = T.params(8, 1, 0, 1)
@@ -223,7 +223,8 @@ def run_mixed(args):
             "data": "synthetic",
             "config": {"workload": f"{n_tti} TTIs x {ues} TBs, log-uniform TBS 16..75376, "
                                    "QPSK/16QAM/64QAM, Es/N0 U[0,18] dB, <= 8 iterations + CRC "
-                                   "stop, autotuned windows (latency objective, W >= 64)"},
+                                   f"stop, autotuned windows (latency objective, W >= "
+                                   f"{min_w(args, 32)})"},
             "per_tti": {"cbs": round(n_cb / n_tti, 1), "kbit": round(kbits / n_tti / 1e3, 1),
                         "latency_ms_p50": round(pct(lat, 0.5), 4),
                         "latency_ms_p99": round(pct(lat, 0.99), 4)},
@@ -231,7 +232,9 @@ def run_mixed(args):
             "mean_iters": round(float(np.mean(iters)), 3),
             "direct_calls_gbit_s": round(payload / wall_direct / 1e9, 4),
             "autotune_s": round(tune_s, 2),
-            "windows": {str(K): choice[K][0] for K in (40, 1024, 2048, 4096, 6144) if K in choice}}
+            "windows": {str(K): choice[K][0] for K in (40, 120, 504, 1024, 2048, 4096, 6144)
+                        if K in choice},
+            "max_window_steps": max(T.win_len(K, choice[K][0]) for K in choice)}
     log(f"[mixed] {line}")
     return line
 
@@ -352,15 +355,22 @@ def serving_pool(D, torch, n, mod, lo_db, hi_db, seed, fixed_tbs=None):
     return d, np.array(tbs, np.int32), ptrs, pays, h2d
 
 
-def tune_windows(D, args, Ks, iters, batch_bits=0):
+def min_w(args, default):
+    """The shortest window the autotuner may choose: --min-w, else the
+    workload's default.  Shorter windows cut latency and cost a little error
+    rate (window edges); the mixed workload reports both."""
+    return args.min_w if getattr(args, "min_w", 0) else default
+
+
+def tune_windows(D, args, Ks, iters, batch_bits=0, default_min_w=64):
     """Autotune window counts: batch_bits = 0 times one block per size (the
     latency objective), batch_bits > 0 times a launch of that many code block
     bits (the throughput objective)."""
     if args.windows != "tuned":
         return {}
     t0 = time.perf_counter()
-    ch = D.autotune(sorted(set(int(k) for k in Ks)), min_W=64, max_iters=iters,
-                    batch_bits=batch_bits)
+    ch = D.autotune(sorted(set(int(k) for k in Ks)), min_W=min_w(args, default_min_w),
+                    max_iters=iters, batch_bits=batch_bits)
     log(f"[tune] {len(ch)} sizes in {time.perf_counter() - t0:.1f} s: {ch}")
     return ch
 
@@ -369,7 +379,10 @@ def run_serving(args):
     import torch
     D = T.Decoder(0, 2 << 30)
     h, ptbs, ptrs, _, h2d = serving_pool(D, torch, 2048, "64qam", 12.0, 22.0, 0)
-    tune_windows(D, args, [k for t in set(ptbs.tolist()) for k, _ in T.cb_sizes(int(t))], 8)
+    # launches hold hundreds to thousands of TBs here, so windows shorter than
+    # 64 steps cost more in throughput than they save in latency
+    tune_windows(D, args, [k for t in set(ptbs.tolist()) for k, _ in T.cb_sizes(int(t))], 8,
+                 default_min_w=64)
     mean_tbs = float(np.mean(ptbs))
     lam1 = 40 * MAX_TB / mean_tbs  # TBs per TTI at rho = 1 (40 cells at full load)
     rows = []
@@ -404,6 +417,7 @@ def run_serving(args):
                                    "8 GB slot budget, pool of 2048 distinct TBs resident in "
                                    "device memory",
                        "mode": args.mode, "ttis": args.ttis, "windows": args.windows,
+                       "min_window_steps": min_w(args, 64),
                        "pool_h2d_gbit_s": round(8 * h2d, 1)},
             "rows": rows}
 
@@ -414,7 +428,7 @@ def run_cells(args):
     # before the calibration (windows change error rates); at capacity a
     # launch holds ~160 TBs = 2080 blocks, so the count is tuned for throughput
     # at that size
-    tune_windows(D, args, [5824], 8, batch_bits=CELLS_TUNE_CBS * 5824)
+    tune_windows(D, args, [5824], 8, batch_bits=CELLS_TUNE_CBS * 5824, default_min_w=64)
     # calibrate Es/N0 for a TB error rate near 30 % at 8 iterations (coarse:
     # 64 TBs per point, bisection to 0.1 dB)
     n_cal = 64

@@ -210,6 +210,14 @@ def segment(tbs: int) -> dict:
     return {n: getattr(s, n) for n, _ in Seg._fields_}
 
 
+def win_len(K: int, n_windows: int) -> int:
+    """Trellis steps of every window but the last for a block of K bits in
+    n_windows windows (include/tdec.h): K for one window, else
+    8 * ceil(K / (8 * n_windows))."""
+    K, n = int(K), int(n_windows)
+    return K if n == 1 else 8 * (-(-K // (8 * n)))
+
+
 def cb_sizes(tbs: int) -> list[tuple[int, int]]:
     s = segment(tbs)
     return [(s["Kminus"] if r < s["Cminus"] else s["Kplus"], s["F"] if r == 0 else 0)
