@@ -138,3 +138,39 @@ def test_device_submission_any_source_alignment(dev, shift):
         assert res[i]["status"] == T.SERVE_DONE
         assert res[i]["tb_ok"] == ores["tb_ok"] == 1, i
         assert np.array_equal(out[i], ob), (i, tbs)
+
+
+def test_launch_records_on_the_device(dev):
+    """Launch records of a device server: one per launch, the TB and block
+    counts add up, every delay is positive, the copies back are part of the
+    post-processing, and launches do not overlap in time."""
+    T, D, torch = dev
+    tbs_list = [40, 6120, 6121, 20000, 75376, 1000]
+    say(f"[server] launch records tbs={tbs_list}")
+    llr, pays, lo, bo = tb_batch(tbs_list, "16qam", 6.0, 10)
+    out, res, st = run_server(dev, 0, tbs_list, llr, lo, T.params(6, 1, 1, 0), 3)
+    assert st["completed"] == len(tbs_list)
+    srv = T.Server(D, T.server_cfg(T.params(6, 1, 1, 0), deadline_us=10_000_000))
+    try:
+        pinned = torch.empty(llr.size, dtype=torch.int16, pin_memory=True)
+        pinned.numpy()[:] = llr
+        outs = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+        for g in np.array_split(np.arange(len(tbs_list)), 2):
+            srv.submit(g.tolist(), [tbs_list[i] for i in g],
+                       [pinned.data_ptr() + 2 * int(lo[i]) for i in g], [outs[i].ctypes.data for i in g])
+            srv.drain(60000)
+        recs = srv.launches()
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert len(recs) == s["batches"] >= 2
+    assert sum(r["n_tb"] for r in recs) == len(tbs_list)
+    assert sum(r["n_cb"] for r in recs) == sum(T.segment(t)["C"] for t in tbs_list)
+    for r in recs:
+        assert r["pre_ns"] > 0 and r["coding_ns"] > 0 and r["post_ns"] > 0
+        assert 0 <= r["copy_ns"] <= r["post_ns"]
+        assert r["t_end_ns"] - r["t_start_ns"] >= r["coding_ns"]
+    for a, b in zip(recs, recs[1:]):
+        assert b["t_start_ns"] >= a["t_end_ns"]
+    for i, t in enumerate(tbs_list):
+        assert np.array_equal(outs[i], out[i]), i
