@@ -239,6 +239,111 @@ def run_mixed(args):
     return line
 
 
+# ----------------------------------------------------------------------------- F1 / F2
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def time_launches(torch, fn, reps=20, warm=3):
+    """(device ms per launch, host ms per call) of fn() on the current stream.
+    The device time is taken between HIP events around `reps` back-to-back
+    launches that the host queued behind a short device-side spin, so the
+    host's per-call work (argument checks, plan lookup) does not leave gaps
+    between the kernels; the host time is the wall time per call."""
+    st = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(50_000_000)  # ~20 ms of device time to queue behind
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    host = (time.perf_counter() - t0) / reps * 1e3
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, host
+
+
+def run_ratematch(args):
+    """Rate matching at the uniform batch's size: 4096 blocks K=6144, E =
+    12288 (rate 1/2).  Receiver (de-rate-matching into int16 HARQ buffers,
+    int8 soft values in) for a first transmission and a combining one, and
+    the transmitter's bit selection."""
+    import torch
+    D = T.Decoder(0)
+    n, K, E = 4096, 6144, 12288
+    descs, n_llr, _ = T.make_descs([(K, 0, T.CRC24B)] * n)
+    pay = torch.from_numpy(np.packbits(wl.random_bits(wl.rng(6, 0), n * (K - 24)))).cuda()
+    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    D.cb_encode_batch(descs, pay, coded)
+    out = {}
+    for rv in (0, 2):
+        rm, ne, ns = T.make_rm_descs([(K, 0, rv, E)] * n)
+        e = torch.zeros(ne, dtype=torch.uint8, device="cuda")
+        ms_tx, h_tx = time_launches(torch, lambda: D.rate_match_batch(rm, coded, e))
+        llr8 = (e.to(torch.int16) * 80 - 40).to(torch.int8)  # noiseless soft values
+        soft = torch.zeros(ns, dtype=torch.int16, device="cuda")
+        ms_rx, h_rx = time_launches(torch, lambda: D.derate_batch(rm, llr8, soft, 1 if rv else 0))
+        out[rv] = (ms_tx, ms_rx, ns, h_tx, h_rx)
+    soft_b = 2 * 3 * (K + 4)
+    # algorithmic HBM bytes per launch: E soft values in, the int16 buffer
+    # written (first transmission) or read and written (combining); the rank
+    # table (2 B per buffer entry) is shared by all blocks of one size and
+    # counted once
+    table_b = 2 * 3 * (K + 4)
+    rx0 = n * (E + soft_b) + table_b
+    rx1 = n * (E + 2 * soft_b) + table_b
+    tx = n * (3 * (K + 4) + E) + table_b
+    ms_tx, ms_rx0, _, h_tx, h_rx0 = out[0]
+    _, ms_rx1, _, _, h_rx1 = out[2]
+    gbs = lambda b, ms: b / ms / 1e6
+    line = {"metric": "de-rate-matching with HARQ combining, GB/s", "value": round(gbs(rx1, ms_rx1), 1),
+            "unit": "GB/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int16",
+            "data": "synthetic (GPU encoder output, noiseless int8 soft values)",
+            "config": {"workload": f"{n} code blocks K={K}, E={E} (rate 1/2), int8 soft values "
+                                   "into int16 [3][K+4] HARQ buffers; rv 0 (clears) then rv 2 "
+                                   "(adds)"},
+            "roofline": {"bound": "hbm", "achieved": round(gbs(rx1, ms_rx1), 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs(rx1, ms_rx1) / HBM_PEAK_GBS, 4), "traffic": None},
+            "kernels_us": {"derate_rv0": round(ms_rx0 * 1e3, 1), "derate_rv2_combine": round(ms_rx1 * 1e3, 1),
+                           "rate_match_tx": round(ms_tx * 1e3, 1)},
+            "gb_s": {"derate_rv0": round(gbs(rx0, ms_rx0), 1), "derate_rv2_combine": round(gbs(rx1, ms_rx1), 1),
+                     "rate_match_tx": round(gbs(tx, ms_tx), 1)},
+            "algorithmic_bytes": {"derate_rv0": rx0, "derate_rv2_combine": rx1, "rate_match_tx": tx},
+            "host_us_per_call": {"derate_rv0": round(h_rx0 * 1e3, 1),
+                                 "derate_rv2_combine": round(h_rx1 * 1e3, 1),
+                                 "rate_match_tx": round(h_tx * 1e3, 1)}}
+    log(f"[ratematch] {line}")
+    return line
+
+
+def run_encode(args):
+    """The GPU turbo encoder at the uniform batch's size: 4096 blocks K=6144
+    with CRC24B attached (payload bits packed in, one byte per coded bit out)."""
+    import torch
+    D = T.Decoder(0)
+    n, K = 4096, 6144
+    descs, n_llr, n_bytes = T.make_descs([(K, 0, T.CRC24B)] * n)
+    pay = torch.from_numpy(np.packbits(wl.random_bits(wl.rng(6, 1), n * (K - 24)))).cuda()
+    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    ms, host = time_launches(torch, lambda: D.cb_encode_batch(descs, pay, coded))
+    byts = n * ((K - 24) // 8 + 3 * (K + 4))
+    line = {"metric": "turbo encoder, payload Gbit/s", "value": round(n * (K - 24) / ms / 1e6, 2),
+            "unit": "Gbit/s", "higher_is_better": True, "n_gpus": 1, "dtype": "u8",
+            "data": "synthetic (random payload)",
+            "config": {"workload": f"{n} code blocks K={K}: CRC24B attach, two RSC encoders with "
+                                   "QPP interleaving, trellis termination"},
+            "kernel_us": round(ms * 1e3, 1), "host_us_per_call": round(host * 1e3, 1),
+            "roofline": {"bound": "hbm", "achieved": round(byts / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+                         "traffic": None},
+            "algorithmic_bytes": byts}
+    log(f"[encode] {line}")
+    return line
+
+
 # ----------------------------------------------------------------------------- c4 / c5
 def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admission,
           deadline_us=3000, budget=8 << 30, seed=0):

@@ -259,6 +259,19 @@ def make_descs(cbs) -> tuple[ct.Array, int, int]:
     return descs, llr_off, bits_off
 
 
+# tdec_rm_desc as a numpy record (same layout)
+RM_DESC_DTYPE = np.dtype([("e_off", "<i8"), ("soft_off", "<i8"), ("K", "<i4"), ("F", "<i2"),
+                          ("rv", "i1"), ("rsv", "i1"), ("E", "<i4"), ("Ncb", "<i4")])
+
+
+def _rm_extent(descs):
+    """(transmitted values, soft-buffer elements) a rate matching descriptor
+    array reaches, vectorised."""
+    v = np.frombuffer(descs, dtype=RM_DESC_DTYPE, count=len(descs))
+    K = v["K"].astype(np.int64)
+    return int((v["e_off"] + v["E"]).max()), int((v["soft_off"] + 3 * (K + 4)).max())
+
+
 def _desc_extent(descs):
     """(LLR elements, payload bytes) a descriptor array reaches, vectorised."""
     if len(descs) == 0:
@@ -397,8 +410,7 @@ class Decoder:
         tensor of [3][K+4] soft buffers (HARQ state)."""
         if len(descs) == 0:
             return
-        ne = max(int(d.e_off) + int(d.E) for d in descs)
-        ns = max(int(d.soft_off) + 3 * (int(d.K) + 4) for d in descs)
+        ne, ns = _rm_extent(descs)
         eb = {"torch.int8": 1, "torch.int16": 2}.get(str(e.dtype))
         if eb is None:
             raise ValueError("e: int8 or int16 tensor expected")
@@ -411,8 +423,7 @@ class Decoder:
     def rate_match_batch(self, descs, coded, e, stream=None):
         if len(descs) == 0:
             return
-        ne = max(int(d.e_off) + int(d.E) for d in descs)
-        nc = max(int(d.soft_off) + 3 * (int(d.K) + 4) for d in descs)
+        ne, nc = _rm_extent(descs)
         _need(coded, "uint8", nc, "coded")
         _need(e, "uint8", ne, "e")
         _check("tdec_rate_match_batch",

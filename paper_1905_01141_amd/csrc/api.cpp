@@ -41,6 +41,7 @@ struct PlanSlot {
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
     int asm_words = 0;  // largest (B + 31) / 32 of the plan's transport blocks
+    int max_k = 0;      // rate matching plans: the largest K
     int state_slots = 1;  // most blocks of any item
     bool uneven = false;  // some item's last window is shorter
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
@@ -1009,6 +1010,7 @@ static tdec_status rm_plan(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc, c
         if (sizeof(RmItem) * (size_t)n > kPlanSlotBytes) return TDEC_ENOMEM;
         std::vector<char> blob(sizeof(RmItem) * (size_t)n);
         RmItem *items = (RmItem *)blob.data();
+        int max_k = 0;
         for (int32_t i = 0; i < n; ++i) {
             const tdec_rm_desc &d = desc[i];
             const int32_t kw = 3 * 32 * ((d.K + 4 + 31) / 32);
@@ -1025,8 +1027,10 @@ static tdec_status rm_plan(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc, c
             items[i].E = d.E;
             items[i].n_valid = t->n_valid;
             items[i].r0 = t->r0[d.rv];
+            max_k = std::max(max_k, d.K);
         }
         ps->n_cb = n;
+        ps->max_k = max_k;
         ps->off_items = 0;
         tdec_status s = upload(ctx, ps, key, blob, st);
         if (s != TDEC_OK) {
@@ -1050,8 +1054,8 @@ tdec_status tdec_derate_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *desc
     PlanSlot *ps;
     tdec_status s = rm_plan(ctx, n, desc, 'D', st, &ps);
     if (s != TDEC_OK) return s;
-    return launch_derate((const RmItem *)ps->d_buf, n, d_e, e_bytes, d_soft, ctx->d_rmtab, combine,
-                         st)
+    return launch_derate((const RmItem *)ps->d_buf, n, ps->max_k, d_e, e_bytes, d_soft,
+                         ctx->d_rmtab, combine, st)
                ? TDEC_EDEVICE
                : TDEC_OK;
 }
@@ -1067,7 +1071,8 @@ tdec_status tdec_rate_match_batch(tdec_ctx *ctx, int32_t n, const tdec_rm_desc *
     PlanSlot *ps;
     tdec_status s = rm_plan(ctx, n, desc, 'M', st, &ps);
     if (s != TDEC_OK) return s;
-    return launch_rate_match((const RmItem *)ps->d_buf, n, d_coded, d_e, ctx->d_rmtab, st)
+    return launch_rate_match((const RmItem *)ps->d_buf, n, ps->max_k, d_coded, d_e,
+                             ctx->d_rmtab, st)
                ? TDEC_EDEVICE
                : TDEC_OK;
 }

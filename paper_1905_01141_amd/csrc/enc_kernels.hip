@@ -7,10 +7,15 @@
 // g0 = 1 + D^2 + D^3 (feedback), g1 = 1 + D + D^3 (parity), QPP
 // interleaver, 3-step termination of each encoder.
 //
-// One work group per code block: the block's input bits are staged in LDS,
-// the block CRC is computed by per-thread LFSR chunks combined with
-// x^n mod g, then two lanes run the two (inherently serial) shift registers
-// while the others copy the systematic stream.
+// One work group of two waves per code block: the block's input bits are
+// staged in LDS, the block CRC is computed by per-thread LFSR chunks combined
+// with the x^m mod g table, and each wave runs one RSC encoder with its 64
+// lanes on 64 consecutive chunks of the block.  An RSC encoder is linear over
+// GF(2) (state s = (a_{k-1}, a_{k-2}, a_{k-3}), s' = A s + b u): every lane
+// first runs its chunk from state 0 to get the chunk's zero-state end state
+// e_j; the true start state of chunk l is the XOR over j < l of
+// A^(L (l-1-j)) e_j, with A^7 = I because 1 + D^2 + D^3 is primitive; then
+// every lane runs its chunk again from that state and writes the parity bits.
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -45,8 +50,11 @@ __device__ static inline uint32_t src_bit(const uint8_t *src, int64_t b)
 }
 
 // CRC (remainder of M(x) x^24 mod g) of bits c[0..n-1] held one per byte,
-// computed by the whole work group; result valid in every thread.
-__device__ static uint32_t block_crc(const uint8_t *c, int n, uint32_t poly, uint32_t *acc)
+// computed by the whole work group; result valid in every thread.  Each
+// thread's chunk remainder is moved to the end by r(x) x^m mod g from the
+// table T[m] = x^m mod g (m + 23 < kCrcTabN).
+__device__ static uint32_t block_crc(const uint8_t *c, int n, uint32_t poly, const uint32_t *T,
+                                     uint32_t *acc)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     if (tid == 0) *acc = 0;
@@ -59,63 +67,145 @@ __device__ static uint32_t block_crc(const uint8_t *c, int n, uint32_t poly, uin
             const uint32_t top = ((r >> 23) ^ c[b]) & 1u;
             r = ((r << 1) & 0xFFFFFFu) ^ (top ? poly : 0u);
         }
-        if (r && n - b1 > 0) r = enc_mulmod(r, enc_xpow((uint64_t)(n - b1), poly), poly);
-        if (r) atomicXor(acc, r);
+        uint32_t o = 0;
+        const int m = n - b1;
+#pragma unroll
+        for (int i = 0; i < 24; ++i) o ^= ((r >> i) & 1u) ? T[m + i] : 0u;
+        if (o) atomicXor(acc, o);
     }
     __syncthreads();
     return *acc;
 }
 
-__global__ void __launch_bounds__(64) turbo_encode_kernel(const EncCb *cbs, const uint8_t *src,
-                                                          uint8_t *out)
+// RSC state as 3 bits: bit 0 = a_{k-1}, bit 1 = a_{k-2}, bit 2 = a_{k-3}.
+// One step with input u: feedback a = u ^ a_{k-2} ^ a_{k-3}, parity
+// z = a ^ a_{k-1} ^ a_{k-3}.
+__device__ static inline uint32_t rsc_step(uint32_t s, uint32_t u, uint32_t *z)
+{
+    const uint32_t a1 = s & 1u, a2 = (s >> 1) & 1u, a3 = (s >> 2) & 1u;
+    const uint32_t a = u ^ a2 ^ a3;
+    *z = a ^ a1 ^ a3;
+    return a | (a1 << 1) | (a2 << 2);
+}
+
+// A^p s: p zero-input steps.
+__device__ static inline uint32_t rsc_zero_steps(uint32_t s, int p)
+{
+    uint32_t z;
+    for (int i = 0; i < p; ++i) s = rsc_step(s, 0u, &z);
+    return s;
+}
+
+constexpr int kEncThreads = 128;  // two waves: encoder 1 and encoder 2
+
+__global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *cbs,
+                                                                   const uint8_t *src,
+                                                                   uint8_t *out,
+                                                                   const uint32_t *crc_tab)
 {
     __shared__ uint8_t c[kKmax];
     __shared__ uint8_t z[2][kKmax];
     __shared__ uint8_t tl[2][6];
+    __shared__ uint8_t es[2][64];
     __shared__ uint32_t acc;
+    __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
     const EncCb cb = cbs[blockIdx.x];
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int k = tid; k < K; k += nthr) {
-        uint8_t v = 0;
-        if (k >= F && k < K - L) v = (uint8_t)src_bit(src, cb.src_bit + (k - F));
-        c[k] = v;
+    // input bits, one per byte; 8 loads in flight per thread
+    for (int k0 = tid; k0 < K; k0 += 8 * nthr) {
+        uint8_t v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int k = k0 + m * nthr;
+            v[m] = (k >= F && k < K - L) ? (uint8_t)src_bit(src, cb.src_bit + (k - F)) : (uint8_t)0;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (k0 + m * nthr < K) c[k0 + m * nthr] = v[m];
     }
+    if (tid < 56) zt[tid >> 3][tid & 7] = (uint8_t)rsc_zero_steps((uint32_t)(tid & 7), tid >> 3);
     __syncthreads();
     if (L) {
-        const uint32_t p = block_crc(c, K - L, cb.crc == 1 ? kPoly24A : kPoly24B, &acc);
+        const uint32_t p = block_crc(c, K - L, cb.crc == 1 ? kPoly24A : kPoly24B,
+                                     crc_tab + (cb.crc == 1 ? 0 : kCrcTabN), &acc);
         if (tid < 24) c[K - 24 + tid] = (uint8_t)((p >> (23 - tid)) & 1u);
         __syncthreads();
     }
-    if (tid < 2) {
-        // shift register (a_{k-1}, a_{k-2}, a_{k-3})
-        uint32_t a1 = 0, a2 = 0, a3 = 0;
-        uint32_t pi = 0, g = (uint32_t)((cb.f1 + cb.f2) % K);
-        const uint32_t f2x2 = (uint32_t)((2 * cb.f2) % K);
-        for (int k = 0; k < K; ++k) {
-            uint32_t u;
-            if (tid == 0) {
-                u = c[k];
+    // wave w runs encoder w + 1 (w = 1: input c'_k = c_{pi(k)}); lane l the
+    // steps [l Lc, min(K, (l + 1) Lc))
+    const int w = tid >> 6, l = tid & 63;
+    const int Lc = (K + 63) / 64;
+    const int k0 = l * Lc, k1 = min(K, k0 + Lc);
+    const uint32_t uK = (uint32_t)K;
+    // QPP pi(k0) = (f1 k0 + f2 k0^2) mod K and its increment
+    // g(k0) = pi(k0 + 1) - pi(k0) = f1 + f2 (2 k0 + 1) mod K
+    const uint32_t pi0 = ((uint32_t)cb.f1 * (uint32_t)k0 % uK +
+                          (uint32_t)cb.f2 * ((uint32_t)k0 * (uint32_t)k0 % uK) % uK) % uK;
+    const uint32_t g0 = ((uint32_t)cb.f1 + (uint32_t)cb.f2 * (2u * (uint32_t)k0 + 1u)) % uK;
+    const uint32_t f2x2 = (2u * (uint32_t)cb.f2) % uK;
+    // The chunk's inputs, 8 steps at a time: the 8 reads go out before the
+    // serial steps use them.
+    auto inputs8 = [&](int k, uint32_t &pi, uint32_t &g, uint32_t u[8]) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (w == 0) {
+                u[m] = k + m < k1 ? c[k + m] : 0u;
             } else {
-                u = c[pi];  // c'_k = c_{pi(k)}
+                u[m] = k + m < k1 ? c[pi] : 0u;
                 pi += g;
-                if (pi >= (uint32_t)K) pi -= K;
+                if (pi >= uK) pi -= uK;
                 g += f2x2;
-                if (g >= (uint32_t)K) g -= K;
+                if (g >= uK) g -= uK;
             }
-            const uint32_t a = u ^ a2 ^ a3;
-            z[tid][k] = (uint8_t)(a ^ a1 ^ a3);
-            a3 = a2;
-            a2 = a1;
-            a1 = a;
         }
-        for (int j = 0; j < 3; ++j) {  // termination: input = feedback, a = 0
-            const uint32_t u = a2 ^ a3;
-            tl[tid][2 * j] = (uint8_t)u;
-            tl[tid][2 * j + 1] = (uint8_t)(a1 ^ a3);
-            a3 = a2;
-            a2 = a1;
-            a1 = 0;
+    };
+    // pass 1: end state of the chunk from state 0
+    uint32_t s = 0, zz;
+    {
+        uint32_t pi = pi0, g = g0, u[8];
+        for (int k = k0; k < k1; k += 8) {
+            inputs8(k, pi, g, u);
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (k + m < k1) s = rsc_step(s, u[m], &zz);
+        }
+    }
+    es[w][l] = (uint8_t)s;
+    __syncthreads();
+    // start state of chunk l: chunks before it all have Lc steps, chunk j
+    // contributes A^(Lc (l - 1 - j)) e_j (exponents mod 7)
+    uint32_t s0 = 0;
+    {
+        const int p = Lc % 7;
+        int q = 0;
+        for (int j = l - 1; j >= 0; --j) {
+            s0 ^= zt[q][es[w][j]];
+            q += p;
+            if (q >= 7) q -= 7;
+        }
+    }
+    // pass 2: the chunk from its true start state
+    s = s0;
+    {
+        uint32_t pi = pi0, g = g0, u[8];
+        for (int k = k0; k < k1; k += 8) {
+            inputs8(k, pi, g, u);
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (k + m < k1) {
+                    s = rsc_step(s, u[m], &zz);
+                    z[w][k + m] = (uint8_t)zz;
+                }
+        }
+    }
+    if (k0 < K && k1 == K) {
+        // termination after the last step: input = feedback, so a = 0
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t u = ((s >> 1) ^ (s >> 2)) & 1u;
+            s = rsc_step(s, u, &zz);
+            tl[w][2 * j] = (uint8_t)u;
+            tl[w][2 * j + 1] = (uint8_t)zz;
         }
     }
     __syncthreads();
@@ -136,10 +226,9 @@ __global__ void __launch_bounds__(64) turbo_encode_kernel(const EncCb *cbs, cons
 int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
                   const uint32_t *crc_tab, void *stream)
 {
-    (void)crc_tab;
     if (n_cb <= 0) return 0;
-    hipLaunchKernelGGL(turbo_encode_kernel, dim3(n_cb), dim3(64), 0, (hipStream_t)stream, cbs, src,
-                       out);
+    hipLaunchKernelGGL(turbo_encode_kernel, dim3(n_cb), dim3(kEncThreads), 0, (hipStream_t)stream,
+                       cbs, src, out, crc_tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -10,66 +10,108 @@
 
 namespace tdec {
 
-// One work group per code block.  A transmission longer than the buffer's
-// non-<NULL> entries revisits positions; it is added in chunks of one pass,
-// a barrier apart, so that saturating sums are taken in transmission order.
+// One work group per code block; the block's [3][K+4] buffer is staged in
+// LDS (read, or cleared for a first transmission, and written back once), so
+// the scattered read-modify-writes of the table walk stay on chip.  The walk
+// wraps its rank incrementally: one pass covers each non-<NULL> entry once.
+// A transmission longer than the buffer's non-<NULL> entries revisits
+// positions; it is added in chunks of one pass, a barrier apart, so that
+// saturating sums are taken in transmission order.
 template <typename T>
 __global__ void __launch_bounds__(256) derate_kernel(const RmItem *items, const T *e,
                                                      int16_t *soft, const uint16_t *tab,
                                                      int combine)
 {
+    extern __shared__ __align__(16) int16_t sb[];
     const RmItem it = items[blockIdx.x];
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int n = 3 * (it.K + 4);  // even
     int16_t *s = soft + it.soft_off;
     const T *src = e + it.e_off;
     const uint16_t *t = tab + it.tab_off;
-    if (!combine) {
-        const int n = 3 * (it.K + 4);
-        for (int i = tid; i < n; i += nthr) s[i] = 0;
-        __syncthreads();
+    const bool wide = (((uintptr_t)s) & 3) == 0;
+    if (wide) {
+        uint32_t *sw = (uint32_t *)sb;
+        const uint32_t *gw = (const uint32_t *)s;
+        for (int i = tid; i < n / 2; i += nthr) sw[i] = combine ? gw[i] : 0u;
+    } else {
+        for (int i = tid; i < n; i += nthr) sb[i] = combine ? s[i] : (int16_t)0;
     }
-    for (int64_t c0 = 0; c0 < it.E; c0 += it.n_valid) {
-        const int64_t c1 = min((int64_t)it.E, c0 + it.n_valid);
-        for (int64_t k = c0 + tid; k < c1; k += nthr) {
-            int64_t r = it.r0 + k;
-            r %= it.n_valid;
+    __syncthreads();
+    const int nv = it.n_valid;
+    for (int64_t c0 = 0; c0 < it.E; c0 += nv) {
+        const int len = (int)min((int64_t)nv, (int64_t)it.E - c0);
+        for (int i = tid; i < len; i += nthr) {
+            int r = it.r0 + i;  // r0 < nv and i < nv
+            if (r >= nv) r -= nv;
             const int d = t[r];
-            const int v = (int)s[d] + (int)src[k];
-            s[d] = (int16_t)max(-32767, min(32767, v));
+            const int v = (int)sb[d] + (int)src[c0 + i];
+            sb[d] = (int16_t)max(-32767, min(32767, v));
         }
         __syncthreads();
     }
+    if (wide) {
+        uint32_t *gw = (uint32_t *)s;
+        const uint32_t *sw = (const uint32_t *)sb;
+        for (int i = tid; i < n / 2; i += nthr) gw[i] = sw[i];
+    } else {
+        for (int i = tid; i < n; i += nthr) s[i] = sb[i];
+    }
 }
 
+// One work group per code block: the block's coded bits are staged in LDS,
+// then the transmission reads them in circular-buffer order.
 __global__ void __launch_bounds__(256) rate_match_kernel(const RmItem *items, const uint8_t *coded,
                                                          uint8_t *e, const uint16_t *tab)
 {
+    extern __shared__ __align__(16) uint8_t cbits[];
     const RmItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int n = 3 * (it.K + 4);  // a multiple of 4
     const uint8_t *d = coded + it.soft_off;
     uint8_t *dst = e + it.e_off;
     const uint16_t *t = tab + it.tab_off;
-    for (int64_t k = threadIdx.x; k < it.E; k += blockDim.x)
-        dst[k] = d[t[(it.r0 + k) % it.n_valid]];
+    if ((((uintptr_t)d) & 3) == 0) {
+        const uint32_t *gw = (const uint32_t *)d;
+        uint32_t *sw = (uint32_t *)cbits;
+        for (int i = tid; i < n / 4; i += nthr) sw[i] = gw[i];
+    } else {
+        for (int i = tid; i < n; i += nthr) cbits[i] = d[i];
+    }
+    __syncthreads();
+    const int nv = it.n_valid;
+    for (int64_t c0 = 0; c0 < it.E; c0 += nv) {
+        const int len = (int)min((int64_t)nv, (int64_t)it.E - c0);
+        for (int i = tid; i < len; i += nthr) {
+            int r = it.r0 + i;
+            if (r >= nv) r -= nv;
+            dst[c0 + i] = cbits[t[r]];
+        }
+    }
 }
 
-int launch_derate(const RmItem *items, int n, const void *e, int e_bytes, int16_t *soft,
-                  const uint16_t *tab, int combine, void *stream)
+int launch_derate(const RmItem *items, int n, int max_k, const void *e, int e_bytes,
+                  int16_t *soft, const uint16_t *tab, int combine, void *stream)
 {
     if (n <= 0) return 0;
+    if (max_k < 40 || max_k > kKmax) return -1;
+    const size_t lds = (size_t)3 * (max_k + 4) * sizeof(int16_t);
     if (e_bytes == 1)
-        hipLaunchKernelGGL(derate_kernel<int8_t>, dim3(n), dim3(256), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(derate_kernel<int8_t>, dim3(n), dim3(256), lds, (hipStream_t)stream,
                            items, (const int8_t *)e, soft, tab, combine);
     else
-        hipLaunchKernelGGL(derate_kernel<int16_t>, dim3(n), dim3(256), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(derate_kernel<int16_t>, dim3(n), dim3(256), lds, (hipStream_t)stream,
                            items, (const int16_t *)e, soft, tab, combine);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_rate_match(const RmItem *items, int n, const uint8_t *coded, uint8_t *e,
+int launch_rate_match(const RmItem *items, int n, int max_k, const uint8_t *coded, uint8_t *e,
                       const uint16_t *tab, void *stream)
 {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(rate_match_kernel, dim3(n), dim3(256), 0, (hipStream_t)stream, items,
+    if (max_k < 40 || max_k > kKmax) return -1;
+    const size_t lds = (size_t)3 * (max_k + 4);
+    hipLaunchKernelGGL(rate_match_kernel, dim3(n), dim3(256), lds, (hipStream_t)stream, items,
                        coded, e, tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

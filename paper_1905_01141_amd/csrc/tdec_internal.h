@@ -140,9 +140,10 @@ struct RmItem {
     int32_t n_valid;   // non-<NULL> entries among the first Ncb of the circular buffer
     int32_t r0;        // rank of the first non-<NULL> entry at or after k0(rv)
 };
-int launch_derate(const RmItem *items, int n, const void *e, int e_bytes, int16_t *soft,
-                  const uint16_t *tab, int combine, void *stream);
-int launch_rate_match(const RmItem *items, int n, const uint8_t *coded, uint8_t *e,
+// max_k: the largest K among the items (sizes the LDS staging buffer).
+int launch_derate(const RmItem *items, int n, int max_k, const void *e, int e_bytes,
+                  int16_t *soft, const uint16_t *tab, int combine, void *stream);
+int launch_rate_match(const RmItem *items, int n, int max_k, const uint8_t *coded, uint8_t *e,
                       const uint16_t *tab, void *stream);
 // Host: the circular buffer of a block as [3][K+4] indices, -1 for <NULL>
 // (tables.cpp); returns its length 3 * 32 * ceil((K+4)/32).

@@ -202,6 +202,37 @@ def test_tb_batch_mixed(dev):
 # ------------------------------------------------------------------ encoder
 
 
+def test_encoder_parity_every_size(dev):
+    """Every one of the 188 block sizes (the chunked parallel encoder splits a
+    block into 64 chunks of ceil(K/64) steps, so chunk lengths cover every
+    residue mod 7 and the short last chunk every length), with filler and
+    each CRC type, equals the oracle's serial encoder."""
+    T, D, torch = dev
+    g = np.random.default_rng(6)
+    Ks = [int(k) for k in O.k_table()]
+    crcs = (O.CRC24B, O.CRC24A, O.CRC_NONE)
+    cbs = [(int(K), int(g.integers(0, 16)) if K >= 64 else 0, crcs[i % 3]) for i, K in enumerate(Ks)]
+    td, n_llr, n_bytes = T.make_descs(cbs)
+    pay = g.integers(0, 256, n_bytes).astype(np.uint8)
+    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    say(f"[enc] cb_encode_batch of {len(cbs)} sizes")
+    D.cb_encode_batch(td, torch.from_numpy(pay).cuda(), coded)
+    torch.cuda.synchronize()
+    got = coded.cpu().numpy()
+    for i, (K, F, crc) in enumerate(cbs):
+        L = 0 if crc == O.CRC_NONE else 24
+        bits = np.unpackbits(pay[td[i].bits_off:])[:K - F - L]
+        c = np.zeros(K, np.uint8)
+        c[F:K - L] = bits
+        if L:
+            p = O.crc24(c[:K - L], crc)
+            c[K - L:] = [(p >> (23 - j)) & 1 for j in range(24)]
+        ref = O.turbo_encode_cb(c).reshape(3, K + 4)
+        g3 = got[td[i].llr_off:td[i].llr_off + 3 * (K + 4)].reshape(3, K + 4)
+        ref[:2, :F] = 0
+        assert np.array_equal(g3, ref), (K, F, crc)
+
+
 def test_encoder_parity(dev):
     T, D, torch = dev
     g = np.random.default_rng(5)
