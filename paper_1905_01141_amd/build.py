@@ -35,7 +35,30 @@ def build(verbose: bool = False) -> str:
     if verbose and r.stderr:
         print(r.stderr)
     os.replace(tmp, LIB)
+    build_example()
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "tb_roundtrip.c")
+EXAMPLE = os.path.join(HERE, "examples", "tb_roundtrip")
+
+
+def example_cmd(out: str) -> list[str]:
+    """gcc line of the plain-C example: the public header and libtdec.so only
+    (plus the HIP runtime for device memory)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return ["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+            "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+            EXAMPLE_SRC, "-o", out, "-L", HERE, "-ltdec", "-L", os.path.join(rocm, "lib"),
+            "-lamdhip64", "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+
+
+def build_example() -> str:
+    r = subprocess.run(example_cmd(EXAMPLE + ".tmp"), capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed on the C example:\n" + r.stderr[-4000:])
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

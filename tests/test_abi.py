@@ -4,6 +4,7 @@ the oracle.  No GPU needed."""
 import ctypes as ct
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -78,3 +79,13 @@ def test_segmentation_matches_oracle_for_every_size(orc):
         if (r1 == 0) != (r2 == 0) or (r1 == 0 and bytes(s1) != bytes(s2)):
             bad += 1
     assert bad == 0
+
+
+def test_c_example_builds_against_the_header_alone(tmp_path):
+    """The C ABI is usable from plain C: the example compiles with gcc -std=c99
+    -Werror against include/tdec.h and links against libtdec.so."""
+    from paper_1905_01141_amd import build as B
+    out = str(tmp_path / "tb_roundtrip")
+    r = subprocess.run(B.example_cmd(out), capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert os.path.exists(out)
