@@ -82,8 +82,12 @@ def run_tb(args):
     res_s = torch.zeros(T.TB_RESULT_BYTES * n_stream, dtype=torch.uint8, device="cuda")
     st = torch.cuda.current_stream()
     out = {}
-    for label, nw in (("full_length", 1), ("windows", 0)):
-        p = T.params(6, 0, nw, 1 if nw != 1 else 0)
+    # full length in one window; full length through exact window boundaries
+    # (identical output, windowed latency); ordinary windows (library count,
+    # previous-iteration boundaries: an approximation)
+    for label, nw, wi in (("full_length", 1, 0), ("exact_91_windows", 91, 2),
+                          ("exact_122_windows", 122, 2), ("windows", 0, 1)):
+        p = T.params(6, 0, nw, wi)
         xd = torch.empty(n1, dtype=torch.int16, device="cuda")
         for _ in range(3):
             D.tb_decode(x[:n1], tbs, p, bits, res)
@@ -117,18 +121,21 @@ def run_tb(args):
         ok = sum(q["tb_ok"] for q in rr)
         got = np.unpackbits(bits_s.cpu().numpy()).reshape(n_stream, -1)[:, :tbs]
         errs = int(sum(np.count_nonzero(got[i] != pays[i % n_pool]) for i in range(n_stream)))
-        out[label] = {"n_windows": nw if nw else D.pick_windows(5824),
+        out[label] = {"n_windows": nw if nw else D.pick_windows(5824), "win_init": wi,
                       "latency_device_ms_p50": round(pct(dev_ms, 0.5), 4),
                       "latency_host_to_host_ms_p50": round(pct(e2e_ms, 0.5), 4),
                       "tb_ok_alone": r["tb_ok"],
                       "stream_gbit_s": round(n_stream * tbs / wall / 1e9, 4),
                       "stream_tb_ok": f"{ok}/{n_stream}", "stream_bit_errors": errs}
         log(f"[tb] {label}: {out[label]}")
-    return {"metric": "single TB latency (75376 bits, 6 iterations)",
-            "value": out["full_length"]["latency_device_ms_p50"], "unit": "ms",
+    best = min(("exact_91_windows", "exact_122_windows", "full_length"),
+               key=lambda k: out[k]["latency_device_ms_p50"])
+    return {"metric": "single TB latency (75376 bits, full-length max-log-MAP, 6 iterations)",
+            "value": out[best]["latency_device_ms_p50"], "unit": "ms",
             "higher_is_better": False, "n_gpus": 1, "dtype": "int16", "data": "synthetic",
             "config": {"workload": "one 75376-bit TB = 13 x K5824, QPSK Es/N0 2 dB, exactly 6 "
-                                   "iterations; stream of 2048 TBs (128 distinct, cycled)"},
+                                   "iterations; stream of 2048 TBs (128 distinct, cycled)",
+                       "decoder": best},
             "results": out}
 
 

@@ -34,6 +34,14 @@
  *     previous iteration of the same constituent decoder; window 0 always
  *     starts in state 0 and the last window always from the trellis
  *     termination; n_windows = 1 is exact full-length max-log-MAP;
+ *   - exact boundaries (win_init = 2): before each constituent decoder every
+ *     window computes the max-plus transfer matrices of its steps (one forward
+ *     run from each of the 8 states at its start, one backward run from each
+ *     state at its end) and a scan along the windows gives the full-length
+ *     recursions' metrics at every window boundary, so the output equals
+ *     full-length decoding (n_windows = 1) with the latency of the windows;
+ *     the transfer runs cost about 8 times the window's own forward and
+ *     backward work, so this is for latency-bound decodes, not throughput;
  *   - the CRC of a code block is checked over bits F..K-1 (the filler bits are
  *     known zeros) after each full iteration (CRC24B when the block belongs to
  *     a transport block of several blocks, CRC24A when it is the only one).
@@ -83,7 +91,9 @@ typedef struct {
                            must be non-empty; 0 = the library's choice for each K
                            (tdec_pick_windows) */
     int32_t win_init;   /* 0: windows start from zero metrics every iteration;
-                           1: from the neighbours' previous-iteration boundary metrics */
+                           1: from the neighbours' previous-iteration boundary metrics;
+                           2: from the exact boundary metrics (see below): the result
+                              equals n_windows = 1 for any window count */
 } tdec_params;
 
 /* ---------------------------------------------------------------- host-only helpers */

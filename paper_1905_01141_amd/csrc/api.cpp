@@ -44,6 +44,7 @@ struct PlanSlot {
     int max_k = 0;      // rate matching plans: the largest K
     int state_slots = 1;  // most blocks of any item
     bool uneven = false;  // some item's last window is shorter
+    bool exact = false;   // exact window boundaries (win_init = 2): transfer-run scratch
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
@@ -93,7 +94,7 @@ namespace {
 bool params_ok(const tdec_params *p)
 {
     return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
-           p->early_stop <= 1 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 1;
+           p->early_stop <= 1 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 2;
 }
 
 int32_t pick_windows(int32_t K)
@@ -202,7 +203,7 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
 // Build the decode plan (items + code block list) from a request.
 tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot &ps,
                               std::vector<char> &blob, const std::vector<TbItem> *tbs,
-                              hipStream_t st)
+                              hipStream_t st, bool exact)
 {
     // group by (K, nw), biggest blocks first, request order within a group:
     // a counting sort over the size table (a size has one window count per
@@ -285,19 +286,22 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         lds = std::max(lds, n * sb);
         max_n = std::max(max_n, n);
         const int lanes = n * nw;
+        // restaged inputs, checkpoints, boundaries, and with exact boundaries
+        // the transfer runs (2 directions x 8 states x 32 bytes per lane)
         const int64_t need = (int64_t)lanes * W * 8 + (int64_t)(W / kSeg) * lanes * 16 +
-                             (int64_t)4 * lanes * 16 + 256;
+                             (int64_t)4 * lanes * 16 + (exact ? (int64_t)lanes * 512 : 0) + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
     lds += lds_state_bytes(max_n);
     // persistent grid: as many work groups as can be resident
     int occ = 0;
-    const int64_t okey = (int64_t)wg << 33 | (int64_t)uneven << 32 | (uint32_t)lds;
+    const int64_t okey = (int64_t)wg << 34 | (int64_t)exact << 33 | (int64_t)uneven << 32 |
+                         (uint32_t)lds;
     auto oc = ctx->occ_cache.find(okey);
     if (oc != ctx->occ_cache.end()) {
         occ = oc->second;
     } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(uneven), wg,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(uneven, exact), wg,
                                                          lds) !=
                 hipSuccess ||
             occ < 1)
@@ -332,6 +336,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.lds = lds;
     ps.state_slots = max_n;
     ps.uneven = uneven;
+    ps.exact = exact;
     ps.stride = stride;
     return TDEC_OK;
 }
@@ -388,7 +393,8 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
     a.state_slots = ps->state_slots;
-    if (launch_decode(a, ps->uneven, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
+    if ((p->win_init == 2) != ps->exact) return TDEC_EINVAL;  // the plan's scratch layout
+    if (launch_decode(a, ps->uneven, ps->exact, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
     return TDEC_OK;
 }
 
@@ -399,6 +405,7 @@ std::string cb_key(int32_t n_cb, const tdec_cb_desc *desc, const tdec_params *p,
 {
     std::string key(1, 'C');
     key.append((const char *)&p->n_windows, sizeof(int32_t));
+    key.push_back(p->win_init == 2 ? 1 : 0);
     key.append((const char *)&gen, sizeof gen);
     key.push_back(bits ? 1 : 0);
     key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
@@ -410,6 +417,7 @@ std::string tb_key(int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
 {
     std::string key(1, 'T');
     key.append((const char *)&p->n_windows, sizeof(int32_t));
+    key.push_back(p->win_init == 2 ? 1 : 0);
     key.append((const char *)&gen, sizeof gen);
     key.push_back(bits_off ? 1 : 0);
     key.append((const char *)tbs, sizeof(int32_t) * (size_t)n_tb);
@@ -541,13 +549,13 @@ void graph_free(tdec_graph *g)
 // stream into an instantiated graph.
 template <class F>
 tdec_status graph_capture(tdec_ctx *ctx, std::vector<CbReq> &reqs,
-                                 const std::vector<TbItem> *tbl, F body, tdec_graph **out)
+                                 const std::vector<TbItem> *tbl, bool exact, F body, tdec_graph **out)
 {
     PlanSlot ps;
     std::vector<char> blob;
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TDEC_EDEVICE;
-    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs);
+    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs, exact);
     tdec_graph *g = nullptr;
     if (s == TDEC_OK) {
         g = new tdec_graph();
@@ -757,7 +765,7 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
     tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
     if (s != TDEC_OK) return s;
     std::vector<char> blob;
-    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st);
+    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st, params->win_init == 2);
     if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
     if (s != TDEC_OK) {
         ps->key.clear();
@@ -800,7 +808,7 @@ tdec_status tdec::tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32
                                      reqs, tbl);
         if (s != TDEC_OK) return s;
         std::vector<char> blob;
-        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st);
+        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st, params->win_init == 2);
         if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
         if (s != TDEC_OK) {
             ps->key.clear();
@@ -836,7 +844,7 @@ tdec_status tdec_graph_cb_decode(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc
     tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
     if (s != TDEC_OK) return s;
     const tdec_params p = *params;
-    return graph_capture(ctx, reqs, nullptr,
+    return graph_capture(ctx, reqs, nullptr, p.win_init == 2,
                          [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
                              PlanSlot v = ps;
                              v.d_buf = d_plan;
@@ -863,7 +871,7 @@ tdec_status tdec_graph_tb_decode(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs
         make_tb_reqs(ctx, n_tb, tbs, llr_off, d_bits ? bits_off : nullptr, params, reqs, tbl);
     if (s != TDEC_OK) return s;
     const tdec_params p = *params;
-    return graph_capture(ctx, reqs, &tbl,
+    return graph_capture(ctx, reqs, &tbl, p.win_init == 2,
                          [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
                              return launch_tb_plan(ctx, &ps, d_plan, d_llr, &p, d_bits, d_res, cs);
                          },

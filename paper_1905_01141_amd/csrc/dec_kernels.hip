@@ -470,6 +470,130 @@ __device__ void ph2_bwd(const Win &c, s2 B[4])
     }
 }
 
+// ---- exact window boundaries (win_init = 2)
+//
+// Full-length max-log-MAP computed window by window: before each half-
+// iteration every window computes the max-plus transfer matrices of its steps
+// (one forward run from each state at its start, one backward run from each
+// state at its end), and a scan along the windows turns them into the exact
+// forward metric at every window start and backward metric at every window
+// end -- the values the full-length recursion has there, in its normalised
+// form (maximum 0: window boundaries are multiples of 8 steps from both block
+// ends, where the full-length recursion has just been normalised).  The
+// windows then run from those boundaries, so every extrinsic equals the
+// full-length decoder's (metrics that differ by a constant per step give the
+// same extrinsic).
+
+// Normalise as normalise() and return the amount subtracted.
+__device__ __forceinline__ int normalise_acc(s2 V[4])
+{
+    s2 m = vmax(vmax(V[0], V[1]), vmax(V[2], V[3]));
+    m = vmax(m, swp(m));
+    V[0] = subs(V[0], m);
+    V[1] = subs(V[1], m);
+    V[2] = subs(V[2], m);
+    V[3] = subs(V[3], m);
+    return (int)m.x;
+}
+
+// Keep register `keep` (and `keep2`) of a metric vector, set the others to
+// minus infinity: the states a run cannot have reached yet.
+__device__ __forceinline__ void pin_regs(s2 V[4], int keep, int keep2)
+{
+    const s2 neg = (s2){kNeg, kNeg};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (r != keep && r != keep2) V[r] = neg;
+}
+
+// Forward transfer runs over the whole window: for each start state i, the
+// forward recursion from i (P layout: state i in register i & 3, half i >> 2)
+// with the usual normalisation; out[2i] = the metrics at the window end,
+// out[2i+1].x = the total subtracted by normalisation (int32), so that the
+// best path metric from i to j is metric_j + total.  The states reachable from
+// i after 1 step sit in register i >> 1, after 2 steps in i >> 2 and
+// (i >> 2) | 2; the others are pinned to minus infinity until then.
+template <int DEC>
+__device__ void tf_fwd(const Win &c, uint4 *out)
+{
+    for (int i = 0; i < 8; ++i) {
+        s2 A[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            A[r] = (s2){(short)((r == (i & 3) && i < 4) ? 0 : kNeg),
+                        (short)((r == (i & 3) && i >= 4) ? 0 : kNeg)};
+        int acc = 0;
+        uint32_t r0[S];
+        load_seg(c, 0, r0);
+        for (int i0 = 0; i0 < c.W; i0 += S) {
+            uint32_t rn[S];
+            load_seg(c, min(i0 + S, c.W - S), rn);
+            s2 g[S];
+            gammas<DEC>(c, i0, r0, g);
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                acs_fwd(A, mk_g00(g[t]), g[t]);
+                if ((t & 1) || (i0 == 0 && t == 0)) acc += normalise_acc(A);
+                if (i0 == 0 && t == 0) pin_regs(A, i >> 1, i >> 1);
+                if (i0 == 0 && t == 1) pin_regs(A, i >> 2, (i >> 2) | 2);
+            }
+#pragma unroll
+            for (int t = 0; t < S; ++t) r0[t] = rn[t];
+        }
+        out[2 * i] = pack4(A);
+        out[2 * i + 1] = make_uint4((uint32_t)acc, 0u, 0u, 0u);
+    }
+}
+
+// Backward transfer runs: for each end state j, the backward recursion from j
+// (Q layout: state j in register j >> 1, half j & 1) to the window start;
+// out[2j] = the metrics at the window start, out[2j+1].x = the total
+// subtracted.  The states that reach j in 1 step sit in register j & 3, in 2
+// steps in registers 2 (j & 1) and 2 (j & 1) + 1.
+template <int DEC>
+__device__ void tf_bwd(const Win &c, uint4 *out)
+{
+    for (int j = 0; j < 8; ++j) {
+        s2 B[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            B[r] = (s2){(short)((r == (j >> 1) && !(j & 1)) ? 0 : kNeg),
+                        (short)((r == (j >> 1) && (j & 1)) ? 0 : kNeg)};
+        int acc = 0;
+        uint32_t r0[S];
+        load_seg(c, c.W - S, r0);
+        for (int i0 = c.W - S; i0 >= 0; i0 -= S) {
+            uint32_t rn[S];
+            load_seg(c, max(i0 - S, 0), rn);
+            s2 g[S];
+            gammas<DEC>(c, i0, r0, g);
+#pragma unroll
+            for (int t = S - 1; t >= 0; --t) {
+                acs_bwd(B, mk_g00(g[t]), g[t]);
+                if (bwd_norm(i0, t, c.W)) acc += normalise_acc(B);
+                if (i0 == c.W - S && t == S - 1) pin_regs(B, j & 3, j & 3);
+                if (i0 == c.W - S && t == S - 2) pin_regs(B, 2 * (j & 1), 2 * (j & 1) + 1);
+            }
+#pragma unroll
+            for (int t = 0; t < S; ++t) r0[t] = rn[t];
+        }
+        out[2 * j] = pack4(B);
+        out[2 * j + 1] = make_uint4((uint32_t)acc, 0u, 0u, 0u);
+    }
+}
+
+// Windows whose transfer values one scan trip loads before it combines them.
+constexpr int kScanB = 4;
+
+// Max over the 8 lanes of a group (lanes 8g .. 8g+7 of a wave).
+__device__ __forceinline__ int group8_max(int v)
+{
+    v = max(v, __shfl_xor(v, 1, 64));
+    v = max(v, __shfl_xor(v, 2, 64));
+    v = max(v, __shfl_xor(v, 4, 64));
+    return v;
+}
+
 // Hard decisions (the low bit of E after decoder 2) of the 8 positions g..g+7 (g a multiple of 8, g + 7 < K),
 // MSB first, from one 16-byte LDS read: position g + 2i is the low half of
 // word i, g + 2i + 1 its high half.
@@ -565,7 +689,7 @@ __device__ __forceinline__ void restage_unit(const uint2 v[3], uint2 q, int pos,
                      __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
 }
 
-template <bool UNEVEN>
+template <bool UNEVEN, bool EXACT>
 __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs a)
 {
     // dynamic LDS: per-slot state (CRC, done, iterations, ok) for the most
@@ -610,6 +734,9 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         uint32_t *R2 = R1 + rsz;                                 // rsz int32
         uint4 *ck = (uint4 *)(R2 + rsz);                         // (W/S)*lanes
         uint4 *bnd = ck + (int64_t)(W / S) * lanes;              // [4][lanes]
+        // exact boundaries only: transfer runs, [lanes][8 states][2] each
+        uint4 *tfA = bnd + (int64_t)4 * lanes;
+        uint4 *tfB = tfA + (int64_t)16 * lanes;
 
         // ---- restage the channel LLRs, clear LDS.  One unit = 4 trellis
         // steps of one window, written as one 16-byte word per decoder at
@@ -758,7 +885,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         const uint32_t *T = a.crc_tab + (cb.crc == 1 ? 0 : kCrcTabN);
         for (int iter = 1; iter <= a.max_iters; ++iter) {
             const bool run = active && !s_done[cs];
-            const bool prev = a.win_init && iter > 1;
+            const bool prev = EXACT || (a.win_init && iter > 1);
             const s2 z = (s2){0, 0};
             s2 V[4];  // this lane's running metric (alpha or beta)
 #pragma unroll
@@ -768,6 +895,88 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 if (dec == 2) cd.E = E0;
                 uint4 *bA = bnd + (dec - 1) * 2 * lanes;  // alpha boundaries of this decoder
                 uint4 *bB = bA + lanes;                   // beta boundaries
+                if (EXACT) {
+                    // transfer runs of every window, then the scans that give
+                    // the exact boundaries (8 lanes per block: lane q owns state q)
+                    if (run) {
+                        if (!bwd_first && !c.last) {
+                            if (dec == 1) tf_fwd<1>(cd, tfA + (size_t)wi * 16);
+                            else tf_fwd<2>(cd, tfA + (size_t)wi * 16);
+                        } else if (bwd_first && !c.first) {
+                            if (dec == 1) tf_bwd<1>(cd, tfB + (size_t)wi * 16);
+                            else tf_bwd<2>(cd, tfB + (size_t)wi * 16);
+                        }
+                    }
+                    __syncthreads();
+                    const int tl = bwd_first ? tid - half : tid;  // lane within the half
+                    const int q = tl & 7, lb = (tid & 63) & ~7;   // state; group base lane in the wave
+                    for (int cs0 = 0; cs0 < ncb; cs0 += half >> 3) {
+                        const int cg = cs0 + (tl >> 3);
+                        if (cg >= ncb || s_done[cg]) continue;  // the same for the group's 8 lanes
+                        if (!bwd_first) {
+                            // alpha at the start of windows 1 .. nw-1, from state 0;
+                            // the transfer values of kScanB windows are loaded per
+                            // trip (each lane: its state's metric of the 8 runs and
+                            // the 8 totals), then combined window by window
+                            int av = q == 0 ? 0 : -(1 << 30);
+                            const int h = 2 * (q & 3) + (q >> 2);  // P-layout halfword of state q
+                            for (int w0 = 0; w0 < nw - 1; w0 += kScanB) {
+                                int tv[kScanB][8];
+#pragma unroll
+                                for (int b = 0; b < kScanB; ++b) {
+                                    const int ww = min(w0 + b, nw - 2);
+                                    const uint32_t *Tm = (const uint32_t *)(tfA + (size_t)(cg * nw + ww) * 16);
+#pragma unroll
+                                    for (int i = 0; i < 8; ++i)
+                                        tv[b][i] = (int)(short)(Tm[8 * i + (h >> 1)] >> (16 * (h & 1))) +
+                                                   (int)Tm[8 * i + 4];
+                                }
+#pragma unroll
+                                for (int b = 0; b < kScanB; ++b) {
+                                    if (w0 + b >= nw - 1) break;
+                                    int best = -0x7fffffff;
+#pragma unroll
+                                    for (int i = 0; i < 8; ++i) best = max(best, __shfl(av, lb | i, 64) + tv[b][i]);
+                                    av = best - group8_max(best);
+                                    ((short *)&bA[cg * nw + w0 + b + 1])[h] = (short)max(-32768, av);
+                                }
+                            }
+                        } else {
+                            // beta at the end of windows nw-2 .. 0, from the termination
+                            const int16_t *src = a.llr + a.cbs[it.cb0 + cg].llr_off;
+                            const int N = K + 4, o = K + 2 * (dec - 1);
+                            const int lx0 = clamp_llr(src[o]), lz0 = clamp_llr(src[N + o]),
+                                      lx1 = clamp_llr(src[2 * N + o]), lz1 = clamp_llr(src[o + 1]),
+                                      lx2 = clamp_llr(src[N + o + 1]), lz2 = clamp_llr(src[2 * N + o + 1]);
+                            const int s1 = (q >> 2) & 1, s2b = (q >> 1) & 1, s3 = q & 1;
+                            const int v0 = (s2b ^ s3) * lx0 + (s1 ^ s3) * lz0 + (s1 ^ s2b) * lx1 +
+                                           s2b * lz1 + s1 * lx2 + s1 * lz2;
+                            int bv = v0 - group8_max(v0);
+                            for (int w0 = nw - 1; w0 >= 1; w0 -= kScanB) {
+                                int tv[kScanB][8];
+#pragma unroll
+                                for (int b = 0; b < kScanB; ++b) {
+                                    const int ww = max(w0 - b, 1);
+                                    const uint32_t *U = (const uint32_t *)(tfB + (size_t)(cg * nw + ww) * 16);
+#pragma unroll
+                                    for (int j = 0; j < 8; ++j)  // Q layout: halfword q
+                                        tv[b][j] = (int)(short)(U[8 * j + (q >> 1)] >> (16 * (q & 1))) +
+                                                   (int)U[8 * j + 4];
+                                }
+#pragma unroll
+                                for (int b = 0; b < kScanB; ++b) {
+                                    if (w0 - b < 1) break;
+                                    int best = -0x7fffffff;
+#pragma unroll
+                                    for (int j = 0; j < 8; ++j) best = max(best, __shfl(bv, lb | j, 64) + tv[b][j]);
+                                    bv = best - group8_max(best);
+                                    ((short *)&bB[cg * nw + w0 - b - 1])[q] = (short)max(-32768, bv);
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
                 if (run) {
                     if (dec == 1 && w == 0 && !bwd_first) s_crc[cs] = 0;
                     if (!bwd_first) {
@@ -795,10 +1004,10 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 if (run) {
                     if (!bwd_first) {
                         if (dec == 1) ph2_fwd<1>(cd, V); else ph2_fwd<2>(cd, V);
-                        if (!c.last) bA[wi + 1] = pack4(V);  // alpha at the window end
+                        if (!EXACT && !c.last) bA[wi + 1] = pack4(V);  // alpha at the window end
                     } else {
                         if (dec == 1) ph2_bwd<1>(cd, V); else ph2_bwd<2>(cd, V);
-                        if (!c.first) bB[wi - 1] = pack4(V);  // beta at the window start
+                        if (!EXACT && !c.first) bB[wi - 1] = pack4(V);  // beta at the window start
                     }
                 }
                 __syncthreads();
@@ -876,20 +1085,31 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
     }
 }
 
-const void *decode_kernel_address(bool uneven)
+const void *decode_kernel_address(bool uneven, bool exact)
 {
-    return uneven ? (const void *)turbo_decode_kernel<true> : (const void *)turbo_decode_kernel<false>;
+    if (exact)
+        return uneven ? (const void *)turbo_decode_kernel<true, true>
+                      : (const void *)turbo_decode_kernel<false, true>;
+    return uneven ? (const void *)turbo_decode_kernel<true, false>
+                  : (const void *)turbo_decode_kernel<false, false>;
 }
 
-int launch_decode(const DecArgs &a, bool uneven, int grid, int wg_threads, int lds_bytes,
-                  void *stream)
+int launch_decode(const DecArgs &a, bool uneven, bool exact, int grid, int wg_threads,
+                  int lds_bytes, void *stream)
 {
-    if (uneven)
-        hipLaunchKernelGGL(turbo_decode_kernel<true>, dim3(grid), dim3(wg_threads), lds_bytes,
-                           (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(turbo_decode_kernel<false>, dim3(grid), dim3(wg_threads), lds_bytes,
-                           (hipStream_t)stream, a);
+    const dim3 g(grid), b(wg_threads);
+    hipStream_t st = (hipStream_t)stream;
+    if (exact) {
+        if (uneven)
+            hipLaunchKernelGGL((turbo_decode_kernel<true, true>), g, b, lds_bytes, st, a);
+        else
+            hipLaunchKernelGGL((turbo_decode_kernel<false, true>), g, b, lds_bytes, st, a);
+    } else {
+        if (uneven)
+            hipLaunchKernelGGL((turbo_decode_kernel<true, false>), g, b, lds_bytes, st, a);
+        else
+            hipLaunchKernelGGL((turbo_decode_kernel<false, false>), g, b, lds_bytes, st, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -174,9 +174,10 @@ tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tb
 
 // Launchers (dec_kernels.hip / enc_kernels.hip).
 // uneven: some item's windows are not all of equal length (per-lane lengths)
-const void *decode_kernel_address(bool uneven);
-int launch_decode(const DecArgs &a, bool uneven, int grid, int wg_threads, int lds_bytes,
-                  void *stream);
+// exact: exact window boundaries (win_init = 2)
+const void *decode_kernel_address(bool uneven, bool exact);
+int launch_decode(const DecArgs &a, bool uneven, bool exact, int grid, int wg_threads,
+                  int lds_bytes, void *stream);
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
