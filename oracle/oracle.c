@@ -227,9 +227,16 @@ int or_turbo_encode_cb(const uint8_t *c, int32_t K, uint8_t *d)
 {
     if (or_k_index(K) < 0) return -1;
     int32_t *pi = (int32_t *)malloc(sizeof(int32_t) * K);
-    uint8_t *ci = (uint8_t *)malloc(K);
+    uint8_t *ci = (uint8_t *)calloc((size_t)K, 1);
     uint8_t *z1 = (uint8_t *)malloc(K), *z2 = (uint8_t *)malloc(K);
     uint8_t x1t[3], z1t[3], x2t[3], z2t[3];
+    if (!pi || !ci || !z1 || !z2) {
+        free(pi);
+        free(ci);
+        free(z1);
+        free(z2);
+        return -2;
+    }
     or_qpp(K, pi);
     for (int32_t k = 0; k < K; ++k) ci[k] = c[pi[k]] & 1; /* c'_k = c_{pi(k)} */
     or_rsc(c, K, z1, x1t, z1t);

@@ -89,7 +89,7 @@ int32_t or_seg_k(const or_seg *s, int32_t r);
 /* Turbo-encode one code block c[0..K-1] (filler bits, if any, are the first F
  * entries and must be 0).  d is [3][K+4] (d0 systematic, d1 parity 1,
  * d2 parity 2, trellis termination at indices K..K+3 of each stream).
- * Returns 0, or -1 if K is not a table size. */
+ * Returns 0, -1 if K is not a table size, or -2 if an allocation fails. */
 int or_turbo_encode_cb(const uint8_t *c, int32_t K, uint8_t *d);
 
 /* Transport block encoder: attaches CRC24A to payload[0..tbs-1], segments,
