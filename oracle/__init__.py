@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
         tmp = LIB_PATH + ".tmp"
         subprocess.run(
             ["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
-             os.path.join(HERE, "oracle.c"), "-o", tmp],
+             os.path.join(HERE, "oracle.c"), "-o", tmp, "-lm"],
             check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -46,7 +46,8 @@ class Seg(ct.Structure):
 
 class Params(ct.Structure):
     _fields_ = [("max_iters", ct.c_int32), ("early_stop", ct.c_int32),
-                ("n_windows", ct.c_int32), ("win_init", ct.c_int32)]
+                ("n_windows", ct.c_int32), ("win_init", ct.c_int32),
+                ("mi_eps", ct.c_int32)]
 
 
 class CbDesc(ct.Structure):
@@ -105,6 +106,12 @@ def lib():
         L.or_win_len.restype = ct.c_int32
         L.or_tb_decode_w.argtypes = [ct.c_void_p, ct.c_int32, P(Params), ct.c_void_p,
                                      ct.c_void_p, P(TbResult)]
+        L.or_mi_table.argtypes = [ct.c_void_p]
+        L.or_mi_table.restype = None
+        L.or_mi_sum.argtypes = [ct.c_void_p, ct.c_int32]
+        L.or_mi_sum.restype = ct.c_int64
+        L.or_mi_converged.argtypes = [ct.c_int64, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32]
+        L.or_mi_converged.restype = ct.c_int
         _lib = L
     return _lib
 
@@ -187,8 +194,31 @@ def tb_encode(payload) -> tuple[np.ndarray, np.ndarray]:
 
 
 # --------------------------------------------------------------------------- decoder
-def params(max_iters=6, early_stop=0, n_windows=1, win_init=0) -> Params:
-    return Params(max_iters, early_stop, n_windows, win_init)
+MI_TAB_N = 128
+STOP_CRC, STOP_MI = 1, 2  # early_stop bits
+
+
+def params(max_iters=6, early_stop=0, n_windows=1, win_init=0, mi_eps=0) -> Params:
+    return Params(max_iters, early_stop, n_windows, win_init, mi_eps)
+
+
+def mi_table() -> np.ndarray:
+    """T[m] = round(2^15 h(1 / (1 + e^(m/8)))), h the binary entropy, m <
+    MI_TAB_N (paper Sec. IV-B mutual-information stop; the estimator of Land,
+    Hoeher et al. for consistent LLRs without reference bits)."""
+    out = np.zeros(MI_TAB_N, np.int32)
+    lib().or_mi_table(_ptr(out))
+    return out
+
+
+def mi_sum(L) -> int:
+    """Sum of T[min(|L_k|, MI_TAB_N - 1)]: 1 - I = mi_sum / (2^15 K)."""
+    L = np.ascontiguousarray(L, np.int64)
+    return int(lib().or_mi_sum(_ptr(L), L.size))
+
+
+def mi_converged(s, s_prev, it, K, eps) -> bool:
+    return bool(lib().or_mi_converged(s, s_prev, it, K, eps))
 
 
 def constituent(lsa, lp, tail, n_windows=1, a_in=None, b_in=None, use16=False):

@@ -24,6 +24,7 @@
  */
 #include "oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -578,10 +579,44 @@ static uint32_t or_crc_bits(const uint8_t *hard, int32_t K, int32_t F, int32_t c
     return crc == OR_CRC_NONE ? 0u : or_crc24(hard + F, K - F, crc);
 }
 
+/* ---- mutual-information stop (paper Sec. IV-B, "Decoding function") ---- */
+
+/* Binary entropy of the error probability p = 1 / (1 + e^x) of a decision
+ * on an LLR of magnitude x nats:
+ *   h(p) = -(1-p) log2(1-p) - p log2(p) = log2(1 + e^-x) + p x / ln 2. */
+void or_mi_table(int32_t out[OR_MI_TAB_N])
+{
+    for (int m = 0; m < OR_MI_TAB_N; ++m) {
+        const double x = (double)m / 8.0, p = 1.0 / (1.0 + exp(x));
+        const double h = -(1.0 - p) * log2(1.0 - p) - (p > 0.0 ? p * log2(p) : 0.0);
+        out[m] = (int32_t)llround(32768.0 * h);
+    }
+}
+
+int64_t or_mi_sum(const int64_t *L, int32_t K)
+{
+    int32_t T[OR_MI_TAB_N];
+    or_mi_table(T);
+    int64_t s = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        const int64_t m = L[k] < 0 ? -L[k] : L[k];
+        s += T[m < OR_MI_TAB_N - 1 ? m : OR_MI_TAB_N - 1];
+    }
+    return s;
+}
+
+int or_mi_converged(int64_t s, int64_t s_prev, int32_t it, int32_t K, int32_t eps)
+{
+    const int64_t thr = (int64_t)K * eps;
+    const int64_t d = s - s_prev;
+    return s <= thr || (it >= 2 && (d < 0 ? -d : d) <= thr);
+}
+
 static int or_params_ok(const or_params *p, int32_t K)
 {
     if (!p) return 0;
     if (p->max_iters < 1 || p->max_iters > 16) return 0;
+    if (p->early_stop < 0 || p->early_stop > 3 || p->mi_eps < 0 || p->mi_eps > 32768) return 0;
     const int32_t W = or_win_len(K, p->n_windows);
     if (!W || W < 8 || K - (p->n_windows - 1) * W < 8) return 0;
     return 1;
@@ -629,6 +664,7 @@ int or_cb_decode_ex(const int16_t *llr, int32_t K, int32_t F, int32_t crc, const
         t2[j] = or_clamp(t2[j], -OR_LLR_MAX, OR_LLR_MAX);
     }
     int32_t it, passed = 0, done_iters = p->max_iters;
+    int64_t mi_prev = 0;
     for (it = 1; it <= p->max_iters; ++it) {
         /* decoder 1: natural order */
         for (int32_t k = 0; k < K; ++k) lsa[k] = Ls[k] + La1[k];
@@ -654,7 +690,13 @@ int or_cb_decode_ex(const int16_t *llr, int32_t K, int32_t F, int32_t crc, const
             hard[pi[k]] = L2[pi[k]] > 0;
         }
         passed = crc == OR_CRC_NONE ? 1 : or_crc_bits(hard, K, F, crc) == 0;
-        if (p->early_stop && crc != OR_CRC_NONE && passed) {
+        int stop = (p->early_stop & 1) && crc != OR_CRC_NONE && passed;
+        if (p->early_stop & 2) {
+            const int64_t mi = or_mi_sum(L2, K);
+            stop = stop || or_mi_converged(mi, mi_prev, it, K, p->mi_eps);
+            mi_prev = mi;
+        }
+        if (stop) {
             done_iters = it;
             break;
         }

@@ -103,10 +103,34 @@ int or_tb_encode(const uint8_t *payload, int32_t tbs, uint8_t *d_out, uint8_t *c
 /* ---- decoder ------------------------------------------------------------ */
 typedef struct {
     int32_t max_iters;   /* 1..16 */
-    int32_t early_stop;  /* 1: stop after the first full iteration whose CRC passes */
+    int32_t early_stop;  /* bit 0: stop after the first full iteration whose CRC passes;
+                            bit 1: stop once the average mutual information of the
+                            a-posteriori values has converged (or_mi_converged) */
     int32_t n_windows;   /* >= 1, divides K, K/n_windows >= 8; 1 = full length */
     int32_t win_init;    /* 1: window boundaries start from the previous iteration's metrics */
+    int32_t mi_eps;      /* convergence threshold of the mutual-information stop, in
+                            2^-15 bit per code block bit, 0..32768 */
 } or_params;
+
+/* ---- mutual-information stop (paper Sec. IV-B, "Decoding function") ----
+ * The paper stops the iterations when the average mutual information of the
+ * LLRs converges.  Its estimate here is the estimator of Land, Hoeher et al.
+ * for consistent LLRs that needs no reference bits:
+ *   I = 1 - mean_k h(p_k),  p_k = 1 / (1 + e^|L_k|)  (L in nats),
+ * h the binary entropy function and p_k the error probability of the hard
+ * decision on L_k.  In integers, with L in the decoder's unit of 1/8 nat:
+ *   T[m] = round(2^15 h(1 / (1 + e^(m/8)))) for m < OR_MI_TAB_N, 0 beyond
+ *          (T[m] is 0 well before m = OR_MI_TAB_N - 1);
+ *   S    = sum over the K a-posteriori values of T[min(|L_k|, OR_MI_TAB_N-1)],
+ *          so that 1 - I = S / (2^15 K). */
+#define OR_MI_TAB_N 128
+void or_mi_table(int32_t out[OR_MI_TAB_N]);
+int64_t or_mi_sum(const int64_t *L, int32_t K);
+/* Convergence after full iteration `it` (1-based) with sums s (this
+ * iteration) and s_prev (the one before): 1 - I within eps of 1, or a change
+ * of at most eps since the previous iteration (both per bit):
+ *   s <= K eps  or  (it >= 2 and |s - s_prev| <= K eps). */
+int or_mi_converged(int64_t s, int64_t s_prev, int32_t it, int32_t K, int32_t eps);
 
 /* One constituent max-log-MAP pass (exact, int64).
  *   lsa[k] = Ls[k] + La[k], lp[k] parity LLR, k < K;
