@@ -133,7 +133,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="uniform",
-                    choices=["uniform", "tb", "mixed", "serving", "cells", "ratematch", "encode"])
+                    choices=["uniform", "tb", "mixed", "serving", "cells", "ratematch", "encode",
+                             "stop"])
     ap.add_argument("--rho", type=str, default="0.25,0.5,1,2,4",
                     help="serving: load points (fractions of 40 cells' capacity)")
     ap.add_argument("--ttis", type=int, default=3000, help="serving/cells: measured TTIs")

@@ -224,6 +224,32 @@ def run_mixed(args):
     wall_direct = time.perf_counter() - t0
     for gph in graphs:
         gph.close()
+    # TB granularity: one launch per transport block, the TTI's blocks one
+    # after the other (the paper's UE parallelism, against the one launch per
+    # TTI above, its CB parallelism); same inputs, same decoder, same results
+    tb_out = [(torch.zeros_like(o[0]), torch.zeros_like(o[1])) for o in outs]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_tti)]
+    R = T.TB_RESULT_BYTES
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    for i in range(n_tti):
+        tl = tbs[i]
+        b_off = outs[i][2]
+        tb_bits, tb_res = tb_out[i]
+        ev[i][0].record(st)
+        for j, t in enumerate(tl):
+            o, nb = int(lo[k + j]), (int(t) + 7) // 8
+            D.tb_decode(x[o:o + T.tb_llr_count(int(t))], int(t), p,
+                        tb_bits[int(b_off[j]):int(b_off[j]) + nb], tb_res[j * R:(j + 1) * R])
+        ev[i][1].record(st)
+        k += len(tl)
+    torch.cuda.synchronize()
+    wall_tb = time.perf_counter() - t0
+    lat_tb = [a.elapsed_time(b) for a, b in ev]
+    same_tb = all(torch.equal(tb_out[i][0], outs[i][0]) and torch.equal(tb_out[i][1], outs[i][1])
+                  for i in range(n_tti))
     value = payload * reps / wall / 1e9
     line = {"metric": "decoded info Gbit/s, mixed TTIs (captured graphs)", "value": round(value, 4),
             "unit": "Gbit/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int16",
@@ -238,6 +264,12 @@ def run_mixed(args):
             "tb_ok": f"{ok}/{len(flat)}", "bit_errors_in_passed_tbs": errs_ok,
             "mean_iters": round(float(np.mean(iters)), 3),
             "direct_calls_gbit_s": round(payload / wall_direct / 1e9, 4),
+            "granularity": {
+                "cb_one_launch_per_tti_gbit_s": round(value, 4),
+                "tb_one_launch_per_tb_gbit_s": round(payload / wall_tb / 1e9, 4),
+                "tb_per_tti_ms_p50": round(pct(lat_tb, 0.5), 4),
+                "tb_per_tti_ms_p99": round(pct(lat_tb, 0.99), 4),
+                "tb_results_equal": bool(same_tb)},
             "autotune_s": round(tune_s, 2),
             "windows": {str(K): choice[K][0] for K in (40, 120, 504, 1024, 2048, 4096, 6144)
                         if K in choice},
@@ -349,6 +381,79 @@ def run_encode(args):
             "algorithmic_bytes": byts}
     log(f"[encode] {line}")
     return line
+
+
+# ----------------------------------------------------------------------------- stopping rules
+OPS_PER_KBIT_ITER = 178  # algorithmic int16 ops per trellis step and full iteration
+PEAK_INT16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def run_stop(args):
+    """The stopping rules at the uniform batch's shape: 4096 blocks of K =
+    6144 in 32 windows with previous-iteration boundaries, at most 8
+    iterations, 16QAM.  Per Es/N0 point and rule (none, the CRC stop, the
+    mutual-information stop of the paper's Sec. IV-B, either): mean
+    iterations, blocks decoded wrongly (bits unequal to the payload) and
+    decoded Gbit/s; a sweep of the MI threshold; and blocks without a CRC,
+    which only the MI rule can stop early (the headline figure)."""
+    import torch
+    D = T.Decoder(0)
+    n, K, nw, it_max, eps0 = 4096, 6144, 32, 8, T.MI_EPS_DEFAULT
+    rules = {"none": 0, "crc": T.STOP_CRC, "mi": T.STOP_MI, "mi|crc": T.STOP_MI | T.STOP_CRC}
+    plan = ((T.CRC24B, 3.0, [("none", eps0), ("crc", eps0), ("mi", eps0), ("mi|crc", eps0)]),
+            (T.CRC24B, 3.5, [("none", eps0), ("crc", eps0), ("mi", eps0), ("mi|crc", eps0),
+                             ("mi", 0), ("mi", 4), ("mi", 33)]),
+            (T.CRC24B, 8.0, [("none", eps0), ("crc", eps0), ("mi", eps0), ("mi|crc", eps0),
+                             ("mi", 0), ("mi", 4), ("mi", 33)]),
+            (T.CRC_NONE, 3.5, [("none", eps0), ("mi", eps0)]),
+            (T.CRC_NONE, 8.0, [("none", eps0), ("mi", eps0)]))
+    rows, head, cur = [], None, None
+    for crc, db, runs in plan:
+        L = 24 if crc else 0
+        if cur != crc:
+            cur = crc
+            descs, n_llr, n_bytes = T.make_descs([(K, 0, crc)] * n)
+            pay_bits = wl.random_bits(wl.rng(8, crc), n * (K - L))
+            pay = torch.from_numpy(np.packbits(pay_bits)).cuda()
+            coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+            D.cb_encode_batch(descs, pay, coded)
+            torch.cuda.synchronize()
+            coded_h = coded.cpu().numpy()
+            bits = torch.zeros(n_bytes, dtype=torch.uint8, device="cuda")
+            ok = torch.zeros(n, dtype=torch.uint8, device="cuda")
+            it = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        llr = torch.from_numpy(wl.channel_blocks(coded_h, [(K, 0)] * n, "16qam", db,
+                                                 wl.rng(8, 10 + int(db * 10) + crc))).cuda()
+        for name, eps in runs:
+            p = T.params(it_max, rules[name], nw, 1, eps)
+            ms, host = time_launches(torch, lambda: D.cb_decode_batch(descs, llr, p, bits, ok, it))
+            iters = it.cpu().numpy().astype(np.int64)
+            wrong = int((bits != pay).view(n, -1).any(1).sum().item())
+            ops = OPS_PER_KBIT_ITER * K * int(iters.sum())
+            row = {"crc": "24B" if crc else "none", "esn0_db": db, "rule": name,
+                   "mi_eps": eps if rules[name] & T.STOP_MI else None,
+                   "kernel_ms": round(ms, 4), "gbit_s": round(n * (K - L) / ms / 1e6, 3),
+                   "mean_iters": round(float(iters.mean()), 3), "max_iters_seen": int(iters.max()),
+                   "blocks_wrong": wrong, "crc_pass": int(ok.sum().item()) if crc else None,
+                   "valu_frac": round(ops / ms / 1e9 / PEAK_INT16_TOPS, 4)}
+            log(f"[stop] {row}")
+            rows.append(row)
+            if not crc and db == 8.0 and name == "mi":
+                head = (row, ops, ms)
+    row, ops, ms = head
+    return {"metric": "decoded info Gbit/s, mutual-information stop (<= 8 iterations), "
+                      "blocks without CRC", "value": row["gbit_s"],
+            "unit": "Gbit/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int16",
+            "data": "synthetic (random payload, GPU turbo encoder, 16QAM AWGN, quantised LLRs)",
+            "config": {"workload": f"{n} code blocks K={K} without CRC, {nw} windows, previous-"
+                                   "iteration boundaries, <= 8 iterations, stop on converged "
+                                   f"mutual information (eps {eps0} / 2^15 bit), Es/N0 8 dB",
+                       "mi_eps": eps0},
+            "roofline": {"bound": "alu", "achieved": round(ops / ms / 1e9, 3),
+                         "peak": round(PEAK_INT16_TOPS, 2), "unit": "TOP/s",
+                         "frac": round(ops / ms / 1e9 / PEAK_INT16_TOPS, 4), "traffic": None},
+            "blocks_wrong": row["blocks_wrong"], "mean_iters": row["mean_iters"],
+            "rows": rows}
 
 
 # ----------------------------------------------------------------------------- c4 / c5

@@ -81,11 +81,27 @@ typedef enum {
 
 enum { TDEC_CRC_NONE = 0, TDEC_CRC24A = 1, TDEC_CRC24B = 2 };
 
+enum { TDEC_STOP_CRC = 1, TDEC_STOP_MI = 2 }; /* bits of tdec_params.early_stop */
+
 /* Decoder parameters. */
 typedef struct {
     int32_t max_iters;  /* 1..16 full iterations (decoder 1 + decoder 2) */
-    int32_t early_stop; /* 0: run exactly max_iters; 1: stop after the first
-                           iteration whose CRC passes (blocks without CRC never stop early) */
+    int32_t early_stop; /* 0: run exactly max_iters; otherwise a block stops after the
+                           first full iteration that meets one of the rules set:
+                           TDEC_STOP_CRC: its CRC passes (blocks without CRC never stop
+                             on this rule);
+                           TDEC_STOP_MI: the average mutual information of its
+                             a-posteriori values has converged (paper Sec. IV-B,
+                             decoding function).  The estimate is
+                             1 - I = (1/K) sum_k h(1 / (1 + e^|L_k|)), h the binary
+                             entropy and L_k decoder 2's a-posteriori value in nats
+                             (consistent-LLR estimator without reference bits), summed
+                             in units of 2^-15 bit from a table over |L| in the
+                             decoder's 1/8-nat unit, clipped at 127:
+                             T[m] = round(2^15 h(1 / (1 + e^(m/8)))).  With S_i the
+                             sum after iteration i, the block stops when
+                             S_i <= K mi_eps, or i >= 2 and |S_i - S_(i-1)| <= K mi_eps.
+                           crc_ok reports the CRC at the iteration the block stopped. */
     int32_t n_windows;  /* windows per code block, 1..128: every window but the last has
                            W = 8*ceil(K/(8n)) steps (K for n = 1), the last the rest, which
                            must be non-empty; 0 = the library's choice for each K
@@ -94,6 +110,10 @@ typedef struct {
                            1: from the neighbours' previous-iteration boundary metrics;
                            2: from the exact boundary metrics (see below): the result
                               equals n_windows = 1 for any window count */
+    int32_t mi_eps;     /* threshold of TDEC_STOP_MI in 2^-15 bit per code block bit,
+                           0..32768; ignored without it.  Max-log-MAP a-posteriori
+                           values are overconfident, so thresholds above a few units
+                           can stop blocks that still hold errors: 1 is a safe choice */
 } tdec_params;
 
 /* ---------------------------------------------------------------- host-only helpers */

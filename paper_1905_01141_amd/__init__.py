@@ -41,7 +41,8 @@ class TdecError(RuntimeError):
 
 class Params(ct.Structure):
     _fields_ = [("max_iters", ct.c_int32), ("early_stop", ct.c_int32),
-                ("n_windows", ct.c_int32), ("win_init", ct.c_int32)]
+                ("n_windows", ct.c_int32), ("win_init", ct.c_int32),
+                ("mi_eps", ct.c_int32)]
 
 
 class Seg(ct.Structure):
@@ -200,8 +201,15 @@ def _stream(stream):
 
 
 # ----------------------------------------------------------------------------- helpers
-def params(max_iters=6, early_stop=0, n_windows=1, win_init=0) -> Params:
-    return Params(max_iters, early_stop, n_windows, win_init)
+STOP_CRC, STOP_MI = 1, 2  # bits of Params.early_stop
+MI_EPS_DEFAULT = 1         # 2^-15 bit per bit: looser thresholds stop max-log-MAP blocks
+                           # whose a-posteriori values are large but still wrong
+
+
+def params(max_iters=6, early_stop=0, n_windows=1, win_init=0, mi_eps=MI_EPS_DEFAULT) -> Params:
+    """Decoder parameters (tdec_params).  early_stop: 0, or an OR of STOP_CRC
+    and STOP_MI; mi_eps: the STOP_MI threshold."""
+    return Params(max_iters, early_stop, n_windows, win_init, mi_eps)
 
 
 def segment(tbs: int) -> dict:

@@ -45,6 +45,7 @@ struct PlanSlot {
     int state_slots = 1;  // most blocks of any item
     bool uneven = false;  // some item's last window is shorter
     bool exact = false;   // exact window boundaries (win_init = 2): transfer-run scratch
+    bool mi = false;      // mutual-information stop (early_stop bit 1): LDS table and sums
     size_t off_items = 0, off_cbs = 0, off_tbs = 0, off_enc = 0;
 };
 
@@ -94,7 +95,8 @@ namespace {
 bool params_ok(const tdec_params *p)
 {
     return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
-           p->early_stop <= 1 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 2;
+           p->early_stop <= 3 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 2 &&
+           p->mi_eps >= 0 && p->mi_eps <= 32768;
 }
 
 int32_t pick_windows(int32_t K)
@@ -203,7 +205,7 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
 // Build the decode plan (items + code block list) from a request.
 tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot &ps,
                               std::vector<char> &blob, const std::vector<TbItem> *tbs,
-                              hipStream_t st, bool exact)
+                              hipStream_t st, bool exact, bool mi)
 {
     // group by (K, nw), biggest blocks first, request order within a group:
     // a counting sort over the size table (a size has one window count per
@@ -292,16 +294,16 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
                              (int64_t)4 * lanes * 16 + (exact ? (int64_t)lanes * 512 : 0) + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
-    lds += lds_state_bytes(max_n);
+    lds += lds_state_bytes(max_n) + (mi ? lds_mi_bytes(max_n) : 0);
     // persistent grid: as many work groups as can be resident
     int occ = 0;
-    const int64_t okey = (int64_t)wg << 34 | (int64_t)exact << 33 | (int64_t)uneven << 32 |
-                         (uint32_t)lds;
+    const int64_t okey = (int64_t)mi << 44 | (int64_t)wg << 34 | (int64_t)exact << 33 |
+                         (int64_t)uneven << 32 | (uint32_t)lds;
     auto oc = ctx->occ_cache.find(okey);
     if (oc != ctx->occ_cache.end()) {
         occ = oc->second;
     } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(uneven, exact), wg,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, decode_kernel_address(uneven, exact, mi), wg,
                                                          lds) !=
                 hipSuccess ||
             occ < 1)
@@ -337,6 +339,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.state_slots = max_n;
     ps.uneven = uneven;
     ps.exact = exact;
+    ps.mi = mi;
     ps.stride = stride;
     return TDEC_OK;
 }
@@ -389,12 +392,16 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.scratch_stride = ps->stride;
     a.counter = ctx->d_counter;
     a.qtab = ctx->d_qtab;
+    a.mi_tab = ctx->d_crc_tab + kCrcTabWords;
     a.max_iters = p->max_iters;
     a.early_stop = p->early_stop;
     a.win_init = p->win_init;
+    a.mi_eps = p->mi_eps;
     a.state_slots = ps->state_slots;
-    if ((p->win_init == 2) != ps->exact) return TDEC_EINVAL;  // the plan's scratch layout
-    if (launch_decode(a, ps->uneven, ps->exact, ps->grid, ps->wg, ps->lds, st)) return TDEC_EDEVICE;
+    // the plan's scratch and LDS layouts
+    if ((p->win_init == 2) != ps->exact || ((p->early_stop & 2) != 0) != ps->mi) return TDEC_EINVAL;
+    if (launch_decode(a, ps->uneven, ps->exact, ps->mi, ps->grid, ps->wg, ps->lds, st))
+        return TDEC_EDEVICE;
     return TDEC_OK;
 }
 
@@ -405,7 +412,7 @@ std::string cb_key(int32_t n_cb, const tdec_cb_desc *desc, const tdec_params *p,
 {
     std::string key(1, 'C');
     key.append((const char *)&p->n_windows, sizeof(int32_t));
-    key.push_back(p->win_init == 2 ? 1 : 0);
+    key.push_back((p->win_init == 2 ? 1 : 0) | ((p->early_stop & 2) ? 2 : 0));
     key.append((const char *)&gen, sizeof gen);
     key.push_back(bits ? 1 : 0);
     key.append((const char *)desc, sizeof(tdec_cb_desc) * (size_t)n_cb);
@@ -417,7 +424,7 @@ std::string tb_key(int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
 {
     std::string key(1, 'T');
     key.append((const char *)&p->n_windows, sizeof(int32_t));
-    key.push_back(p->win_init == 2 ? 1 : 0);
+    key.push_back((p->win_init == 2 ? 1 : 0) | ((p->early_stop & 2) ? 2 : 0));
     key.append((const char *)&gen, sizeof gen);
     key.push_back(bits_off ? 1 : 0);
     key.append((const char *)tbs, sizeof(int32_t) * (size_t)n_tb);
@@ -549,13 +556,14 @@ void graph_free(tdec_graph *g)
 // stream into an instantiated graph.
 template <class F>
 tdec_status graph_capture(tdec_ctx *ctx, std::vector<CbReq> &reqs,
-                                 const std::vector<TbItem> *tbl, bool exact, F body, tdec_graph **out)
+                                 const std::vector<TbItem> *tbl, bool exact, bool mi, F body,
+                                 tdec_graph **out)
 {
     PlanSlot ps;
     std::vector<char> blob;
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TDEC_EDEVICE;
-    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs, exact);
+    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs, exact, mi);
     tdec_graph *g = nullptr;
     if (s == TDEC_OK) {
         g = new tdec_graph();
@@ -658,7 +666,7 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
         return TDEC_EDEVICE;
     }
     c->num_cus = prop.multiProcessorCount;
-    const size_t tab_bytes = kCrcTabWords * sizeof(uint32_t);
+    const size_t tab_bytes = kTabWords * sizeof(uint32_t);
     c->flags_cap = 1 << 20;
     c->encbuf_bytes = 1 << 20;
     const size_t plan_bytes = (size_t)kPlanSlots * kPlanSlotBytes;
@@ -691,10 +699,11 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
              hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) == hipSuccess;
     }
     if (ok) {
-        std::vector<uint32_t> tab(kCrcTabWords);
+        std::vector<uint32_t> tab(kTabWords);
         crc_shift_table(kPoly24A, tab.data(), kCrcTabN);
         crc_shift_table(kPoly24B, tab.data() + kCrcTabN, kCrcTabN);
         crc_x32_table(kPoly24A, tab.data() + 2 * kCrcTabN, kX32N);
+        mi_table(tab.data() + kCrcTabWords);
         ok = hipMemcpy(c->d_crc_tab, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (ok) {
@@ -765,7 +774,8 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
     tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
     if (s != TDEC_OK) return s;
     std::vector<char> blob;
-    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st, params->win_init == 2);
+    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st, params->win_init == 2,
+                          (params->early_stop & 2) != 0);
     if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
     if (s != TDEC_OK) {
         ps->key.clear();
@@ -808,7 +818,8 @@ tdec_status tdec::tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32
                                      reqs, tbl);
         if (s != TDEC_OK) return s;
         std::vector<char> blob;
-        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st, params->win_init == 2);
+        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st, params->win_init == 2,
+                              (params->early_stop & 2) != 0);
         if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
         if (s != TDEC_OK) {
             ps->key.clear();
@@ -844,7 +855,7 @@ tdec_status tdec_graph_cb_decode(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc
     tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
     if (s != TDEC_OK) return s;
     const tdec_params p = *params;
-    return graph_capture(ctx, reqs, nullptr, p.win_init == 2,
+    return graph_capture(ctx, reqs, nullptr, p.win_init == 2, (p.early_stop & 2) != 0,
                          [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
                              PlanSlot v = ps;
                              v.d_buf = d_plan;
@@ -871,7 +882,7 @@ tdec_status tdec_graph_tb_decode(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs
         make_tb_reqs(ctx, n_tb, tbs, llr_off, d_bits ? bits_off : nullptr, params, reqs, tbl);
     if (s != TDEC_OK) return s;
     const tdec_params p = *params;
-    return graph_capture(ctx, reqs, &tbl, p.win_init == 2,
+    return graph_capture(ctx, reqs, &tbl, p.win_init == 2, (p.early_stop & 2) != 0,
                          [&](PlanSlot &ps, char *d_plan, hipStream_t cs) {
                              return launch_tb_plan(ctx, &ps, d_plan, d_llr, &p, d_bits, d_res, cs);
                          },

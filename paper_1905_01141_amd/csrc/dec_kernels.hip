@@ -218,6 +218,7 @@ struct Win {
                          // the LDS base, since its addresses include the slot offset
     const uint4 *R;      // restaged input: [t/4][window] x 4 steps, one int32 per step
     uint4 *ck;           // checkpoints [segment][window]
+    const unsigned short *mit;  // LDS entropy table (mutual-information stop only)
 };
 
 // The restaged inputs of 8 steps starting at local step i0.
@@ -262,17 +263,22 @@ __device__ __forceinline__ void gammas(const Win &c, int i0, const uint32_t r[S]
 // systematic + a-priori) at its natural position; decoder 2 stores twice the
 // scaled Le (decoder 1's next a-priori) plus the hard decision of pi(k) in
 // the low bit.  The hard decisions stay readable from the low bits until the
-// next decoder-1 pass, i.e. through the CRC check and the output.
-template <int DEC>
-__device__ __forceinline__ void emit(const Win &c, int i0, int t, uint32_t r, s2 g01, int le)
+// next decoder-1 pass, i.e. through the CRC check and the output.  With MI,
+// decoder 2 also adds the entropy of its hard decision, h(|L|) from the LDS
+// table (L = Ls + La + Le, the a-posteriori value), to the lane's sum.
+template <int DEC, bool MI = false>
+__device__ __forceinline__ void emit(const Win &c, int i0, int t, uint32_t r, s2 g01, int le,
+                                     int &acc)
 {
     const int q = scale_ext(le);
     if (DEC == 1) {
         c.E[epad(c.lo + i0) + t] = (short)((int)(short)(r >> 16) + q);
     } else {
         const uint32_t a = r >> 16;
-        const int bit = (int)g01.y + le > 0;
+        const int lapp = (int)g01.y + le;
+        const int bit = lapp > 0;
         *(short *)((char *)c.E + a) = (short)(2 * q + bit);
+        if (MI) acc += c.mit[min(abs(lapp), kMiTabN - 1)];
     }
 }
 
@@ -338,10 +344,12 @@ __device__ __forceinline__ uint4 ck_at(const Win &c, int i0)
 // ---- phase 2, forward-first lane: the upper half [M, W) in forward order.
 // Per segment: beta recomputed backward from the checkpoint at its end, then
 // alpha forward over it with the extrinsic.
-template <int DEC>
-__device__ void ph2_fwd(const Win &c, s2 A[4])
+// Returns the lane's entropy sum when MI (else 0).
+template <int DEC, bool MI = false>
+__device__ int ph2_fwd(const Win &c, s2 A[4])
 {
-    if (c.M >= c.W) return;
+    int acc = 0;
+    if (c.M >= c.W) return acc;
     const int last = c.W - S;
     int i0 = c.M;
     uint32_t r[S], rn[S], rnn[S];
@@ -380,7 +388,7 @@ __device__ void ph2_fwd(const Win &c, s2 A[4])
             if (bwd_norm(i1, u, c.W)) normalise(Bn);
             const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
             fwd_post(A, i0, t, c.first);
-            emit<DEC>(c, i0, t, r[t], g[t], le);
+            emit<DEC, MI>(c, i0, t, r[t], g[t], le, acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -399,17 +407,20 @@ __device__ void ph2_fwd(const Win &c, s2 A[4])
     for (int t = 0; t < S; ++t) {
         const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
         fwd_post(A, i0, t, c.first);
-        emit<DEC>(c, i0, t, r[t], g[t], le);
+        emit<DEC, MI>(c, i0, t, r[t], g[t], le, acc);
     }
+    return acc;
 }
 
 // ---- phase 2, backward-first lane: the lower half [0, M) in backward order.
 // Per segment: alpha recomputed forward from the checkpoint at its start,
 // then beta backward over it with the extrinsic.
-template <int DEC>
-__device__ void ph2_bwd(const Win &c, s2 B[4])
+// Returns the lane's entropy sum when MI (else 0).
+template <int DEC, bool MI = false>
+__device__ int ph2_bwd(const Win &c, s2 B[4])
 {
-    if (c.M <= 0) return;
+    int acc = 0;
+    if (c.M <= 0) return acc;
     int i0 = c.M - S;
     uint32_t r[S], rn[S], rnn[S];
     s2 g[S], g0[S], AQ[S][4];
@@ -447,7 +458,7 @@ __device__ void ph2_bwd(const Win &c, s2 B[4])
             const int u = S - 1 - t;
             const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
             if (bwd_norm(i0, u, c.W)) normalise(B);
-            emit<DEC>(c, i0, u, r[u], g[u], le);
+            emit<DEC, MI>(c, i0, u, r[u], g[u], le, acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -466,8 +477,9 @@ __device__ void ph2_bwd(const Win &c, s2 B[4])
     for (int u = S - 1; u >= 0; --u) {
         const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
         if (bwd_norm(i0, u, c.W)) normalise(B);
-        emit<DEC>(c, i0, u, r[u], g[u], le);
+        emit<DEC, MI>(c, i0, u, r[u], g[u], le, acc);
     }
+    return acc;
 }
 
 // ---- exact window boundaries (win_init = 2)
@@ -689,20 +701,27 @@ __device__ __forceinline__ void restage_unit(const uint2 v[3], uint2 q, int pos,
                      __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
 }
 
-template <bool UNEVEN, bool EXACT>
+template <bool UNEVEN, bool EXACT, bool MI>
 __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs a)
 {
     // dynamic LDS: per-slot state (CRC, done, iterations, ok) for the most
-    // blocks an item of this launch holds, then the blocks' extrinsic arrays
+    // blocks an item of this launch holds; with MI the entropy table and the
+    // per-slot entropy sums of this and the previous iteration; then the
+    // blocks' extrinsic arrays
     extern __shared__ __align__(16) char lds_all[];
     const int ss = a.state_slots;
     uint32_t *s_crc = (uint32_t *)lds_all;
     int *s_done = (int *)(lds_all + 4 * ss);
     int *s_iters = (int *)(lds_all + 8 * ss);
     int *s_ok = (int *)(lds_all + 12 * ss);
-    char *lds = lds_all + lds_state_bytes(ss);
+    unsigned short *s_mit = (unsigned short *)(lds_all + lds_state_bytes(ss));
+    int *s_mi = (int *)(s_mit + kMiTabN);
+    int *s_mip = s_mi + ss;
+    char *lds = lds_all + lds_state_bytes(ss) + (MI ? lds_mi_bytes(ss) : 0);
 
     const int tid = threadIdx.x, nthr = blockDim.x, half = nthr >> 1;
+    if (MI)
+        for (int m = tid; m < kMiTabN; m += nthr) s_mit[m] = (unsigned short)a.mi_tab[m];
     const bool bwd_first = tid >= half;       // wave-uniform role
     const int wi = bwd_first ? tid - half : tid;  // window index within the item
     char *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
@@ -836,6 +855,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             s_done[tid] = 0;
             s_iters[tid] = a.max_iters;
             s_ok[tid] = 0;
+            if (MI) s_mip[tid] = 0;
         }
 
         // ---- lane role within the item
@@ -854,6 +874,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         c.last = w == nw - 1;
         c.E = (short *)(lds + (int64_t)cs * it.lds_slot);
         c.ck = ck;
+        c.mit = s_mit;
         // decoder 2 addresses E through byte offsets from the slot of block 0
         short *E0 = (short *)lds;
 
@@ -888,6 +909,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             const bool prev = EXACT || (a.win_init && iter > 1);
             const s2 z = (s2){0, 0};
             s2 V[4];  // this lane's running metric (alpha or beta)
+            int acc = 0;  // entropy sum of this lane's decoder-2 steps (MI)
 #pragma unroll
             for (int dec = 1; dec <= 2; ++dec) {
                 Win cd = c;
@@ -978,7 +1000,10 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                     __syncthreads();
                 }
                 if (run) {
-                    if (dec == 1 && w == 0 && !bwd_first) s_crc[cs] = 0;
+                    if (dec == 1 && w == 0 && !bwd_first) {
+                        s_crc[cs] = 0;
+                        if (MI) s_mi[cs] = 0;
+                    }
                     if (!bwd_first) {
                         if (c.first) {
                             V[0] = (s2){0, kNeg};
@@ -1003,12 +1028,13 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 __syncthreads();
                 if (run) {
                     if (!bwd_first) {
-                        if (dec == 1) ph2_fwd<1>(cd, V); else ph2_fwd<2>(cd, V);
+                        if (dec == 1) ph2_fwd<1>(cd, V); else acc = ph2_fwd<2, MI>(cd, V);
                         if (!EXACT && !c.last) bA[wi + 1] = pack4(V);  // alpha at the window end
                     } else {
-                        if (dec == 1) ph2_bwd<1>(cd, V); else ph2_bwd<2>(cd, V);
+                        if (dec == 1) ph2_bwd<1>(cd, V); else acc = ph2_bwd<2, MI>(cd, V);
                         if (!EXACT && !c.first) bB[wi - 1] = pack4(V);  // beta at the window start
                     }
+                    if (MI && dec == 2) atomicAdd(&s_mi[cs], acc);
                 }
                 __syncthreads();
             }
@@ -1022,10 +1048,18 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             __syncthreads();
             if (run && w == 0 && !bwd_first) {
                 const bool pass = cb.crc == 0 || s_crc[cs] == 0;
-                if (a.early_stop && cb.crc != 0 && pass) {
+                bool stop = (a.early_stop & 1) && cb.crc != 0 && pass;
+                if (MI) {
+                    // converged: 1 - I within eps of 0, or changed by at most
+                    // eps since the previous iteration (per bit, 2^-15 units)
+                    const int sum = s_mi[cs], thr = K * a.mi_eps;
+                    stop = stop || sum <= thr || (iter > 1 && abs(sum - s_mip[cs]) <= thr);
+                    s_mip[cs] = sum;
+                }
+                if (stop) {
                     s_done[cs] = 1;
                     s_iters[cs] = iter;
-                    s_ok[cs] = 1;
+                    s_ok[cs] = pass;
                 } else if (iter == a.max_iters) {
                     s_iters[cs] = iter;
                     s_ok[cs] = pass;
@@ -1085,31 +1119,29 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
     }
 }
 
-const void *decode_kernel_address(bool uneven, bool exact)
+using DecodeKernel = void (*)(DecArgs);
+
+// The eight instantiations, indexed by uneven + 2 exact + 4 mi.
+static DecodeKernel decode_kernel(bool uneven, bool exact, bool mi)
 {
-    if (exact)
-        return uneven ? (const void *)turbo_decode_kernel<true, true>
-                      : (const void *)turbo_decode_kernel<false, true>;
-    return uneven ? (const void *)turbo_decode_kernel<true, false>
-                  : (const void *)turbo_decode_kernel<false, false>;
+    static const DecodeKernel k[8] = {
+        turbo_decode_kernel<false, false, false>, turbo_decode_kernel<true, false, false>,
+        turbo_decode_kernel<false, true, false>,  turbo_decode_kernel<true, true, false>,
+        turbo_decode_kernel<false, false, true>,  turbo_decode_kernel<true, false, true>,
+        turbo_decode_kernel<false, true, true>,   turbo_decode_kernel<true, true, true>};
+    return k[(uneven ? 1 : 0) + (exact ? 2 : 0) + (mi ? 4 : 0)];
 }
 
-int launch_decode(const DecArgs &a, bool uneven, bool exact, int grid, int wg_threads,
+const void *decode_kernel_address(bool uneven, bool exact, bool mi)
+{
+    return (const void *)decode_kernel(uneven, exact, mi);
+}
+
+int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, int wg_threads,
                   int lds_bytes, void *stream)
 {
-    const dim3 g(grid), b(wg_threads);
-    hipStream_t st = (hipStream_t)stream;
-    if (exact) {
-        if (uneven)
-            hipLaunchKernelGGL((turbo_decode_kernel<true, true>), g, b, lds_bytes, st, a);
-        else
-            hipLaunchKernelGGL((turbo_decode_kernel<false, true>), g, b, lds_bytes, st, a);
-    } else {
-        if (uneven)
-            hipLaunchKernelGGL((turbo_decode_kernel<true, false>), g, b, lds_bytes, st, a);
-        else
-            hipLaunchKernelGGL((turbo_decode_kernel<false, false>), g, b, lds_bytes, st, a);
-    }
+    hipLaunchKernelGGL(decode_kernel(uneven, exact, mi), dim3(grid), dim3(wg_threads), lds_bytes,
+                       (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -7,6 +7,7 @@
 // Segmentation: TS 36.212 5.1.2 (Z = 6144), which is the rule behind the
 // paper's Algorithm 1 cap of 6120 payload bits per code block.
 #include <algorithm>
+#include <cmath>
 
 #include "tdec_internal.h"
 
@@ -124,6 +125,24 @@ void crc_x32_table(uint32_t poly, uint32_t *out, int n)
             v <<= 1;
             if (v & 0x1000000u) v = (v ^ poly) & 0xFFFFFFu;
         }
+    }
+}
+
+// Entropy table of the mutual-information stop (paper Sec. IV-B, decoding
+// function).  A hard decision on an LLR of magnitude x nats errs with
+// probability p = 1 / (1 + e^x); the table holds its binary entropy
+// h(p) = -p log2 p - (1 - p) log2 (1 - p) in units of 2^-15 bit for x = m / 8
+// (the decoder's LLR unit).  1 - (sum of h over a block's a-posteriori values)
+// / K estimates the block's average mutual information (Land and Hoeher's
+// estimator for consistent LLRs, which needs no reference bits).
+void mi_table(uint32_t *out)
+{
+    for (int m = 0; m < kMiTabN; ++m) {
+        const double x = m / 8.0;
+        const double p = 1.0 / (1.0 + std::exp(x)), q = 1.0 - p;
+        double h = -q * std::log2(q);
+        if (p > 0.0) h -= p * std::log2(p);
+        out[m] = (uint32_t)std::lround(32768.0 * h);
     }
 }
 

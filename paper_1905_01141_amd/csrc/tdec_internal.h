@@ -18,6 +18,10 @@ constexpr int kCrcTabN = kKmax + 32;
 constexpr int kX32N = 64 * kKmax / 32 + 2;
 // layout of the CRC table in device memory: [x^m mod g24A][x^m mod g24B][x^(32j) mod g24A]
 constexpr int kCrcTabWords = 2 * kCrcTabN + kX32N;
+// mutual-information stop: entries of the entropy table, which follows the
+// CRC tables in the same device buffer (one word per entry)
+constexpr int kMiTabN = 128;
+constexpr int kTabWords = kCrcTabWords + kMiTabN;
 constexpr uint32_t kPoly24A = 0x864CFBu;  // D^24+D^23+D^18+D^17+D^14+D^11+D^10+D^7+D^6+D^5+D^4+D^3+D+1
 constexpr uint32_t kPoly24B = 0x800063u;  // D^24+D^23+D^6+D^5+D+1
 constexpr int kMaxSlotsPerWg = 64;        // code blocks per work group
@@ -31,6 +35,8 @@ void qpp_coeffs(int i, int32_t *f1, int32_t *f2);
 int segment(int32_t tbs, int32_t seg[8]);  // B C L K+ K- C+ C- F; 0 ok, -1 range
 void crc_shift_table(uint32_t poly, uint32_t *out, int n);  // out[m] = x^m mod g
 void crc_x32_table(uint32_t poly, uint32_t *out, int n);    // out[j] = x^(32 j) mod g
+// out[m] = round(2^15 h(1 / (1 + e^(m/8)))), m < kMiTabN, h the binary entropy
+void mi_table(uint32_t *out);
 
 // One work item of the decode kernel: `ncb` code blocks of the same size K,
 // each cut into `nw` windows of W steps; lane l < ncb*nw of the work group
@@ -79,7 +85,8 @@ struct DecArgs {
     // (4 trellis steps of window w) the LDS byte offsets 2 * epad(pi(k)),
     // k = w * W + 4 * t4 + j, j = 0..3, relative to the block's slot
     const uint16_t *qtab;
-    int32_t max_iters, early_stop, win_init;
+    const uint32_t *mi_tab;  // kMiTabN entropy table entries (mutual-information stop)
+    int32_t max_iters, early_stop, win_init, mi_eps;
     int32_t state_slots;  // most blocks of any item (size of the per-slot LDS state)
 };
 
@@ -106,6 +113,9 @@ __host__ __device__ inline int32_t lds_e_bytes(int32_t K) { return ((epad(K - 1)
 __host__ __device__ inline int32_t lds_slot_bytes(int32_t K) { return (lds_e_bytes(K) + 63) & ~63; }
 // LDS bytes of the per-slot state that precedes the extrinsic arrays.
 __host__ __device__ inline int32_t lds_state_bytes(int32_t slots) { return (16 * slots + 63) & ~63; }
+// With the mutual-information stop, the entropy table (16-bit entries) and
+// two sums per slot follow the state.
+__host__ __device__ inline int32_t lds_mi_bytes(int32_t slots) { return (2 * kMiTabN + 8 * slots + 63) & ~63; }
 // Window length of K steps cut into nw windows: all windows but the last
 // have W = 8 ceil(K / (8 nw)) steps (K for one window), the last the rest;
 // 0 when some window would be empty.
@@ -175,8 +185,9 @@ tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tb
 // Launchers (dec_kernels.hip / enc_kernels.hip).
 // uneven: some item's windows are not all of equal length (per-lane lengths)
 // exact: exact window boundaries (win_init = 2)
-const void *decode_kernel_address(bool uneven, bool exact);
-int launch_decode(const DecArgs &a, bool uneven, bool exact, int grid, int wg_threads,
+// mi: the mutual-information stop is on (early_stop bit 1)
+const void *decode_kernel_address(bool uneven, bool exact, bool mi);
+int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, int wg_threads,
                   int lds_bytes, void *stream);
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,

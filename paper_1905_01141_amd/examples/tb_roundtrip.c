@@ -73,7 +73,7 @@ int main(int argc, char **argv)
     CHECK_HIP(hipMemcpy(d_llr, llr, (size_t)n_llr * sizeof(int16_t), hipMemcpyHostToDevice));
 
     /* decode: up to 8 iterations with CRC stop, the library's window count */
-    const tdec_params p = {8, 1, 0, 1};
+    const tdec_params p = {8, TDEC_STOP_CRC, 0, 1, 0};
     CHECK_HIP(hipMemset(d_bits, 0, nbytes));
     CHECK_TDEC(tb_decode(ctx, d_llr, tbs, &p, d_bits, d_res, NULL));
     CHECK_HIP(hipDeviceSynchronize());
