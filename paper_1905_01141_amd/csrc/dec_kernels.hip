@@ -784,36 +784,53 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                     const int lg = __builtin_ctz((unsigned)R), rs = R + 1, nl = nw * R;
                     for (int c0 = 0; c0 < W; c0 += 4 * R) {
                         const int Rc = min(R, (W - c0) >> 2);
+                        // the three streams' loads of 4 rows are all issued
+                        // before the first LDS store (12 loads in flight)
+                        for (int e0 = tid; e0 < nl; e0 += 4 * nthr) {
+                            uint2 v[3][4];
 #pragma unroll
-                        for (int st = 0; st < 3; ++st) {
-                            for (int e0 = tid; e0 < nl; e0 += 4 * nthr) {
-                                uint2 v[4];
+                            for (int st = 0; st < 3; ++st)
 #pragma unroll
                                 for (int m = 0; m < 4; ++m) {
                                     const int e = e0 + m * nthr;
                                     const int ww = e >> lg, j = e & (R - 1);
                                     const int p = ww * W + c0 + 4 * j;
-                                    v[m] = make_uint2(0u, 0u);
+                                    v[st][m] = make_uint2(0u, 0u);
                                     if (e < nl && j < Rc && p < K)
-                                        v[m] = load4(src + st * N + p, aligned);
+                                        v[st][m] = load4(src + st * N + p, aligned);
                                 }
+#pragma unroll
+                            for (int st = 0; st < 3; ++st)
 #pragma unroll
                                 for (int m = 0; m < 4; ++m) {
                                     const int e = e0 + m * nthr;
                                     const int ww = e >> lg, j = e & (R - 1);
-                                    if (e < nl && j < Rc) tile[(st * nw + ww) * rs + j] = v[m];
+                                    if (e < nl && j < Rc) tile[(st * nw + ww) * rs + j] = v[st][m];
                                 }
-                            }
                         }
                         __syncthreads();
-                        for (int e = tid; e < nw * Rc; e += nthr) {
-                            const int jj = e / nw, ww = e - jj * nw;
-                            const int t4 = (c0 >> 2) + jj;
-                            const uint2 v[3] = {tile[ww * rs + jj], tile[(nw + ww) * rs + jj],
-                                                tile[(2 * nw + ww) * rs + jj]};
-                            restage_unit(v, qt[t4 * nw + ww], ww * W + 4 * t4, cb.F, so2,
-                                         R1v + (size_t)t4 * lanes + cs * nw + ww,
-                                         R2v + (size_t)t4 * lanes + cs * nw + ww);
+                        // four units per trip: their QPP address loads first
+                        const int nu = nw * Rc;
+                        for (int e0 = tid; e0 < nu; e0 += 4 * nthr) {
+                            uint2 q[4];
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) {
+                                const int e = min(e0 + m * nthr, nu - 1);
+                                const int jj = e / nw, ww = e - jj * nw;
+                                q[m] = qt[((c0 >> 2) + jj) * nw + ww];
+                            }
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) {
+                                const int e = e0 + m * nthr;
+                                if (e >= nu) break;
+                                const int jj = e / nw, ww = e - jj * nw;
+                                const int t4 = (c0 >> 2) + jj;
+                                const uint2 v[3] = {tile[ww * rs + jj], tile[(nw + ww) * rs + jj],
+                                                    tile[(2 * nw + ww) * rs + jj]};
+                                restage_unit(v, q[m], ww * W + 4 * t4, cb.F, so2,
+                                             R1v + (size_t)t4 * lanes + cs * nw + ww,
+                                             R2v + (size_t)t4 * lanes + cs * nw + ww);
+                            }
                         }
                         __syncthreads();
                     }
