@@ -16,6 +16,9 @@
 // e_j; the true start state of chunk l is the XOR over j < l of
 // A^(L (l-1-j)) e_j, with A^7 = I because 1 + D^2 + D^3 is primitive; then
 // every lane runs its chunk again from that state and writes the parity bits.
+// The start states come from a log-depth scan across the wave's lanes: with
+// P(l) = XOR over j <= l of A^(L (l-j)) e_j, the step with offset d sets
+// P(l) ^= A^(L d) P(l - d), and chunk l starts in P(l - 1).
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -106,25 +109,36 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     __shared__ uint8_t c[kKmax];
     __shared__ uint8_t z[2][kKmax];
     __shared__ uint8_t tl[2][6];
-    __shared__ uint8_t es[2][64];
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
     const EncCb cb = cbs[blockIdx.x];
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    // input bits, one per byte; 8 loads in flight per thread
-    for (int k0 = tid; k0 < K; k0 += 8 * nthr) {
-        uint8_t v[8];
+    // input bits: the payload bytes that hold bits src_bit .. src_bit + n - 1
+    // are copied into LDS (z[0] serves as the buffer; it is written only by
+    // the second pass), then expanded to one bit per byte
+    const int n = K - F - L;
+    const int64_t byte0 = cb.src_bit >> 3;
+    const int bo = (int)(cb.src_bit & 7);
+    const int nbytes = (bo + n + 7) >> 3;
+    uint8_t *raw = z[0];
+    for (int i0 = tid; i0 < nbytes; i0 += 4 * nthr) {
+        uint8_t v[4];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int k = k0 + m * nthr;
-            v[m] = (k >= F && k < K - L) ? (uint8_t)src_bit(src, cb.src_bit + (k - F)) : (uint8_t)0;
+        for (int m = 0; m < 4; ++m) {
+            const int i = i0 + m * nthr;
+            v[m] = i < nbytes ? src[byte0 + i] : (uint8_t)0;
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (k0 + m * nthr < K) c[k0 + m * nthr] = v[m];
+        for (int m = 0; m < 4; ++m)
+            if (i0 + m * nthr < nbytes) raw[i0 + m * nthr] = v[m];
     }
     if (tid < 56) zt[tid >> 3][tid & 7] = (uint8_t)rsc_zero_steps((uint32_t)(tid & 7), tid >> 3);
+    __syncthreads();
+    for (int k = tid; k < K; k += nthr) {
+        const int b = bo + (k - F);
+        c[k] = (k >= F && k < K - L) ? (uint8_t)((raw[b >> 3] >> (7 - (b & 7))) & 1u) : (uint8_t)0;
+    }
     __syncthreads();
     if (L) {
         const uint32_t p = block_crc(c, K - L, cb.crc == 1 ? kPoly24A : kPoly24B,
@@ -171,19 +185,19 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
                 if (k + m < k1) s = rsc_step(s, u[m], &zz);
         }
     }
-    es[w][l] = (uint8_t)s;
-    __syncthreads();
     // start state of chunk l: chunks before it all have Lc steps, chunk j
-    // contributes A^(Lc (l - 1 - j)) e_j (exponents mod 7)
-    uint32_t s0 = 0;
+    // contributes A^(Lc (l - 1 - j)) e_j (exponents mod 7); inclusive scan
+    // of the wave, then the state of the lane before
+    uint32_t s0;
     {
-        const int p = Lc % 7;
-        int q = 0;
-        for (int j = l - 1; j >= 0; --j) {
-            s0 ^= zt[q][es[w][j]];
-            q += p;
-            if (q >= 7) q -= 7;
+        uint32_t P = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)P, d, 64);
+            if (l >= d) P ^= zt[(Lc * d) % 7][t];
         }
+        s0 = (uint32_t)__shfl_up((int)P, 1, 64);
+        if (l == 0) s0 = 0;
     }
     // pass 2: the chunk from its true start state
     s = s0;
@@ -211,10 +225,21 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     __syncthreads();
     uint8_t *d = out + cb.out_off;
     const int N = K + 4;
-    for (int k = tid; k < K; k += nthr) {
-        d[k] = c[k];
-        d[N + k] = z[0][k];
-        d[2 * N + k] = z[1][k];
+    // the three streams' first K bytes: byte stores up to a 4-byte boundary
+    // of the destination, then whole words assembled from LDS, then the rest
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+        const uint8_t *v = st == 0 ? c : z[st - 1];
+        uint8_t *o = d + st * N;
+        const int head = min(K, (int)((4u - ((uint32_t)(uintptr_t)o & 3u)) & 3u));
+        const int nw4 = (K - head) >> 2;
+        if (tid < head) o[tid] = v[tid];
+        for (int q = tid; q < nw4; q += nthr) {
+            const int k = head + 4 * q;
+            *(uint32_t *)(o + k) = (uint32_t)v[k] | ((uint32_t)v[k + 1] << 8) |
+                                   ((uint32_t)v[k + 2] << 16) | ((uint32_t)v[k + 3] << 24);
+        }
+        for (int k = head + 4 * nw4 + tid; k < K; k += nthr) o[k] = v[k];
     }
     if (tid < 12) {
         // x z x z x z of each encoder, read round robin into d0, d1, d2
