@@ -15,7 +15,9 @@
 // first runs its chunk from state 0 to get the chunk's zero-state end state
 // e_j; the true start state of chunk l is the XOR over j < l of
 // A^(L (l-1-j)) e_j, with A^7 = I because 1 + D^2 + D^3 is primitive; then
-// every lane runs its chunk again from that state and writes the parity bits.
+// every lane runs its chunk again from that state and writes its parity bits
+// straight to the output (the block's LDS holds only its input bits, so 16
+// blocks fit a CU).
 // The start states come from a log-depth scan across the wave's lanes: with
 // P(l) = XOR over j <= l of A^(L (l-j)) e_j, the step with offset d sets
 // P(l) ^= A^(L d) P(l - d), and chunk l starts in P(l - 1).
@@ -107,7 +109,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
                                                                    const uint32_t *crc_tab)
 {
     __shared__ uint8_t c[kKmax];
-    __shared__ uint8_t z[2][kKmax];
+    __shared__ uint8_t raw[kKmax / 8 + 2];
     __shared__ uint8_t tl[2][6];
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
@@ -115,13 +117,11 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     // input bits: the payload bytes that hold bits src_bit .. src_bit + n - 1
-    // are copied into LDS (z[0] serves as the buffer; it is written only by
-    // the second pass), then expanded to one bit per byte
+    // are copied into LDS, then expanded to one bit per byte
     const int n = K - F - L;
     const int64_t byte0 = cb.src_bit >> 3;
     const int bo = (int)(cb.src_bit & 7);
-    const int nbytes = (bo + n + 7) >> 3;
-    uint8_t *raw = z[0];
+    const int nbytes = (bo + n + 7) >> 3;  // <= kKmax / 8 + 1
     for (int i0 = tid; i0 < nbytes; i0 += 4 * nthr) {
         uint8_t v[4];
 #pragma unroll
@@ -199,18 +199,32 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         s0 = (uint32_t)__shfl_up((int)P, 1, 64);
         if (l == 0) s0 = 0;
     }
-    // pass 2: the chunk from its true start state
+    // pass 2: the chunk from its true start state; the parity bytes of 8
+    // steps go straight to the encoder's output stream, as two words when
+    // the destination is 4-byte aligned
+    uint8_t *d = out + cb.out_off;
+    const int N = K + 4;
     s = s0;
     {
+        uint8_t *oz = d + (w + 1) * N;
         uint32_t pi = pi0, g = g0, u[8];
         for (int k = k0; k < k1; k += 8) {
             inputs8(k, pi, g, u);
+            uint32_t zw[2] = {0u, 0u};
 #pragma unroll
             for (int m = 0; m < 8; ++m)
                 if (k + m < k1) {
                     s = rsc_step(s, u[m], &zz);
-                    z[w][k + m] = (uint8_t)zz;
+                    zw[m >> 2] |= zz << (8 * (m & 3));
                 }
+            uint8_t *o = oz + k;
+            const int cnt = min(8, k1 - k);
+            if (cnt == 8 && ((uint32_t)(uintptr_t)o & 3u) == 0) {
+                *(uint32_t *)o = zw[0];
+                *(uint32_t *)(o + 4) = zw[1];
+            } else {
+                for (int m = 0; m < cnt; ++m) o[m] = (uint8_t)(zw[m >> 2] >> (8 * (m & 3)));
+            }
         }
     }
     if (k0 < K && k1 == K) {
@@ -223,23 +237,20 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         }
     }
     __syncthreads();
-    uint8_t *d = out + cb.out_off;
-    const int N = K + 4;
-    // the three streams' first K bytes: byte stores up to a 4-byte boundary
-    // of the destination, then whole words assembled from LDS, then the rest
-#pragma unroll
-    for (int st = 0; st < 3; ++st) {
-        const uint8_t *v = st == 0 ? c : z[st - 1];
-        uint8_t *o = d + st * N;
+    // the systematic stream's first K bytes: byte stores up to a 4-byte
+    // boundary of the destination, then whole words assembled from LDS,
+    // then the rest
+    {
+        uint8_t *o = d;
         const int head = min(K, (int)((4u - ((uint32_t)(uintptr_t)o & 3u)) & 3u));
         const int nw4 = (K - head) >> 2;
-        if (tid < head) o[tid] = v[tid];
+        if (tid < head) o[tid] = c[tid];
         for (int q = tid; q < nw4; q += nthr) {
             const int k = head + 4 * q;
-            *(uint32_t *)(o + k) = (uint32_t)v[k] | ((uint32_t)v[k + 1] << 8) |
-                                   ((uint32_t)v[k + 2] << 16) | ((uint32_t)v[k + 3] << 24);
+            *(uint32_t *)(o + k) = (uint32_t)c[k] | ((uint32_t)c[k + 1] << 8) |
+                                   ((uint32_t)c[k + 2] << 16) | ((uint32_t)c[k + 3] << 24);
         }
-        for (int k = head + 4 * nw4 + tid; k < K; k += nthr) o[k] = v[k];
+        for (int k = head + 4 * nw4 + tid; k < K; k += nthr) o[k] = c[k];
     }
     if (tid < 12) {
         // x z x z x z of each encoder, read round robin into d0, d1, d2
