@@ -92,12 +92,7 @@ struct tdec_ctx {
 
 namespace {
 
-bool params_ok(const tdec_params *p)
-{
-    return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
-           p->early_stop <= 3 && p->n_windows >= 0 && p->win_init >= 0 && p->win_init <= 2 &&
-           p->mi_eps >= 0 && p->mi_eps <= 32768;
-}
+bool params_ok(const tdec_params *p) { return tdec::params_valid(p); }
 
 int32_t pick_windows(int32_t K)
 {
@@ -794,6 +789,13 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
 }
 
 }  // extern "C"
+
+bool tdec::params_valid(const tdec_params *p)
+{
+    return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
+           p->early_stop <= 3 && p->n_windows >= 0 && p->n_windows <= 128 && p->win_init >= 0 &&
+           p->win_init <= 2 && p->mi_eps >= 0 && p->mi_eps <= 32768;
+}
 
 tdec_status tdec::tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
                                         const int64_t *llr_off, const int64_t *bits_off,

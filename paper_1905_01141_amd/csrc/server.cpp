@@ -381,7 +381,7 @@ tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
 {
     if (!cfg || cfg->deadline_us <= 0 || cfg->max_batch_cb < 0 ||
         (cfg->mode != TDEC_SERVE_CONTINUOUS && cfg->mode != TDEC_SERVE_PER_TB) ||
-        cfg->params.max_iters < 1 || cfg->params.max_iters > 16 || cfg->model_lat_ns < 0 ||
+        !tdec::params_valid(&cfg->params) || cfg->model_lat_ns < 0 ||
         cfg->model_ns_per_kbit < 0)
         return TDEC_EINVAL;
     s->cfg = *cfg;

@@ -174,6 +174,10 @@ struct GatherArgs {
 };
 int launch_gather(const GatherArgs &g, void *stream);
 
+// The ranges tdec.h gives for every field of tdec_params (the window count
+// is checked against each block size where it is used).
+bool params_valid(const tdec_params *p);
+
 // tb_decode_batch that also records ev_start (hipEvent_t, may be null) just
 // before the decode kernel and ev_mid between it and the assembly kernel.
 tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,

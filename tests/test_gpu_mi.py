@@ -167,3 +167,41 @@ def test_mi_params_rejected(dev):
     for p in (T.params(8, 4, 1, 0), T.params(8, MI, 1, 0, -1), T.params(8, MI, 1, 0, 32769)):
         with pytest.raises(T.TdecError):
             gpu_cbs(dev, od, llr, p, n_bytes)
+
+
+def test_mi_stop_through_the_serving_loop(dev):
+    """The serving loop hands its parameters to every launch: with the MI
+    and CRC stops set, each TB comes back with the oracle's bits, verdict and
+    iteration count."""
+    import time
+    T, D, torch = dev
+    tbs_list = [75376, 40, 6120, 6121, 20000, 3000, 12000, 500]
+    esn0 = np.linspace(0.5, 4.0, len(tbs_list))
+    say(f"[mi] serving loop, tbs={tbs_list}")
+    llr, _, lo, _ = tb_batch(tbs_list, "16qam", esn0, 407)
+    pinned = torch.empty(llr.size, dtype=torch.int16, pin_memory=True)
+    pinned.numpy()[:] = llr
+    out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+    p = T.params(8, MI | CRC, 1, 0, 1)
+    srv = T.Server(D, T.server_cfg(p, deadline_us=10_000_000, mode=0))
+    try:
+        base = pinned.data_ptr()
+        for g in np.array_split(np.arange(len(tbs_list)), 2):
+            srv.submit(g.tolist(), [tbs_list[i] for i in g], [base + 2 * int(lo[i]) for i in g],
+                       [out[i].ctypes.data for i in g])
+            time.sleep(0.0005)
+        srv.drain(60000)
+        res, t0 = [], time.monotonic()
+        while len(res) < len(tbs_list) and time.monotonic() - t0 < 30:
+            res += srv.poll(4096, 100000)
+    finally:
+        srv.close()
+    res = {r["tag"]: r for r in res}
+    op = O.params(8, MI | CRC, 1, 0, 1)
+    for i, tbs in enumerate(tbs_list):
+        ob, ores = O.tb_decode(llr[lo[i]:lo[i] + O.tb_llr_count(tbs)], tbs, op)
+        r = res[i]
+        assert r["status"] == T.SERVE_DONE
+        assert r["tb_ok"] == ores["tb_ok"] and r["max_iters_used"] == ores["max_iters_used"], i
+        assert np.array_equal(out[i], ob), (i, tbs)
+
