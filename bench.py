@@ -111,16 +111,32 @@ def cpu_baseline(llr, sample_cbs: int, threads: int):
         r = O.cb_decode(llr[i * blk:(i + 1) * blk], K, 0, O.CRC24B, p)
         return r["ok"]
 
+    def timed(n, t):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=t) as ex:
+            oks = list(ex.map(one, range(n)))
+        return time.perf_counter() - t0, oks
+
     O.lib()
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        oks = list(ex.map(one, range(sample_cbs)))
-    dt = time.perf_counter() - t0
+    dt, oks = timed(sample_cbs, threads)
+    # also one thread and the paper's six dedicated cores, on 256 blocks each
+    sweep = []
+    for t in (1, 6):
+        n = min(256, sample_cbs)
+        d, _ = timed(n, t)
+        sweep.append({"threads": t, "value": round(n * PAYLOAD / d / 1e9, 6), "blocks": n})
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(sample_cbs * PAYLOAD / dt / 1e9, 6), "unit": "Gbit/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{sample_cbs} of the {N_CB} code blocks, {ITERS} iterations, "
                       f"{N_WIN} windows, one block per task; {dt:.2f} s wall, "
-                      f"{sum(oks)} CRC pass"}
+                      f"{sum(oks)} CRC pass",
+            "by_threads": sweep, "cpu": model}
 
 
 def main():
