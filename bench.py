@@ -150,7 +150,7 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="uniform",
                     choices=["uniform", "tb", "mixed", "serving", "cells", "ratematch", "encode",
-                             "stop"])
+                             "stop", "peaks"])
     ap.add_argument("--rho", type=str, default="0.25,0.5,1,2,4",
                     help="serving: load points (fractions of 40 cells' capacity)")
     ap.add_argument("--ttis", type=int, default=3000, help="serving/cells: measured TTIs")
@@ -247,6 +247,10 @@ def main():
         log(f"[bench] copy probe: {n} bytes read + {n} bytes written")
 
     cpu = None
+    # the packed int16 VALU rate this device delivers with the decoder's ACS
+    # instructions (independent chains, every CU), beside the published peak
+    valu_meas = T.probe_valu_int16(0)
+    log(f"[bench] measured packed int16 VALU rate {valu_meas:.2f} TOP/s")
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"[bench] CPU oracle baseline on {threads} threads, {args.cpu_sample} blocks")
@@ -273,7 +277,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT16_TOPS, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_INT16_TOPS, 4),
-                     "traffic": measured_traffic()},
+                     "traffic": measured_traffic(),
+                     "peak_measured": round(valu_meas, 2),
+                     "frac_of_measured": round(achieved / valu_meas, 4)},
         "cpu_baseline": cpu,
         "as_configured": as_cfg,
         "kernel_ms": round(launch_s * 1e3, 4),

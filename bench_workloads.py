@@ -282,6 +282,37 @@ def run_mixed(args):
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+def hbm_measured(achieved_gbs):
+    """The device's measured streaming copy rate (read + write, 1 GiB) beside
+    the published HBM peak."""
+    _, copy = T.probe_hbm(0, 1 << 30)
+    return {"peak_measured": round(copy, 1), "frac_of_measured": round(achieved_gbs / copy, 4)}
+
+
+def run_peaks(args):
+    """Measured device ceilings (include/tdec_probe.h): the packed int16 VALU
+    rate with the decoder's add-compare-select instructions, HBM streaming
+    read and copy bandwidth, and launch overheads."""
+    valu = [T.probe_valu_int16(0) for _ in range(3)]
+    hbm = [T.probe_hbm(0, 4 << 30) for _ in range(3)]
+    launch = T.probe_launch(0, 2000)
+    line = {"metric": "measured packed int16 VALU rate", "value": round(max(valu), 3),
+            "unit": "TOP/s", "higher_is_better": True, "n_gpus": 1, "dtype": "int16",
+            "data": "synthetic",
+            "config": {"workload": "device ceilings: 8 chains of saturating packed add + packed "
+                                   "max per lane, 8 work groups of 256 threads per CU; 16-byte "
+                                   "streaming read and copy of 4 GiB; 2000 empty launches"},
+            "published": {"valu_int16_tops": round(PEAK_INT16_TOPS, 2), "hbm_gbs": HBM_PEAK_GBS},
+            "valu_tops_runs": [round(v, 3) for v in valu],
+            "valu_frac_of_published": round(max(valu) / PEAK_INT16_TOPS, 4),
+            "hbm_read_gbs": round(max(r for r, _ in hbm), 1),
+            "hbm_copy_gbs": round(max(c for _, c in hbm), 1),
+            "hbm_read_frac_of_published": round(max(r for r, _ in hbm) / HBM_PEAK_GBS, 4),
+            "launch_us": round(launch[0], 3), "graph_node_us": round(launch[1], 3)}
+    log(f"[peaks] {line}")
+    return line
+
+
 def time_launches(torch, fn, reps=20, warm=3):
     """(device ms per launch, host ms per call) of fn() on the current stream.
     The device time is taken between HIP events around `reps` back-to-back
@@ -345,7 +376,8 @@ def run_ratematch(args):
                                    "(adds)"},
             "roofline": {"bound": "hbm", "achieved": round(gbs(rx1, ms_rx1), 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs(rx1, ms_rx1) / HBM_PEAK_GBS, 4), "traffic": None},
+                         "frac": round(gbs(rx1, ms_rx1) / HBM_PEAK_GBS, 4), "traffic": None,
+                         **hbm_measured(gbs(rx1, ms_rx1))},
             "kernels_us": {"derate_rv0": round(ms_rx0 * 1e3, 1), "derate_rv2_combine": round(ms_rx1 * 1e3, 1),
                            "rate_match_tx": round(ms_tx * 1e3, 1)},
             "gb_s": {"derate_rv0": round(gbs(rx0, ms_rx0), 1), "derate_rv2_combine": round(gbs(rx1, ms_rx1), 1),
@@ -377,7 +409,7 @@ def run_encode(args):
             "kernel_us": round(ms * 1e3, 1), "host_us_per_call": round(host * 1e3, 1),
             "roofline": {"bound": "hbm", "achieved": round(byts / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
-                         "traffic": None},
+                         "traffic": None, **hbm_measured(byts / ms / 1e6)},
             "algorithmic_bytes": byts}
     log(f"[encode] {line}")
     return line

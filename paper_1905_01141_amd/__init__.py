@@ -27,7 +27,8 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_server_destroy", "tdec_graph_cb_decode", "tdec_graph_tb_decode",
            "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
            "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch",
-           "tdec_server_launches")
+           "tdec_server_launches", "tdec_probe_valu_int16", "tdec_probe_hbm",
+           "tdec_probe_launch")
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -170,6 +171,10 @@ def lib():
         L.tdec_server_destroy.argtypes = [vp]
         L.tdec_server_destroy.restype = None
         L.tdec_server_launches.argtypes = [vp, vp, i32]
+        dp = P(ct.c_double)
+        L.tdec_probe_valu_int16.argtypes = [ct.c_int, i32, dp]
+        L.tdec_probe_hbm.argtypes = [ct.c_int, ct.c_size_t, dp, dp]
+        L.tdec_probe_launch.argtypes = [ct.c_int, i32, dp, dp]
         _lib = L
     return _lib
 
@@ -210,6 +215,27 @@ def params(max_iters=6, early_stop=0, n_windows=1, win_init=0, mi_eps=MI_EPS_DEF
     """Decoder parameters (tdec_params).  early_stop: 0, or an OR of STOP_CRC
     and STOP_MI; mi_eps: the STOP_MI threshold."""
     return Params(max_iters, early_stop, n_windows, win_init, mi_eps)
+
+
+def probe_valu_int16(device: int = 0, iters: int = 20000) -> float:
+    """Measured packed int16 VALU rate, TOP/s (include/tdec_probe.h)."""
+    v = ct.c_double()
+    _check("tdec_probe_valu_int16", lib().tdec_probe_valu_int16(device, iters, ct.byref(v)))
+    return v.value
+
+
+def probe_hbm(device: int = 0, nbytes: int = 1 << 30) -> tuple[float, float]:
+    """Measured HBM (read GB/s, copy GB/s counting read + write)."""
+    r, c = ct.c_double(), ct.c_double()
+    _check("tdec_probe_hbm", lib().tdec_probe_hbm(device, nbytes, ct.byref(r), ct.byref(c)))
+    return r.value, c.value
+
+
+def probe_launch(device: int = 0, n: int = 2000) -> tuple[float, float]:
+    """Device microseconds per back-to-back empty launch and per graph node."""
+    a, b = ct.c_double(), ct.c_double()
+    _check("tdec_probe_launch", lib().tdec_probe_launch(device, n, ct.byref(a), ct.byref(b)))
+    return a.value, b.value
 
 
 def segment(tbs: int) -> dict:

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtdec.so")
 SOURCES = ["csrc/api.cpp", "csrc/tables.cpp", "csrc/server.cpp", "csrc/dec_kernels.hip",
-           "csrc/enc_kernels.hip", "csrc/serve_kernels.hip", "csrc/rm_kernels.hip"]
+           "csrc/enc_kernels.hip", "csrc/serve_kernels.hip", "csrc/rm_kernels.hip",
+           "csrc/probe_kernels.hip"]
 ARCH = os.environ.get("TDEC_ARCH", "gfx950")
 
 

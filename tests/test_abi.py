@@ -89,3 +89,15 @@ def test_c_example_builds_against_the_header_alone(tmp_path):
     r = subprocess.run(B.example_cmd(out), capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert os.path.exists(out)
+
+
+def test_probes_check_their_arguments():
+    """The device probes refuse bad arguments before touching a device."""
+    L = T.lib()
+    d = ct.c_double()
+    assert L.tdec_probe_valu_int16(0, 0, ct.byref(d)) == -1
+    assert L.tdec_probe_valu_int16(0, 1000001, ct.byref(d)) == -1
+    assert L.tdec_probe_valu_int16(0, 10, None) == -1
+    assert L.tdec_probe_hbm(0, 1 << 20, ct.byref(d), ct.byref(d)) == -1      # below 16 MiB
+    assert L.tdec_probe_hbm(0, (16 << 20) + 8, ct.byref(d), ct.byref(d)) == -1  # not a multiple of 16
+    assert L.tdec_probe_launch(0, 0, ct.byref(d), ct.byref(d)) == -1
