@@ -95,7 +95,9 @@ def test_mi_stop_mixed_sizes_one_launch(dev):
         assert np.array_equal(gb[o.bits_off:o.bits_off + nb], want[:nb]), i
 
 
-@pytest.mark.parametrize("K,nw", [(6144, 32), (1024, 16), (40, 5)])
+@pytest.mark.parametrize("K,nw", [(6144, 32), (1024, 16), (40, 5),
+                                  (5824, 122),   # uneven: 121 of 48, the last of 16
+                                  (488, 8)])     # uneven: 7 of 64, the last of 40
 def test_mi_stop_exact_windows_equal_full_length(dev, K, nw):
     T = dev[0]
     n = 8
