@@ -249,7 +249,7 @@ def main():
     cpu = None
     # the packed int16 VALU rate this device delivers with the decoder's ACS
     # instructions (independent chains, every CU), beside the published peak
-    valu_meas = T.probe_valu_int16(0)
+    valu_meas = max(T.probe_valu_int16(0) for _ in range(3))  # the first run is the lowest
     log(f"[bench] measured packed int16 VALU rate {valu_meas:.2f} TOP/s")
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
