@@ -134,11 +134,14 @@ struct tdec_server {
     hipEvent_t copy_ev[kCopyEvents] = {};
     hipEvent_t done_ev = nullptr;
     hipEvent_t ev_s = nullptr, ev_m = nullptr;  // around the decode kernel (timing)
-    hipEvent_t ev_c = nullptr;                  // before the copies back (timing)
+    hipEvent_t ev_c = nullptr;                  // after the assembly kernel (timing)
     uint64_t copy_seq = 0;  // events recorded so far
-    uint8_t *d_bits = nullptr, *h_bits_stage = nullptr;
+    // Results land in mapped pinned host memory: the assembly kernel writes the
+    // payload bits and per-TB records straight over PCIe (device addresses
+    // hd_*), so no copy back follows the launch.
+    uint8_t *h_bits_stage = nullptr, *hd_bits = nullptr;
     size_t bits_cap = 0;
-    tdec_tb_result *d_res = nullptr, *h_res = nullptr;
+    tdec_tb_result *h_res = nullptr, *hd_res = nullptr;
     int32_t res_cap = 0;
     std::mutex submit_mu;  // serialises submitters (held across their copies)
     // queue state (under mu)
@@ -206,14 +209,10 @@ void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server
     }
     bool ok = hipStreamWaitEvent(s->dec_st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
     ok = ok && tdec::tb_decode_batch_timed(s->ctx, n, tbs.data(), lo.data(), bo.data(), s->d_arena,
-                                           &s->cfg.params, s->d_bits, s->d_res, s->dec_st,
+                                           &s->cfg.params, s->hd_bits, s->hd_res, s->dec_st,
                                            s->ev_s, s->ev_m) == TDEC_OK;
     const int64_t t_enq = mono_ns();
     ok = ok && hipEventRecord(s->ev_c, s->dec_st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(s->h_bits_stage, s->d_bits, (size_t)bytes, hipMemcpyDeviceToHost,
-                              s->dec_st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(s->h_res, s->d_res, sizeof(tdec_tb_result) * (size_t)n,
-                              hipMemcpyDeviceToHost, s->dec_st) == hipSuccess;
     ok = ok && hipEventRecord(s->done_ev, s->dec_st) == hipSuccess;
     ok = ok && hipEventSynchronize(s->done_ev) == hipSuccess;
     float coding_ms = 0.f, post_ms = 0.f, copy_ms = 0.f;
@@ -363,8 +362,6 @@ void free_device(tdec_server *s)
     if (s->model) return;
     (void)hipSetDevice(s->device);
     if (s->d_arena) (void)hipFree(s->d_arena);
-    if (s->d_bits) (void)hipFree(s->d_bits);
-    if (s->d_res) (void)hipFree(s->d_res);
     if (s->h_bits_stage) (void)hipHostFree(s->h_bits_stage);
     if (s->h_res) (void)hipHostFree(s->h_res);
     for (auto &e : s->copy_ev)
@@ -420,11 +417,11 @@ tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_s
     s->bits_cap = (size_t)s->cfg.max_batch_cb * 768 + 64;
     s->res_cap = s->cfg.max_batch_cb;
     bool ok = hipMalloc(&s->d_arena, s->cfg.slot_budget_bytes) == hipSuccess &&
-              hipMalloc(&s->d_bits, s->bits_cap) == hipSuccess &&
-              hipMalloc(&s->d_res, sizeof(tdec_tb_result) * (size_t)s->res_cap) == hipSuccess &&
-              hipHostMalloc(&s->h_bits_stage, s->bits_cap, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->h_bits_stage, s->bits_cap, hipHostMallocMapped) == hipSuccess &&
               hipHostMalloc(&s->h_res, sizeof(tdec_tb_result) * (size_t)s->res_cap,
-                            hipHostMallocDefault) == hipSuccess &&
+                            hipHostMallocMapped) == hipSuccess &&
+              hipHostGetDevicePointer((void **)&s->hd_bits, s->h_bits_stage, 0) == hipSuccess &&
+              hipHostGetDevicePointer((void **)&s->hd_res, s->h_res, 0) == hipSuccess &&
               hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&s->dec_st, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreate(&s->done_ev) == hipSuccess && hipEventCreate(&s->ev_s) == hipSuccess &&
