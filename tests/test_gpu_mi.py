@@ -173,7 +173,7 @@ def test_mi_params_rejected(dev):
 
 def test_mi_stop_through_the_serving_loop(dev):
     """The serving loop hands its parameters to every launch: with the MI
-    and CRC stops set, each TB comes back with the oracle's bits, verdict and
+    and CRC stops set, each TB comes back with the oracle's bits, pass flag and
     iteration count."""
     import time
     T, D, torch = dev
