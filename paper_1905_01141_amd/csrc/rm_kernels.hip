@@ -10,7 +10,9 @@
 
 namespace tdec {
 
-constexpr int kRmThreads = 512;  // per block: 8 waves, the loads of four blocks per CU in flight
+// Threads per block: the LDS buffer allows four blocks per CU, and 512
+// threads each keep 32 waves of loads in flight there.
+constexpr int kRmThreads = 512;
 
 // One work group per code block; the block's [3][K+4] buffer is staged in
 // LDS (read, or cleared for a first transmission, and written back once), so
@@ -24,8 +26,8 @@ constexpr int kRmThreads = 512;  // per block: 8 waves, the loads of four blocks
 // 8-byte words (n = 3 (K + 4) is a multiple of 4), four loads in flight.
 template <typename T>
 __global__ void __launch_bounds__(kRmThreads) derate_kernel(const RmItem *items, const T *e,
-                                                     int16_t *soft, const uint16_t *tab,
-                                                     int combine)
+                                                            int16_t *soft, const uint16_t *tab,
+                                                            int combine)
 {
     extern __shared__ __align__(16) int16_t sb[];
     const RmItem it = items[blockIdx.x];
@@ -87,8 +89,9 @@ __global__ void __launch_bounds__(kRmThreads) derate_kernel(const RmItem *items,
 
 // One work group per code block: the block's coded bits are staged in LDS,
 // then the transmission reads them in circular-buffer order.
-__global__ void __launch_bounds__(kRmThreads) rate_match_kernel(const RmItem *items, const uint8_t *coded,
-                                                         uint8_t *e, const uint16_t *tab)
+__global__ void __launch_bounds__(kRmThreads) rate_match_kernel(const RmItem *items,
+                                                                const uint8_t *coded, uint8_t *e,
+                                                                const uint16_t *tab)
 {
     extern __shared__ __align__(16) uint8_t cbits[];
     const RmItem it = items[blockIdx.x];
