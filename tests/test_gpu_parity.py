@@ -256,8 +256,8 @@ def test_encoder_parity(dev):
         g3 = got[td[i].llr_off:td[i].llr_off + 3 * (K + 4)].reshape(3, K + 4)
         ref[:2, :F] = 0
         assert np.array_equal(g3, ref), (K, F, crc)
-    # block payloads start at bit offsets of every residue mod 8 across these sizes
-    for tbs in (1, 16, 6121, 12345, 30001, 75376):
+    # 6121..6128: block 1's payload starts at bit offsets of every residue mod 8
+    for tbs in (1, 16, 6121, 6122, 6123, 6124, 6125, 6126, 6127, 6128, 12345, 30001, 75376):
         pay_bits = g.integers(0, 2, tbs).astype(np.uint8)
         packed = np.packbits(pay_bits)
         out = torch.zeros(T.tb_llr_count(tbs), dtype=torch.uint8, device="cuda")
