@@ -11,16 +11,20 @@
 // staged in LDS, the block CRC is computed by per-thread LFSR chunks combined
 // with the x^m mod g table, and each wave runs one RSC encoder with its 64
 // lanes on 64 consecutive chunks of the block.  An RSC encoder is linear over
-// GF(2) (state s = (a_{k-1}, a_{k-2}, a_{k-3}), s' = A s + b u): every lane
-// first runs its chunk from state 0 to get the chunk's zero-state end state
-// e_j; the true start state of chunk l is the XOR over j < l of
-// A^(L (l-1-j)) e_j, with A^7 = I because 1 + D^2 + D^3 is primitive; then
-// every lane runs its chunk again from that state and writes its parity bits
-// straight to the output (the block's LDS holds only its input bits, so 16
-// blocks fit a CU).
-// The start states come from a log-depth scan across the wave's lanes: with
-// P(l) = XOR over j <= l of A^(L (l-j)) e_j, the step with offset d sets
-// P(l) ^= A^(L d) P(l - d), and chunk l starts in P(l - 1).
+// GF(2) (state s = (a_{k-1}, a_{k-2}, a_{k-3}), s' = A s + b u), so a chunk's
+// output is its zero-state response plus the zero-input response of its
+// start state.  Each lane gathers its chunk's input bits into a 128-bit word
+// and computes the zero-state response with word operations (the feedback's
+// impulse response is 7-periodic); the start state of chunk l is the XOR over
+// j < l of A^(L (l-1-j)) e_j, e_j being chunk j's zero-state end state, with
+// A^7 = I because 1 + D^2 + D^3 is primitive.  The start states come from a
+// log-depth scan across the wave's lanes: with P(l) = XOR over j <= l of
+// A^(L (l-j)) e_j, the step with offset d sets P(l) ^= A^(L d) P(l - d), and
+// chunk l starts in P(l - 1).  The zero-input parity from a state is
+// 7-periodic too, so the true parity is one more XOR.  The parity bits are
+// ORed into the encoder's LDS bit array, and the work group writes all three
+// streams with coalesced stores (the block's LDS holds its input bits, one
+// per byte, and the two parity bit arrays, so 16 blocks fit a CU).
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -102,6 +106,14 @@ __device__ static inline uint32_t rsc_zero_steps(uint32_t s, int p)
 }
 
 constexpr int kEncThreads = 128;  // two waves: encoder 1 and encoder 2
+typedef unsigned __int128 u128;
+constexpr int kPzWords = kKmax / 32 + 2;  // parity bit array; one spare word for 8-bit reads
+
+// One byte per bit of a 4-bit value: bit j of n becomes byte j.
+__device__ static inline uint32_t spread4(uint32_t n)
+{
+    return (n & 1u) | ((n & 2u) << 7) | ((n & 4u) << 14) | ((n & 8u) << 21);
+}
 
 __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *cbs,
                                                                    const uint8_t *src,
@@ -113,15 +125,16 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     __shared__ uint8_t tl[2][6];
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
+    __shared__ uint32_t pz[2][kPzWords];  // parity bit k of encoder w: bit k % 32 of pz[w][k / 32]
     const EncCb cb = cbs[blockIdx.x];
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    // input bits: the payload bytes that hold bits src_bit .. src_bit + n - 1
+    // input bits: the payload bytes that hold bits src_bit .. src_bit + n_in - 1
     // are copied into LDS, then expanded to one bit per byte
-    const int n = K - F - L;
+    const int n_in = K - F - L;
     const int64_t byte0 = cb.src_bit >> 3;
     const int bo = (int)(cb.src_bit & 7);
-    const int nbytes = (bo + n + 7) >> 3;  // <= kKmax / 8 + 1
+    const int nbytes = (bo + n_in + 7) >> 3;  // <= kKmax / 8 + 1
     for (int i0 = tid; i0 < nbytes; i0 += 4 * nthr) {
         uint8_t v[4];
 #pragma unroll
@@ -134,6 +147,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
             if (i0 + m * nthr < nbytes) raw[i0 + m * nthr] = v[m];
     }
     if (tid < 56) zt[tid >> 3][tid & 7] = (uint8_t)rsc_zero_steps((uint32_t)(tid & 7), tid >> 3);
+    for (int i = tid; i < 2 * kPzWords; i += nthr) pz[i / kPzWords][i % kPzWords] = 0u;
     __syncthreads();
     for (int k = tid; k < K; k += nthr) {
         const int b = bo + (k - F);
@@ -147,50 +161,66 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         __syncthreads();
     }
     // wave w runs encoder w + 1 (w = 1: input c'_k = c_{pi(k)}); lane l the
-    // steps [l Lc, min(K, (l + 1) Lc))
+    // n steps [l Lc, min(K, (l + 1) Lc)), Lc <= 96
     const int w = tid >> 6, l = tid & 63;
     const int Lc = (K + 63) / 64;
-    const int k0 = l * Lc, k1 = min(K, k0 + Lc);
+    const int k0 = l * Lc, n = max(0, min(K, k0 + Lc) - k0);
     const uint32_t uK = (uint32_t)K;
-    // QPP pi(k0) = (f1 k0 + f2 k0^2) mod K and its increment
-    // g(k0) = pi(k0 + 1) - pi(k0) = f1 + f2 (2 k0 + 1) mod K
-    const uint32_t pi0 = ((uint32_t)cb.f1 * (uint32_t)k0 % uK +
-                          (uint32_t)cb.f2 * ((uint32_t)k0 * (uint32_t)k0 % uK) % uK) % uK;
-    const uint32_t g0 = ((uint32_t)cb.f1 + (uint32_t)cb.f2 * (2u * (uint32_t)k0 + 1u)) % uK;
-    const uint32_t f2x2 = (2u * (uint32_t)cb.f2) % uK;
-    // The chunk's inputs, 8 steps at a time: the 8 reads go out before the
-    // serial steps use them.
-    auto inputs8 = [&](int k, uint32_t &pi, uint32_t &g, uint32_t u[8]) {
+    // The chunk's input bits, bit k = input of step k0 + k.  Encoder 1 reads
+    // c in order; encoder 2 reads c_{pi(k)} with the QPP pi(k0) = (f1 k0 +
+    // f2 k0^2) mod K and its increment g(k) = pi(k + 1) - pi(k) = f1 + f2
+    // (2 k + 1) mod K, which grows by 2 f2 per step.  Reads run on to a whole
+    // number of words; every index stays below K and bits past n are unused.
+    uint32_t pi, g, dg;
+    if (w == 0) {
+        pi = k0 < K ? (uint32_t)k0 : 0u;
+        g = 1u;
+        dg = 0u;
+    } else {
+        const uint32_t kk = (uint32_t)k0;
+        pi = ((uint32_t)cb.f1 * kk % uK + (uint32_t)cb.f2 * (kk * kk % uK) % uK) % uK;
+        g = ((uint32_t)cb.f1 + (uint32_t)cb.f2 * (2u * kk + 1u)) % uK;
+        dg = (2u * (uint32_t)cb.f2) % uK;
+    }
+    const int nw = (Lc + 31) >> 5;
+    uint32_t wv[3] = {0u, 0u, 0u};
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (w == 0) {
-                u[m] = k + m < k1 ? c[k + m] : 0u;
-            } else {
-                u[m] = k + m < k1 ? c[pi] : 0u;
-                pi += g;
-                if (pi >= uK) pi -= uK;
-                g += f2x2;
-                if (g >= uK) g -= uK;
+    for (int j = 0; j < 3; ++j) {
+        if (j < nw) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int m = 0; m < 32; ++m) {
+                x |= (uint32_t)c[pi] << m;
+                pi = min(pi + g, pi + g - uK);  // both below K: one of the two is the sum mod K
+                g = min(g + dg, g + dg - uK);
             }
-        }
-    };
-    // pass 1: end state of the chunk from state 0
-    uint32_t s = 0, zz;
-    {
-        uint32_t pi = pi0, g = g0, u[8];
-        for (int k = k0; k < k1; k += 8) {
-            inputs8(k, pi, g, u);
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-                if (k + m < k1) s = rsc_step(s, u[m], &zz);
+            wv[j] = x;
         }
     }
+    // Zero-state response a = u / (1 + D^2 + D^3).  The feedback's impulse
+    // response is periodic with period 7 (the polynomial is primitive), one
+    // period being 1 0 1 1 1 0 0, so a_k = V_k + V_{k-2} + V_{k-3} + V_{k-4}
+    // over GF(2) with V_k the sum of u_{k-7q}, q >= 0: a stride-7 prefix XOR
+    // by doubling.  Bit k of a 128-bit word is step k.
+    const u128 U = (u128)wv[0] | ((u128)wv[1] << 32) | ((u128)wv[2] << 64);
+    u128 V = U;
+    V ^= V << 7;
+    V ^= V << 14;
+    V ^= V << 28;
+    V ^= V << 56;
+    V ^= V << 112;
+    const u128 av = V ^ (V << 2) ^ (V << 3) ^ (V << 4);
+    const u128 zs = av ^ (av << 1) ^ (av << 3);  // z_k = a_k + a_{k-1} + a_{k-3}
+    // the chunk's end state from state 0: (a_{n-1}, a_{n-2}, a_{n-3}) as
+    // state bits 0, 1, 2 (a_j = 0 for j < 0)
+    const uint32_t t3 = (uint32_t)((av << 3) >> n) & 7u;
+    const uint32_t e = ((t3 & 1u) << 2) | (t3 & 2u) | (t3 >> 2);
     // start state of chunk l: chunks before it all have Lc steps, chunk j
     // contributes A^(Lc (l - 1 - j)) e_j (exponents mod 7); inclusive scan
     // of the wave, then the state of the lane before
     uint32_t s0;
     {
-        uint32_t P = s;
+        uint32_t P = e;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t t = (uint32_t)__shfl_up((int)P, d, 64);
@@ -199,36 +229,39 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         s0 = (uint32_t)__shfl_up((int)P, 1, 64);
         if (l == 0) s0 = 0;
     }
-    // pass 2: the chunk from its true start state; the parity bytes of 8
-    // steps go straight to the encoder's output stream, as two words when
-    // the destination is 4-byte aligned
+    // The true parity adds the zero-input response from s0, whose parity is
+    // periodic with period 7 from the chunk's first step (A^7 = I).
+    uint32_t zz, zp = 0, sz = s0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        sz = rsc_step(sz, 0u, &zz);
+        zp |= zz << j;
+    }
+    u128 R = zp;
+    R |= R << 7;
+    R |= R << 14;
+    R |= R << 28;
+    R |= R << 56;
+    R |= R << 112;
     uint8_t *d = out + cb.out_off;
     const int N = K + 4;
-    s = s0;
-    {
-        uint8_t *oz = d + (w + 1) * N;
-        uint32_t pi = pi0, g = g0, u[8];
-        for (int k = k0; k < k1; k += 8) {
-            inputs8(k, pi, g, u);
-            uint32_t zw[2] = {0u, 0u};
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-                if (k + m < k1) {
-                    s = rsc_step(s, u[m], &zz);
-                    zw[m >> 2] |= zz << (8 * (m & 3));
-                }
-            uint8_t *o = oz + k;
-            const int cnt = min(8, k1 - k);
-            if (cnt == 8 && ((uint32_t)(uintptr_t)o & 3u) == 0) {
-                *(uint32_t *)o = zw[0];
-                *(uint32_t *)(o + 4) = zw[1];
-            } else {
-                for (int m = 0; m < cnt; ++m) o[m] = (uint8_t)(zw[m >> 2] >> (8 * (m & 3)));
-            }
-        }
+    if (n > 0) {
+        // the n parity bits into the LDS bit array at k0: the words from
+        // k0 / 32 to (k0 + n - 1) / 32, shared with the neighbouring chunks
+        const u128 z = (zs ^ R) & (((u128)1 << n) - 1);
+        const int off = k0 & 31;
+        const u128 X = z << off;  // off + n <= 127
+        const int nwo = (off + n + 31) >> 5;
+        uint32_t *pw = pz[w] + (k0 >> 5);
+        atomicOr(&pw[0], (uint32_t)X);
+        if (nwo > 1) atomicOr(&pw[1], (uint32_t)(X >> 32));
+        if (nwo > 2) atomicOr(&pw[2], (uint32_t)(X >> 64));
+        if (nwo > 3) atomicOr(&pw[3], (uint32_t)(X >> 96));
     }
-    if (k0 < K && k1 == K) {
-        // termination after the last step: input = feedback, so a = 0
+    if (n > 0 && k0 + n == K) {
+        // termination after the last step, from the state A^n s0 + e there:
+        // input = feedback, so a = 0
+        uint32_t s = e ^ zt[n % 7][s0];
         for (int j = 0; j < 3; ++j) {
             const uint32_t u = ((s >> 1) ^ (s >> 2)) & 1u;
             s = rsc_step(s, u, &zz);
@@ -251,6 +284,25 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
                                    ((uint32_t)c[k + 2] << 16) | ((uint32_t)c[k + 3] << 24);
         }
         for (int k = head + 4 * nw4 + tid; k < K; k += nthr) o[k] = c[k];
+    }
+    // the parity streams' first K bytes from the bit arrays: byte stores up
+    // to an 8-byte boundary of the destination, then 8 bytes per store, then
+    // the rest
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        uint8_t *o = d + (e + 1) * N;
+        const uint32_t *pw = pz[e];
+        const int head = min(K, (int)((8u - ((uint32_t)(uintptr_t)o & 7u)) & 7u));
+        const int n8 = (K - head) >> 3;
+        if (tid < head) o[tid] = (uint8_t)((pw[tid >> 5] >> (tid & 31)) & 1u);
+        for (int q = tid; q < n8; q += nthr) {
+            const int k = head + 8 * q;
+            const uint64_t v = ((uint64_t)pw[(k >> 5) + 1] << 32) | pw[k >> 5];
+            const uint32_t b = (uint32_t)(v >> (k & 31)) & 0xFFu;
+            *(uint2 *)(o + k) = make_uint2(spread4(b & 0xFu), spread4(b >> 4));
+        }
+        for (int k = head + 8 * n8 + tid; k < K; k += nthr)
+            o[k] = (uint8_t)((pw[k >> 5] >> (k & 31)) & 1u);
     }
     if (tid < 12) {
         // x z x z x z of each encoder, read round robin into d0, d1, d2

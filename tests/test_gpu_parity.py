@@ -214,7 +214,8 @@ def test_encoder_parity_every_size(dev):
     cbs = [(int(K), int(g.integers(0, 16)) if K >= 64 else 0, crcs[i % 3]) for i, K in enumerate(Ks)]
     td, n_llr, n_bytes = T.make_descs(cbs)
     pay = g.integers(0, 256, n_bytes).astype(np.uint8)
-    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    # every output byte must be written: start from a pattern that no coded bit has
+    coded = torch.full((n_llr,), 0xAA, dtype=torch.uint8, device="cuda")
     say(f"[enc] cb_encode_batch of {len(cbs)} sizes")
     D.cb_encode_batch(td, torch.from_numpy(pay).cuda(), coded)
     torch.cuda.synchronize()
@@ -239,7 +240,7 @@ def test_encoder_parity(dev):
     cbs = [(40, 0, O.CRC24B), (6144, 0, O.CRC24B), (1056, 9, O.CRC24A), (512, 3, O.CRC_NONE)]
     td, n_llr, n_bytes = T.make_descs(cbs)
     pay = g.integers(0, 256, n_bytes).astype(np.uint8)
-    coded = torch.zeros(n_llr, dtype=torch.uint8, device="cuda")
+    coded = torch.full((n_llr,), 0xAA, dtype=torch.uint8, device="cuda")
     say("[enc] cb_encode_batch")
     D.cb_encode_batch(td, torch.from_numpy(pay).cuda(), coded)
     torch.cuda.synchronize()
@@ -260,7 +261,7 @@ def test_encoder_parity(dev):
     for tbs in (1, 16, 6121, 6122, 6123, 6124, 6125, 6126, 6127, 6128, 12345, 30001, 75376):
         pay_bits = g.integers(0, 2, tbs).astype(np.uint8)
         packed = np.packbits(pay_bits)
-        out = torch.zeros(T.tb_llr_count(tbs), dtype=torch.uint8, device="cuda")
+        out = torch.full((T.tb_llr_count(tbs),), 0xAA, dtype=torch.uint8, device="cuda")
         say(f"[enc] tb_encode {tbs}")
         D.tb_encode(torch.from_numpy(packed).cuda(), tbs, out)
         torch.cuda.synchronize()
