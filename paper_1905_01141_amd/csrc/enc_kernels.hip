@@ -108,6 +108,7 @@ __device__ static inline uint32_t rsc_zero_steps(uint32_t s, int p)
 constexpr int kEncThreads = 128;  // two waves: encoder 1 and encoder 2
 typedef unsigned __int128 u128;
 constexpr int kPzWords = kKmax / 32 + 2;  // parity bit array; one spare word for 8-bit reads
+constexpr int kCwWords = kKmax / 32 + 4;  // input bit array; spare words for 128-bit reads
 
 // One byte per bit of a 4-bit value: bit j of n becomes byte j.
 __device__ static inline uint32_t spread4(uint32_t n)
@@ -126,11 +127,13 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
     __shared__ uint32_t pz[2][kPzWords];  // parity bit k of encoder w: bit k % 32 of pz[w][k / 32]
+    __shared__ uint32_t cw[kCwWords];     // input bit k: bit k % 32 of cw[k / 32]
     const EncCb cb = cbs[blockIdx.x];
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     // input bits: the payload bytes that hold bits src_bit .. src_bit + n_in - 1
-    // are copied into LDS, then expanded to one bit per byte
+    // are copied into LDS, then expanded to one bit per byte (c) and to a bit
+    // array (cw, one ballot per wave and trip)
     const int n_in = K - F - L;
     const int64_t byte0 = cb.src_bit >> 3;
     const int bo = (int)(cb.src_bit & 7);
@@ -148,16 +151,30 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     }
     if (tid < 56) zt[tid >> 3][tid & 7] = (uint8_t)rsc_zero_steps((uint32_t)(tid & 7), tid >> 3);
     for (int i = tid; i < 2 * kPzWords; i += nthr) pz[i / kPzWords][i % kPzWords] = 0u;
+    for (int i = tid; i < kCwWords; i += nthr) cw[i] = 0u;
     __syncthreads();
-    for (int k = tid; k < K; k += nthr) {
-        const int b = bo + (k - F);
-        c[k] = (k >= F && k < K - L) ? (uint8_t)((raw[b >> 3] >> (7 - (b & 7))) & 1u) : (uint8_t)0;
+    for (int kb = 0; kb < K; kb += nthr) {
+        const int k = kb + tid, b = bo + (k - F);
+        const uint32_t bit =
+            (k >= F && k < K - L) ? (uint32_t)((raw[b >> 3] >> (7 - (b & 7))) & 1u) : 0u;
+        if (k < K) c[k] = (uint8_t)bit;
+        const uint64_t m = __ballot(bit);
+        const int base = kb + (tid & ~63);  // the wave's first k, a multiple of 64
+        if ((tid & 63) == 0 && base < K) {
+            cw[base >> 5] = (uint32_t)m;
+            cw[(base >> 5) + 1] = (uint32_t)(m >> 32);
+        }
     }
     __syncthreads();
     if (L) {
         const uint32_t p = block_crc(c, K - L, cb.crc == 1 ? kPoly24A : kPoly24B,
                                      crc_tab + (cb.crc == 1 ? 0 : kCrcTabN), &acc);
-        if (tid < 24) c[K - 24 + tid] = (uint8_t)((p >> (23 - tid)) & 1u);
+        if (tid < 24) {
+            const int k = K - 24 + tid;
+            const uint32_t bit = (p >> (23 - tid)) & 1u;
+            c[k] = (uint8_t)bit;
+            if (bit) atomicOr(&cw[k >> 5], 1u << (k & 31));
+        }
         __syncthreads();
     }
     // wave w runs encoder w + 1 (w = 1: input c'_k = c_{pi(k)}); lane l the
@@ -166,43 +183,45 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     const int Lc = (K + 63) / 64;
     const int k0 = l * Lc, n = max(0, min(K, k0 + Lc) - k0);
     const uint32_t uK = (uint32_t)K;
-    // The chunk's input bits, bit k = input of step k0 + k.  Encoder 1 reads
-    // c in order; encoder 2 reads c_{pi(k)} with the QPP pi(k0) = (f1 k0 +
-    // f2 k0^2) mod K and its increment g(k) = pi(k + 1) - pi(k) = f1 + f2
-    // (2 k + 1) mod K, which grows by 2 f2 per step.  Reads run on to a whole
-    // number of words; every index stays below K and bits past n are unused.
-    uint32_t pi, g, dg;
+    // The chunk's input bits, bit k = input of step k0 + k; bits past n are
+    // never used.  Encoder 1 takes them from the bit array (k0 <= 63 Lc <=
+    // 6048, so the four words lie in it).  Encoder 2 gathers c_{pi(k)} with the
+    // QPP pi(k0) = (f1 k0 + f2 k0^2) mod K and its increment g(k) = pi(k + 1) -
+    // pi(k) = f1 + f2 (2 k + 1) mod K, which grows by 2 f2 per step; its reads
+    // run on to a whole number of words, every index staying below K.
+    u128 U;
     if (w == 0) {
-        pi = k0 < K ? (uint32_t)k0 : 0u;
-        g = 1u;
-        dg = 0u;
+        const int i = k0 >> 5;
+        const u128 X = (u128)cw[i] | ((u128)cw[i + 1] << 32) | ((u128)cw[i + 2] << 64) |
+                       ((u128)cw[i + 3] << 96);
+        U = X >> (k0 & 31);
     } else {
         const uint32_t kk = (uint32_t)k0;
-        pi = ((uint32_t)cb.f1 * kk % uK + (uint32_t)cb.f2 * (kk * kk % uK) % uK) % uK;
-        g = ((uint32_t)cb.f1 + (uint32_t)cb.f2 * (2u * kk + 1u)) % uK;
-        dg = (2u * (uint32_t)cb.f2) % uK;
-    }
-    const int nw = (Lc + 31) >> 5;
-    uint32_t wv[3] = {0u, 0u, 0u};
+        uint32_t pi = ((uint32_t)cb.f1 * kk % uK + (uint32_t)cb.f2 * (kk * kk % uK) % uK) % uK;
+        uint32_t g = ((uint32_t)cb.f1 + (uint32_t)cb.f2 * (2u * kk + 1u)) % uK;
+        const uint32_t dg = (2u * (uint32_t)cb.f2) % uK;
+        const int nw = (Lc + 31) >> 5;
+        uint32_t wv[3] = {0u, 0u, 0u};
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        if (j < nw) {
-            uint32_t x = 0;
+        for (int j = 0; j < 3; ++j) {
+            if (j < nw) {
+                uint32_t x = 0;
 #pragma unroll
-            for (int m = 0; m < 32; ++m) {
-                x |= (uint32_t)c[pi] << m;
-                pi = min(pi + g, pi + g - uK);  // both below K: one of the two is the sum mod K
-                g = min(g + dg, g + dg - uK);
+                for (int m = 0; m < 32; ++m) {
+                    x |= (uint32_t)c[pi] << m;
+                    pi = min(pi + g, pi + g - uK);  // both below K: one of the two is the sum mod K
+                    g = min(g + dg, g + dg - uK);
+                }
+                wv[j] = x;
             }
-            wv[j] = x;
         }
+        U = (u128)wv[0] | ((u128)wv[1] << 32) | ((u128)wv[2] << 64);
     }
     // Zero-state response a = u / (1 + D^2 + D^3).  The feedback's impulse
     // response is periodic with period 7 (the polynomial is primitive), one
     // period being 1 0 1 1 1 0 0, so a_k = V_k + V_{k-2} + V_{k-3} + V_{k-4}
     // over GF(2) with V_k the sum of u_{k-7q}, q >= 0: a stride-7 prefix XOR
     // by doubling.  Bit k of a 128-bit word is step k.
-    const u128 U = (u128)wv[0] | ((u128)wv[1] << 32) | ((u128)wv[2] << 64);
     u128 V = U;
     V ^= V << 7;
     V ^= V << 14;
