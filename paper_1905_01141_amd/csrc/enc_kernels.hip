@@ -7,24 +7,27 @@
 // g0 = 1 + D^2 + D^3 (feedback), g1 = 1 + D + D^3 (parity), QPP
 // interleaver, 3-step termination of each encoder.
 //
-// One work group of two waves per code block: the block's input bits are
-// staged in LDS, the block CRC is computed by per-thread LFSR chunks combined
-// with the x^m mod g table, and each wave runs one RSC encoder with its 64
-// lanes on 64 consecutive chunks of the block.  An RSC encoder is linear over
-// GF(2) (state s = (a_{k-1}, a_{k-2}, a_{k-3}), s' = A s + b u), so a chunk's
-// output is its zero-state response plus the zero-input response of its
-// start state.  Each lane gathers its chunk's input bits into a 128-bit word
-// and computes the zero-state response with word operations (the feedback's
-// impulse response is 7-periodic); the start state of chunk l is the XOR over
-// j < l of A^(L (l-1-j)) e_j, e_j being chunk j's zero-state end state, with
-// A^7 = I because 1 + D^2 + D^3 is primitive.  The start states come from a
+// One work group of two waves per code block.  The block's payload bytes are
+// staged in LDS and turned into the input bits as 32-bit words (a bit array);
+// the block CRC is computed over those words by 64-bit chunks per thread, 4
+// bits per table step, combined with the x^m mod g table; and each wave runs
+// one RSC encoder with its 64 lanes on 64 consecutive chunks of the block.
+// An RSC encoder is linear over GF(2) (state s = (a_{k-1}, a_{k-2},
+// a_{k-3}), s' = A s + b u), so a chunk's output is its zero-state response
+// plus the zero-input response of its start state.  Each lane takes its
+// chunk's input bits as a 128-bit word (encoder 1 straight from the bit
+// array, encoder 2 gathered through the interleaver) and computes the
+// zero-state response with word operations (the feedback's impulse response
+// is 7-periodic); the start state of chunk l is the XOR over j < l of
+// A^(L (l-1-j)) e_j, e_j being chunk j's zero-state end state, with A^7 = I
+// because 1 + D^2 + D^3 is primitive.  The start states come from a
 // log-depth scan across the wave's lanes: with P(l) = XOR over j <= l of
 // A^(L (l-j)) e_j, the step with offset d sets P(l) ^= A^(L d) P(l - d), and
 // chunk l starts in P(l - 1).  The zero-input parity from a state is
 // 7-periodic too, so the true parity is one more XOR.  The parity bits are
 // ORed into the encoder's LDS bit array, and the work group writes all three
-// streams with coalesced stores (the block's LDS holds its input bits, one
-// per byte, and the two parity bit arrays, so 16 blocks fit a CU).
+// streams from the bit arrays with coalesced stores (3.3 KB of LDS per
+// block).
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -58,34 +61,6 @@ __device__ static inline uint32_t src_bit(const uint8_t *src, int64_t b)
     return (src[b >> 3] >> (7 - (b & 7))) & 1u;
 }
 
-// CRC (remainder of M(x) x^24 mod g) of bits c[0..n-1] held one per byte,
-// computed by the whole work group; result valid in every thread.  Each
-// thread's chunk remainder is moved to the end by r(x) x^m mod g from the
-// table T[m] = x^m mod g (m + 23 < kCrcTabN).
-__device__ static uint32_t block_crc(const uint8_t *c, int n, uint32_t poly, const uint32_t *T,
-                                     uint32_t *acc)
-{
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    if (tid == 0) *acc = 0;
-    __syncthreads();
-    const int chunk = (n + nthr - 1) / nthr;
-    const int b0 = tid * chunk, b1 = min(n, b0 + chunk);
-    if (b0 < b1) {
-        uint32_t r = 0;
-        for (int b = b0; b < b1; ++b) {
-            const uint32_t top = ((r >> 23) ^ c[b]) & 1u;
-            r = ((r << 1) & 0xFFFFFFu) ^ (top ? poly : 0u);
-        }
-        uint32_t o = 0;
-        const int m = n - b1;
-#pragma unroll
-        for (int i = 0; i < 24; ++i) o ^= ((r >> i) & 1u) ? T[m + i] : 0u;
-        if (o) atomicXor(acc, o);
-    }
-    __syncthreads();
-    return *acc;
-}
-
 // RSC state as 3 bits: bit 0 = a_{k-1}, bit 1 = a_{k-2}, bit 2 = a_{k-3}.
 // One step with input u: feedback a = u ^ a_{k-2} ^ a_{k-3}, parity
 // z = a ^ a_{k-1} ^ a_{k-3}.
@@ -107,8 +82,7 @@ __device__ static inline uint32_t rsc_zero_steps(uint32_t s, int p)
 
 constexpr int kEncThreads = 128;  // two waves: encoder 1 and encoder 2
 typedef unsigned __int128 u128;
-constexpr int kPzWords = kKmax / 32 + 2;  // parity bit array; one spare word for 8-bit reads
-constexpr int kCwWords = kKmax / 32 + 4;  // input bit array; spare words for 128-bit reads
+constexpr int kBitWords = kKmax / 32 + 4;  // bit arrays; spare words for 64- and 128-bit reads
 
 // One byte per bit of a 4-bit value: bit j of n becomes byte j.
 __device__ static inline uint32_t spread4(uint32_t n)
@@ -121,19 +95,19 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
                                                                    uint8_t *out,
                                                                    const uint32_t *crc_tab)
 {
-    __shared__ uint8_t c[kKmax];
     __shared__ uint8_t raw[kKmax / 8 + 2];
+    __shared__ uint32_t cw[kBitWords];     // input bit c_k: bit k % 32 of cw[k / 32]
+    __shared__ uint32_t pz[2][kBitWords];  // parity bit k of encoder w: bit k % 32 of pz[w][k / 32]
+    __shared__ uint32_t t4[16];            // CRC register after 4 zero bits from v x^20
     __shared__ uint8_t tl[2][6];
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
-    __shared__ uint32_t pz[2][kPzWords];  // parity bit k of encoder w: bit k % 32 of pz[w][k / 32]
-    __shared__ uint32_t cw[kCwWords];     // input bit k: bit k % 32 of cw[k / 32]
     const EncCb cb = cbs[blockIdx.x];
     const int K = cb.K, F = cb.F, L = cb.crc ? 24 : 0;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const uint32_t poly = cb.crc == 1 ? kPoly24A : kPoly24B;
     // input bits: the payload bytes that hold bits src_bit .. src_bit + n_in - 1
-    // are copied into LDS, then expanded to one bit per byte (c) and to a bit
-    // array (cw, one ballot per wave and trip)
+    // are copied into LDS
     const int n_in = K - F - L;
     const int64_t byte0 = cb.src_bit >> 3;
     const int bo = (int)(cb.src_bit & 7);
@@ -150,30 +124,62 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
             if (i0 + m * nthr < nbytes) raw[i0 + m * nthr] = v[m];
     }
     if (tid < 56) zt[tid >> 3][tid & 7] = (uint8_t)rsc_zero_steps((uint32_t)(tid & 7), tid >> 3);
-    for (int i = tid; i < 2 * kPzWords; i += nthr) pz[i / kPzWords][i % kPzWords] = 0u;
-    for (int i = tid; i < kCwWords; i += nthr) cw[i] = 0u;
+    if (tid < 16) {
+        uint32_t r = (uint32_t)tid << 20;
+        for (int i = 0; i < 4; ++i) r = ((r << 1) & 0xFFFFFFu) ^ (((r >> 23) & 1u) ? poly : 0u);
+        t4[tid] = r;
+    }
+    for (int i = tid; i < 2 * kBitWords; i += nthr) pz[i / kBitWords][i % kBitWords] = 0u;
+    if (tid == 0) acc = 0u;
     __syncthreads();
-    for (int kb = 0; kb < K; kb += nthr) {
-        const int k = kb + tid, b = bo + (k - F);
-        const uint32_t bit =
-            (k >= F && k < K - L) ? (uint32_t)((raw[b >> 3] >> (7 - (b & 7))) & 1u) : 0u;
-        if (k < K) c[k] = (uint8_t)bit;
-        const uint64_t m = __ballot(bit);
-        const int base = kb + (tid & ~63);  // the wave's first k, a multiple of 64
-        if ((tid & 63) == 0 && base < K) {
-            cw[base >> 5] = (uint32_t)m;
-            cw[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    // c as words: 0 for the F filler bits, then the payload, then 0 where the
+    // CRC goes (and past K).  Word j holds c_{32j} .. c_{32j+31}, whose payload
+    // bits start at q = bo + 32 j - F (negative inside the filler): five bytes
+    // from q / 8 hold them most significant bit first.
+    for (int j = tid; j < kBitWords; j += nthr) {
+        const int k = 32 * j, lo = max(F, k), hi = min(K - L, k + 32);
+        uint32_t v = 0;
+        if (lo < hi) {
+            const int q = bo + k - F, base = q >> 3, sh = q & 7;
+            uint64_t B = 0;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                const int bi = base + i;
+                B = (B << 8) | (uint64_t)((bi >= 0 && bi < nbytes) ? raw[bi] : (uint8_t)0);
+            }
+            v = __builtin_bitreverse32((uint32_t)(B >> (8 - sh)));  // bit i = payload bit q + i
+            const uint32_t mhi = hi - k == 32 ? 0xFFFFFFFFu : (1u << (hi - k)) - 1u;
+            v &= mhi & ~((1u << (lo - k)) - 1u);
         }
+        cw[j] = v;
     }
     __syncthreads();
     if (L) {
-        const uint32_t p = block_crc(c, K - L, cb.crc == 1 ? kPoly24A : kPoly24B,
-                                     crc_tab + (cb.crc == 1 ? 0 : kCrcTabN), &acc);
+        // CRC of c_0 .. c_{n-1}, n = K - 24 (the remainder of M(x) x^24 mod
+        // g): each thread takes 64 bits (a multiple of 4 bits, as is n), 4 bits
+        // per table step, and moves its remainder to the end by r(x) x^m mod g
+        // from the table T[m] = x^m mod g (m + 23 < kCrcTabN).
+        const int n = K - 24;
+        const int b0 = 64 * tid, b1 = min(n, b0 + 64);
+        if (b0 < b1) {
+            uint32_t r = 0;
+            for (int j = b0 >> 5; j < (b1 + 31) >> 5; ++j) {
+                const uint32_t x = __builtin_bitreverse32(cw[j]);  // c_{32j} in bit 31
+                const int nb = min(32, b1 - 32 * j) >> 2;
+                for (int i = 0; i < nb; ++i)
+                    r = ((r << 4) & 0xFFFFFFu) ^ t4[((r >> 20) ^ (x >> (28 - 4 * i))) & 15u];
+            }
+            const uint32_t *T = crc_tab + (cb.crc == 1 ? 0 : kCrcTabN);
+            const int m = n - b1;
+            uint32_t o = 0;
+#pragma unroll
+            for (int i = 0; i < 24; ++i) o ^= ((r >> i) & 1u) ? T[m + i] : 0u;
+            if (o) atomicXor(&acc, o);
+        }
+        __syncthreads();
         if (tid < 24) {
             const int k = K - 24 + tid;
-            const uint32_t bit = (p >> (23 - tid)) & 1u;
-            c[k] = (uint8_t)bit;
-            if (bit) atomicOr(&cw[k >> 5], 1u << (k & 31));
+            if ((acc >> (23 - tid)) & 1u) atomicOr(&cw[k >> 5], 1u << (k & 31));
         }
         __syncthreads();
     }
@@ -208,7 +214,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
                 uint32_t x = 0;
 #pragma unroll
                 for (int m = 0; m < 32; ++m) {
-                    x |= (uint32_t)c[pi] << m;
+                    x |= ((cw[pi >> 5] >> (pi & 31)) & 1u) << m;
                     pi = min(pi + g, pi + g - uK);  // both below K: one of the two is the sum mod K
                     g = min(g + dg, g + dg - uK);
                 }
@@ -289,28 +295,13 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         }
     }
     __syncthreads();
-    // the systematic stream's first K bytes: byte stores up to a 4-byte
-    // boundary of the destination, then whole words assembled from LDS,
-    // then the rest
-    {
-        uint8_t *o = d;
-        const int head = min(K, (int)((4u - ((uint32_t)(uintptr_t)o & 3u)) & 3u));
-        const int nw4 = (K - head) >> 2;
-        if (tid < head) o[tid] = c[tid];
-        for (int q = tid; q < nw4; q += nthr) {
-            const int k = head + 4 * q;
-            *(uint32_t *)(o + k) = (uint32_t)c[k] | ((uint32_t)c[k + 1] << 8) |
-                                   ((uint32_t)c[k + 2] << 16) | ((uint32_t)c[k + 3] << 24);
-        }
-        for (int k = head + 4 * nw4 + tid; k < K; k += nthr) o[k] = c[k];
-    }
-    // the parity streams' first K bytes from the bit arrays: byte stores up
-    // to an 8-byte boundary of the destination, then 8 bytes per store, then
-    // the rest
+    // the three streams' first K bytes from the bit arrays (the input bits,
+    // then each encoder's parity): byte stores up to an 8-byte boundary of the
+    // destination, then 8 bytes per store, then the rest
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        uint8_t *o = d + (e + 1) * N;
-        const uint32_t *pw = pz[e];
+    for (int st = 0; st < 3; ++st) {
+        uint8_t *o = d + st * N;
+        const uint32_t *pw = st == 0 ? cw : pz[st - 1];
         const int head = min(K, (int)((8u - ((uint32_t)(uintptr_t)o & 7u)) & 7u));
         const int n8 = (K - head) >> 3;
         if (tid < head) o[tid] = (uint8_t)((pw[tid >> 5] >> (tid & 31)) & 1u);
