@@ -275,6 +275,75 @@ def test_encoder_parity(dev):
         assert np.array_equal(got[mask], ref[mask]), tbs
 
 
+def _oracle_coded(pay, bits_off, K, F, crc):
+    L = 0 if crc == O.CRC_NONE else 24
+    bits = np.unpackbits(pay[bits_off:])[:K - F - L]
+    c = np.zeros(K, np.uint8)
+    c[F:K - L] = bits
+    if L:
+        p = O.crc24(c[:K - L], crc)
+        c[K - L:] = [(p >> (23 - j)) & 1 for j in range(24)]
+    ref = O.turbo_encode_cb(c).reshape(3, K + 4)
+    ref[:2, :F] = 0
+    return ref
+
+
+def test_encoder_unaligned_destinations(dev):
+    """Output blocks 1 to 7 bytes apart, so the three streams of a block start
+    at every address residue mod 8 (the kernel stores 8 bytes at a time after
+    a byte-wise head): every block equals the oracle and the gap bytes keep
+    their pattern."""
+    T, D, torch = dev
+    g = np.random.default_rng(9)
+    Ks = [40, 48, 56, 64, 72, 512, 1056, 2048, 3136, 6144, 6080, 4032]
+    crcs = (O.CRC24B, O.CRC24A, O.CRC_NONE)
+    cbs, offs, pays_off, o, b = [], [], [], 0, 0
+    for i, K in enumerate(Ks * 2):
+        crc = crcs[i % 3]
+        F = int(g.integers(0, 16)) if K >= 64 else 0
+        o += 1 + i % 7                      # gap of 1..7 bytes before the block
+        cbs.append((K, F, crc))
+        offs.append(o)
+        pays_off.append(b)
+        L = 0 if crc == O.CRC_NONE else 24
+        o += 3 * (K + 4)
+        b += (K - F - L + 7) // 8 + 3
+    d = (T.CbDesc * len(cbs))()
+    for i, (K, F, crc) in enumerate(cbs):
+        d[i].llr_off, d[i].bits_off, d[i].K, d[i].F, d[i].crc = offs[i], pays_off[i], K, F, crc
+    pay = g.integers(0, 256, b).astype(np.uint8)
+    coded = torch.full((o + 5,), 0xAA, dtype=torch.uint8, device="cuda")
+    say(f"[enc] unaligned destinations, {len(cbs)} blocks")
+    D.cb_encode_batch(d, torch.from_numpy(pay).cuda(), coded)
+    torch.cuda.synchronize()
+    got = coded.cpu().numpy()
+    written = np.zeros(got.size, bool)
+    for i, (K, F, crc) in enumerate(cbs):
+        g3 = got[offs[i]:offs[i] + 3 * (K + 4)].reshape(3, K + 4)
+        assert np.array_equal(g3, _oracle_coded(pay, pays_off[i], K, F, crc)), (i, K, offs[i] % 8)
+        written[offs[i]:offs[i] + 3 * (K + 4)] = True
+    assert (got[~written] == 0xAA).all()
+
+
+def test_encoder_full_batch_sampled(dev):
+    """The 4096 x K6144 CRC24B launch the encoder benchmark times: 48 sampled
+    blocks equal the oracle's encoder, and every output byte is a bit."""
+    T, D, torch = dev
+    n, K = 4096, 6144
+    g = np.random.default_rng(10)
+    td, n_llr, n_bytes = T.make_descs([(K, 0, T.CRC24B)] * n)
+    pay = g.integers(0, 256, n_bytes).astype(np.uint8)
+    coded = torch.full((n_llr,), 0xAA, dtype=torch.uint8, device="cuda")
+    say(f"[enc] full batch {n} x K{K}")
+    D.cb_encode_batch(td, torch.from_numpy(pay).cuda(), coded)
+    torch.cuda.synchronize()
+    got = coded.cpu().numpy()
+    assert got.max() <= 1
+    for i in g.choice(n, 48, replace=False):
+        g3 = got[td[i].llr_off:td[i].llr_off + 3 * (K + 4)].reshape(3, K + 4)
+        assert np.array_equal(g3, _oracle_coded(pay, td[i].bits_off, K, 0, O.CRC24B)), i
+
+
 # ------------------------------------------------------------------ full-size workload
 
 
