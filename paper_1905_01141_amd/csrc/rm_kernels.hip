@@ -87,8 +87,10 @@ __global__ void __launch_bounds__(kRmThreads) derate_kernel(const RmItem *items,
     }
 }
 
-// One work group per code block: the block's coded bits are staged in LDS,
-// then the transmission reads them in circular-buffer order.
+// One work group per code block: the block's coded bits are staged in LDS
+// (4-byte words, four loads in flight per thread), then the transmission
+// reads them in circular-buffer order, the table loads of eight values issued
+// before their LDS reads and stores.
 __global__ void __launch_bounds__(kRmThreads) rate_match_kernel(const RmItem *items,
                                                                 const uint8_t *coded, uint8_t *e,
                                                                 const uint16_t *tab)
@@ -103,7 +105,18 @@ __global__ void __launch_bounds__(kRmThreads) rate_match_kernel(const RmItem *it
     if ((((uintptr_t)d) & 3) == 0) {
         const uint32_t *gw = (const uint32_t *)d;
         uint32_t *sw = (uint32_t *)cbits;
-        for (int i = tid; i < n / 4; i += nthr) sw[i] = gw[i];
+        const int nq = n / 4;
+        for (int i0 = tid; i0 < nq; i0 += 4 * nthr) {
+            uint32_t v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int i = i0 + m * nthr;
+                v[m] = i < nq ? gw[i] : 0u;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (i0 + m * nthr < nq) sw[i0 + m * nthr] = v[m];
+        }
     } else {
         for (int i = tid; i < n; i += nthr) cbits[i] = d[i];
     }
@@ -111,16 +124,16 @@ __global__ void __launch_bounds__(kRmThreads) rate_match_kernel(const RmItem *it
     const int nv = it.n_valid;
     for (int64_t c0 = 0; c0 < it.E; c0 += nv) {
         const int len = (int)min((int64_t)nv, (int64_t)it.E - c0);
-        for (int i0 = tid; i0 < len; i0 += 4 * nthr) {
-            int d[4];
+        for (int i0 = tid; i0 < len; i0 += 8 * nthr) {
+            int d[8];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                int r = it.r0 + min(i0 + m * nthr, len - 1);
+            for (int m = 0; m < 8; ++m) {
+                int r = it.r0 + min(i0 + m * nthr, len - 1);  // r0 < nv and i < nv
                 if (r >= nv) r -= nv;
                 d[m] = t[r];
             }
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 8; ++m)
                 if (i0 + m * nthr < len) dst[c0 + i0 + m * nthr] = cbits[d[m]];
         }
     }
