@@ -26,8 +26,8 @@
 // chunk l starts in P(l - 1).  The zero-input parity from a state is
 // 7-periodic too, so the true parity is one more XOR.  The parity bits are
 // ORed into the encoder's LDS bit array, and the work group writes all three
-// streams from the bit arrays with coalesced stores (3.3 KB of LDS per
-// block).
+// streams from the bit arrays with coalesced stores, 8 bits to 8 bytes through
+// a 256-entry table (5.6 KB of LDS per block).
 #include <hip/hip_runtime.h>
 
 #include "tdec_internal.h"
@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
     __shared__ uint32_t cw[kBitWords];     // input bit c_k: bit k % 32 of cw[k / 32]
     __shared__ uint32_t pz[2][kBitWords];  // parity bit k of encoder w: bit k % 32 of pz[w][k / 32]
     __shared__ uint32_t t4[16];            // CRC register after 4 zero bits from v x^20
+    __shared__ uint2 sp8[256];             // byte j of sp8[v] = bit j of v
     __shared__ uint8_t tl[2][6];
     __shared__ uint32_t acc;
     __shared__ uint8_t zt[7][8];  // zt[q][s] = A^q s
@@ -130,6 +131,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         t4[tid] = r;
     }
     for (int i = tid; i < 2 * kBitWords; i += nthr) pz[i / kBitWords][i % kBitWords] = 0u;
+    for (int v = tid; v < 256; v += nthr) sp8[v] = make_uint2(spread4(v & 15u), spread4(v >> 4));
     if (tid == 0) acc = 0u;
     __syncthreads();
     // c as words: 0 for the F filler bits, then the payload, then 0 where the
@@ -308,8 +310,7 @@ __global__ void __launch_bounds__(kEncThreads) turbo_encode_kernel(const EncCb *
         for (int q = tid; q < n8; q += nthr) {
             const int k = head + 8 * q;
             const uint64_t v = ((uint64_t)pw[(k >> 5) + 1] << 32) | pw[k >> 5];
-            const uint32_t b = (uint32_t)(v >> (k & 31)) & 0xFFu;
-            *(uint2 *)(o + k) = make_uint2(spread4(b & 0xFu), spread4(b >> 4));
+            *(uint2 *)(o + k) = sp8[(uint32_t)(v >> (k & 31)) & 0xFFu];
         }
         for (int k = head + 8 * n8 + tid; k < K; k += nthr)
             o[k] = (uint8_t)((pw[k >> 5] >> (k & 31)) & 1u);
