@@ -53,6 +53,43 @@ def test_rate_match_equals_oracle(dev):
         assert np.array_equal(got[d.e_off:d.e_off + E], want), (K, F, rv, E)
 
 
+def test_unaligned_buffers_equal_oracle(dev):
+    """Blocks placed 1 to 3 elements apart, so that the coded bits are not
+    4-byte aligned and the soft buffers not 8-byte aligned for some of them:
+    the kernels' element-wise staging paths give the oracle's results too, and
+    nothing outside the blocks is written."""
+    T, D, torch = dev
+    g = wl.rng(405, 0)
+    descs, ne, _ = T.make_rm_descs(BLOCKS)
+    so = 0
+    for i, (K, F, rv, E) in enumerate(BLOCKS):
+        so += 1 + i % 3
+        descs[i].soft_off = so
+        so += 3 * (K + 4)
+    ns = so + 4
+    coded = np.full(ns, 1, np.uint8)
+    for d, (K, F, _, _) in zip(descs, BLOCKS):
+        coded[d.soft_off:d.soft_off + 3 * (K + 4)] = _coded(K, F, g)
+    say(f"[rm] unaligned offsets {[d.soft_off % 8 for d in descs]}")
+    de = torch.zeros(ne, dtype=torch.uint8, device="cuda")
+    D.rate_match_batch(descs, torch.from_numpy(coded).cuda(), de)
+    e = g.integers(-127, 128, ne).astype(np.int8)
+    soft = torch.full((ns,), 777, dtype=torch.int16, device="cuda")
+    D.derate_batch(descs, torch.from_numpy(e).cuda(), soft, combine=0)
+    D.derate_batch(descs, torch.from_numpy(e).cuda(), soft, combine=1)
+    torch.cuda.synchronize()
+    got_e, got_s = de.cpu().numpy(), soft.cpu().numpy()
+    inside = np.zeros(ns, bool)
+    for d, (K, F, rv, E) in zip(descs, BLOCKS):
+        sl = slice(d.soft_off, d.soft_off + 3 * (K + 4))
+        inside[sl] = True
+        assert np.array_equal(got_e[d.e_off:d.e_off + E], O.rate_match(coded[sl], K, F, E, rv)), K
+        ee = e[d.e_off:d.e_off + E].astype(np.int16)
+        want = O.derate_match(ee, K, F, rv, O.derate_match(ee, K, F, rv, None))
+        assert np.array_equal(got_s[sl], want), (K, d.soft_off % 4)
+    assert (got_s[~inside] == 777).all()
+
+
 @pytest.mark.parametrize("ebits", [8, 16])
 def test_soft_combining_equals_oracle(dev, ebits):
     T, D, torch = dev
