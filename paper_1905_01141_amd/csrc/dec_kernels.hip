@@ -654,8 +654,8 @@ __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, 
 // a few spills remain in the phase-1 loop heads).  UNEVEN: some item's last
 // window is shorter than the others, so window lengths are per lane; the
 // even instantiation keeps them uniform (scalar loop bounds).
-// Four consecutive int16 LLRs (8 bytes); the address is 8-byte aligned when
-// the block's offset is a multiple of 4 elements.
+// Four consecutive int16 LLRs (8 bytes); one 8-byte load when the address is
+// 8-byte aligned, else four 2-byte loads.
 __device__ __forceinline__ uint2 load4(const int16_t *p, bool aligned)
 {
     if (aligned) return *(const uint2 *)p;
@@ -776,7 +776,8 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                 const DecCb cb = a.cbs[it.cb0 + cs];
                 const int16_t *src = a.llr + cb.llr_off;
                 const int N = K + 4;
-                const bool aligned = (cb.llr_off & 3) == 0;
+                // every load address is src plus a multiple of 4 elements
+                const bool aligned = (((uintptr_t)src) & 7) == 0;
                 const uint32_t so = (uint32_t)(cs * it.lds_slot);
                 const uint32_t so2 = so | (so << 16);
                 if (R > 0) {

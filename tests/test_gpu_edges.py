@@ -123,6 +123,37 @@ def test_degenerate_llrs(dev, fill):
         assert gok.tolist() == [1, 1, 1]  # the all-zero word passes any CRC24
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_llr_buffer_at_any_alignment(dev, shift):
+    """The LLR buffer may start at any int16 address: a view 1 to 3 elements
+    into an allocation (2-, 4- and 2-byte aligned) decodes like the oracle,
+    through both the tiled restage (large blocks) and the direct one (40-bit
+    blocks, many per item)."""
+    T, D, torch = dev
+    cbs = [(6144, 0, O.CRC24B), (40, 8, O.CRC24A), (1056, 0, O.CRC24B), (40, 0, O.CRC_NONE),
+           (5824, 0, O.CRC24B), (512, 3, O.CRC24A)] * 2
+    llr, _, od, _, nb = cb_batch(cbs, "16qam", list(np.linspace(1.0, 5.0, len(cbs))), 504 + shift)
+    base = torch.zeros(llr.size + 8, dtype=torch.int16, device="cuda")
+    x = base[shift:shift + llr.size]
+    x.copy_(torch.from_numpy(llr))
+    say(f"[edge] LLR buffer shifted by {shift} elements (address mod 8 = {x.data_ptr() % 8})")
+    td = tdesc(T, od)
+    b = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    ok = torch.zeros(len(td), dtype=torch.uint8, device="cuda")
+    it = torch.zeros(len(td), dtype=torch.uint8, device="cuda")
+    D.cb_decode_batch(td, x, T.params(6, 1, 0, 1), b, ok, it)
+    torch.cuda.synchronize()
+    nws = [D.pick_windows(o.K) for o in od]
+    for i, o in enumerate(od):
+        L = 0 if o.crc == O.CRC_NONE else 24
+        r = O.cb_decode(llr[o.llr_off:o.llr_off + 3 * (o.K + 4)], o.K, o.F, o.crc,
+                        O.params(6, 1, nws[i], 1))
+        n = (o.K - o.F - L + 7) // 8
+        assert ok[i].item() == r["ok"] and it[i].item() == r["iters"], i
+        assert np.array_equal(b.cpu().numpy()[o.bits_off:o.bits_off + n],
+                              np.packbits(r["bits"][o.F:o.K - L])[:n]), i
+
+
 def test_invalid_requests_are_refused(dev):
     T, D, torch = dev
     x = torch.zeros(3 * (6144 + 4), dtype=torch.int16, device="cuda")
