@@ -188,6 +188,31 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
                             const int16_t *d_llr, const tdec_params *params, uint8_t *d_bits,
                             uint8_t *d_crc_ok, uint8_t *d_iters, void *stream);
 
+/* cb_decode_batch for callers that cannot allocate device memory while they
+ * run (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, same results, bit for bit.  The decode
+ * kernel's scratch (its claim counters and per-work-group restaged inputs,
+ * checkpoints and window boundaries) lives in a fixed device array of
+ * TDEC_FIXED_SCRATCH_BYTES that the library's code object carries on every
+ * GPU it runs on, held until the process ends; the call allocates nothing
+ * (no hipMalloc, no hipFree).  The context's tables and plan slots, made by
+ * tdec_create, are used as by cb_decode_batch.
+ *   The array bounds how many work groups run at once (fewer than
+ *   cb_decode_batch runs for large batches, so a large batch takes longer);
+ *   any batch is accepted as long as one work group's scratch fits: ENOMEM
+ *   when it does not (the planner keeps a work group's scratch under 256 KiB,
+ *   far below the array, so valid calls do not meet it).
+ *   Every call on a GPU shares that GPU's one array, whatever the context:
+ *   calls whose launches overlap in time on one GPU (other streams, other
+ *   threads, other contexts) race on it and give undefined results.  Each call
+ *   clears the counters it needs with a fill kernel on `stream` before its
+ *   decode kernel, so no state carries from one call to the next. */
+#define TDEC_FIXED_SCRATCH_BYTES ((size_t)64 << 20)
+tdec_status cb_decode_batch_fixed(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                                  const int16_t *d_llr, const tdec_params *params,
+                                  uint8_t *d_bits, uint8_t *d_crc_ok, uint8_t *d_iters,
+                                  void *stream);
+
 /* Result of one transport block (device memory, written by the decoder). */
 typedef struct {
     int32_t tb_ok;          /* 1 iff the reassembled payload passes CRC24A */

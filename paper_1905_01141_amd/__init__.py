@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libtdec.so")
 CRC_NONE, CRC24A, CRC24B = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EDEVICE", -5: "EBUSY"}
 EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tdec_create",
-           "tdec_destroy", "tdec_pick_windows", "cb_decode_batch", "tb_decode", "tb_decode_batch",
+           "tdec_destroy", "tdec_pick_windows", "cb_decode_batch", "cb_decode_batch_fixed",
+           "tb_decode", "tb_decode_batch",
            "cb_encode_batch", "tb_encode", "tdec_now_ns", "tdec_server_create",
            "tdec_server_create_model", "tdec_server_submit", "tdec_server_poll",
            "tdec_server_drain", "tdec_server_stats", "tdec_server_reset_stats",
@@ -143,6 +144,7 @@ def lib():
         L.tdec_destroy.restype = None
         L.tdec_pick_windows.argtypes = [vp, i32]
         L.cb_decode_batch.argtypes = [vp, i32, vp, vp, P(Params), vp, vp, vp, vp]
+        L.cb_decode_batch_fixed.argtypes = [vp, i32, vp, vp, P(Params), vp, vp, vp, vp]
         L.tb_decode.argtypes = [vp, vp, i32, P(Params), vp, vp, vp]
         L.tb_decode_batch.argtypes = [vp, i32, vp, vp, vp, vp, P(Params), vp, vp, vp]
         L.cb_encode_batch.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -367,6 +369,22 @@ class Decoder:
                lib().cb_decode_batch(self._h, n, ct.cast(descs, ct.c_void_p), _dptr(llr),
                                      ct.byref(p), _dptr(bits), _dptr(crc_ok), _dptr(iters),
                                      _stream(stream)))
+
+    def cb_decode_batch_fixed(self, descs, llr, p: Params, bits=None, crc_ok=None, iters=None,
+                              stream=None):
+        """cb_decode_batch through the allocation-free entry point (the decode
+        kernel's scratch is the library's fixed device array)."""
+        n = len(descs)
+        n_llr, n_bits = _desc_extent(descs)
+        _need(llr, "int16", n_llr, "llr")
+        if bits is not None:
+            _need(bits, "uint8", n_bits, "bits")
+        _need(crc_ok, "uint8", n, "crc_ok")
+        _need(iters, "uint8", n, "iters")
+        _check("cb_decode_batch_fixed",
+               lib().cb_decode_batch_fixed(self._h, n, ct.cast(descs, ct.c_void_p), _dptr(llr),
+                                           ct.byref(p), _dptr(bits), _dptr(crc_ok),
+                                           _dptr(iters), _stream(stream)))
 
     def tb_decode(self, llr, tbs: int, p: Params, bits, res, stream=None):
         """res: uint8 CUDA tensor of TB_RESULT_BYTES bytes."""

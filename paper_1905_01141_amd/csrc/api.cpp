@@ -198,9 +198,11 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
 }
 
 // Build the decode plan (items + code block list) from a request.
+// scratch_cap: bytes of per-work-group scratch the launch may use (the
+// context's workspace, or the fixed scratch of the allocation-free entry).
 tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot &ps,
                               std::vector<char> &blob, const std::vector<TbItem> *tbs,
-                              hipStream_t st, bool exact, bool mi)
+                              hipStream_t st, bool exact, bool mi, size_t scratch_cap)
 {
     // group by (K, nw), biggest blocks first, request order within a group:
     // a counting sort over the size table (a size has one window count per
@@ -307,7 +309,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     }
     int grid = std::min<int64_t>((int64_t)items.size(), (int64_t)occ * ctx->num_cus);
     if (ctx->grid_cap > 0) grid = std::min(grid, ctx->grid_cap);
-    const int64_t fit = (int64_t)(ctx->scratch_bytes / (size_t)stride);
+    const int64_t fit = (int64_t)(scratch_cap / (size_t)stride);
     if (fit < 1) return TDEC_ENOMEM;
     grid = (int)std::min<int64_t>(grid, fit);
     grid = std::max(grid, 1);
@@ -369,9 +371,11 @@ tdec_status upload(tdec_ctx *ctx, PlanSlot *ps, const std::string &key, const st
     return TDEC_OK;
 }
 
+// fixed: the fixed scratch of the allocation-free entry (counters, then
+// per-work-group scratch) instead of the context's workspace.
 tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
                         const tdec_params *p, uint8_t *d_bits, uint8_t *d_ok, uint8_t *d_it,
-                        bool hard, hipStream_t st)
+                        bool hard, hipStream_t st, char *fixed = nullptr)
 {
     DecArgs a;
     a.items = (const DecItem *)(ps->d_buf + ps->off_items);
@@ -383,9 +387,9 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.iters = d_it;
     a.hard = hard ? ctx->d_hard : nullptr;
     a.crc_tab = ctx->d_crc_tab;
-    a.scratch = ctx->d_scratch;
+    a.scratch = fixed ? fixed + kCtrBytes : ctx->d_scratch;
     a.scratch_stride = ps->stride;
-    a.counter = ctx->d_counter;
+    a.counter = fixed ? (uint32_t *)fixed : ctx->d_counter;
     a.qtab = ctx->d_qtab;
     a.mi_tab = ctx->d_crc_tab + kCrcTabWords;
     a.max_iters = p->max_iters;
@@ -395,6 +399,9 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.state_slots = ps->state_slots;
     // the plan's scratch and LDS layouts
     if ((p->win_init == 2) != ps->exact || ((p->early_stop & 2) != 0) != ps->mi) return TDEC_EINVAL;
+    // the fixed counters start every call at zero (another call may have
+    // left them set if it overlapped this one, which the header forbids)
+    if (fixed && launch_zero_words((uint32_t *)fixed, kCtrBytes / 4, st)) return TDEC_EDEVICE;
     if (launch_decode(a, ps->uneven, ps->exact, ps->mi, ps->grid, ps->wg, ps->lds, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
@@ -558,7 +565,7 @@ tdec_status graph_capture(tdec_ctx *ctx, std::vector<CbReq> &reqs,
     std::vector<char> blob;
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TDEC_EDEVICE;
-    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs, exact, mi);
+    tdec_status s = build_decode_plan(ctx, reqs, ps, blob, tbl, cs, exact, mi, ctx->scratch_bytes);
     tdec_graph *g = nullptr;
     if (s == TDEC_OK) {
         g = new tdec_graph();
@@ -652,6 +659,8 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TDEC_EDEVICE;
     if (hipSetDevice(device) != hipSuccess) return TDEC_EDEVICE;
+    // the device address of the fixed scratch (allocation-free entry point)
+    if (static_scratch_init(device) != 0) return TDEC_EDEVICE;
     tdec_ctx *c = new tdec_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)1 << 30);
@@ -770,13 +779,46 @@ tdec_status cb_decode_batch(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *des
     if (s != TDEC_OK) return s;
     std::vector<char> blob;
     s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st, params->win_init == 2,
-                          (params->early_stop & 2) != 0);
+                          (params->early_stop & 2) != 0, ctx->scratch_bytes);
     if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
     if (s != TDEC_OK) {
         ps->key.clear();
         return s;
     }
     return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st);
+}
+
+tdec_status cb_decode_batch_fixed(tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *desc,
+                                  const int16_t *d_llr, const tdec_params *params,
+                                  uint8_t *d_bits, uint8_t *d_crc_ok, uint8_t *d_iters,
+                                  void *stream)
+{
+    if (!ctx || n_cb < 0 || !params_ok(params)) return TDEC_EINVAL;
+    if (n_cb == 0) return TDEC_OK;
+    if (!desc || !d_llr || !d_crc_ok || !d_iters) return TDEC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    char *fixed = static_scratch_ptr(ctx->device);
+    if (!fixed) return TDEC_EDEVICE;
+    // plans of this entry differ from cb_decode_batch's in their grid (the
+    // fixed scratch holds fewer work groups), so their keys differ too
+    const std::string key = "F" + cb_key(n_cb, desc, params, d_bits != nullptr, ctx->tune_gen);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (hit) return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st, fixed);
+    std::vector<CbReq> reqs;
+    tdec_status s = make_cb_reqs(ctx, n_cb, desc, params, d_bits != nullptr, reqs);
+    if (s != TDEC_OK) return s;
+    std::vector<char> blob;
+    // ENOMEM when one work group's scratch exceeds the fixed array
+    s = build_decode_plan(ctx, reqs, *ps, blob, nullptr, st, params->win_init == 2,
+                          (params->early_stop & 2) != 0, kStaticScratchBytes - kCtrBytes);
+    if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
+    if (s != TDEC_OK) {
+        ps->key.clear();
+        return s;
+    }
+    return launch_plan(ctx, ps, d_llr, params, d_bits, d_crc_ok, d_iters, false, st, fixed);
 }
 
 tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
@@ -821,7 +863,7 @@ tdec_status tdec::tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32
         if (s != TDEC_OK) return s;
         std::vector<char> blob;
         s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st, params->win_init == 2,
-                              (params->early_stop & 2) != 0);
+                              (params->early_stop & 2) != 0, ctx->scratch_bytes);
         if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
         if (s != TDEC_OK) {
             ps->key.clear();

@@ -47,6 +47,8 @@
 // int16, so every result equals the exact (unbounded) max-log-MAP.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tdec_internal.h"
 
 namespace tdec {
@@ -1160,6 +1162,51 @@ int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, 
 {
     hipLaunchKernelGGL(decode_kernel(uneven, exact, mi), dim3(grid), dim3(wg_threads), lds_bytes,
                        (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free decode entry point: the claim
+// counters (kCtrBytes) and then the per-work-group scratch.  Each device that
+// loads the library holds one copy for the life of the process; its address
+// comes from hipGetSymbolAddress (host code never passes the symbol itself).
+
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;
+char *g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return -1;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_ptr[device]) return 0;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) return -1;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    g_static_ptr[device] = (char *)p;
+    return 0;
+}
+
+char *static_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    return g_static_ptr[device];
+}
+
+__global__ void __launch_bounds__(256) zero_words_kernel(uint32_t *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+int launch_zero_words(uint32_t *p, int n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, p, n);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

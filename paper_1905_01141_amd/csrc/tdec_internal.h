@@ -193,6 +193,17 @@ tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tb
 const void *decode_kernel_address(bool uneven, bool exact, bool mi);
 int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, int wg_threads,
                   int lds_bytes, void *stream);
+// Fixed scratch of the allocation-free decode entry point (a file-scope
+// device array of kStaticScratchBytes per device: kCtrBytes of claim counters,
+// then per-work-group scratch).  static_scratch_init, called with `device`
+// current, looks up and keeps that device's address (0 ok, -1 error);
+// static_scratch_ptr returns it (null before the init).
+constexpr size_t kStaticScratchBytes = TDEC_FIXED_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+int static_scratch_init(int device);
+char *static_scratch_ptr(int device);
+// Zero n words with a fill kernel (no memset node when the stream is captured).
+int launch_zero_words(uint32_t *p, int n, void *stream);
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
