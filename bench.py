@@ -99,44 +99,75 @@ def build_inputs(T, D, torch):
     return descs, llr, pay_bits, n_bytes
 
 
+def host_cpu():
+    """What /proc/cpuinfo says about the host: the model name line as given
+    (virtual machines often shorten it), family / model / stepping, the
+    logical CPUs it lists and the CPUs this process may run on."""
+    info = {"model_name": "", "family": None, "model": None, "stepping": None,
+            "logical_cpus": 0, "affinity": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                k, _, v = ln.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    info["logical_cpus"] += 1
+                elif k == "model name" and not info["model_name"]:
+                    info["model_name"] = v
+                elif k == "cpu family" and info["family"] is None:
+                    info["family"] = int(v)
+                elif k == "model" and info["model"] is None:
+                    info["model"] = int(v)
+                elif k == "stepping" and info["stepping"] is None:
+                    info["stepping"] = int(v)
+    except (OSError, ValueError):
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
+
+
 def cpu_baseline(llr, sample_cbs: int, threads: int):
     """The plain C oracle (never tuned) on `sample_cbs` blocks of the same
-    workload, one block per task on a thread pool."""
+    workload, one block per task on a thread pool (the paper's code block
+    parallelism); returns the timing record and, per block, the oracle's
+    packed payload bytes, CRC flag and iteration count."""
     from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
     import oracle as O
     blk = 3 * (K + 4)
     p = O.params(ITERS, 0, N_WIN, 1)
 
     def one(i):
         r = O.cb_decode(llr[i * blk:(i + 1) * blk], K, 0, O.CRC24B, p)
-        return r["ok"]
+        return np.packbits(r["bits"][:PAYLOAD]), r["ok"], r["iters"]
 
     def timed(n, t):
         t0 = time.perf_counter()
         with ThreadPoolExecutor(max_workers=t) as ex:
-            oks = list(ex.map(one, range(n)))
-        return time.perf_counter() - t0, oks
+            out = list(ex.map(one, range(n)))
+        return time.perf_counter() - t0, out
 
     O.lib()
-    dt, oks = timed(sample_cbs, threads)
+    dt, out = timed(sample_cbs, threads)
     # also one thread and the paper's six dedicated cores, on 256 blocks each
     sweep = []
     for t in (1, 6):
         n = min(256, sample_cbs)
         d, _ = timed(n, t)
         sweep.append({"threads": t, "value": round(n * PAYLOAD / d / 1e9, 6), "blocks": n})
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": round(sample_cbs * PAYLOAD / dt / 1e9, 6), "unit": "Gbit/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{sample_cbs} of the {N_CB} code blocks, {ITERS} iterations, "
-                      f"{N_WIN} windows, one block per task; {dt:.2f} s wall, "
-                      f"{sum(oks)} CRC pass",
-            "by_threads": sweep, "cpu": model}
+    cpu = host_cpu()
+    rec = {"value": round(sample_cbs * PAYLOAD / dt / 1e9, 6), "unit": "Gbit/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{sample_cbs} of the {N_CB} code blocks, {ITERS} iterations, "
+                     f"{N_WIN} windows, one block per task; {dt:.2f} s wall, "
+                     f"{sum(o[1] for o in out)} CRC pass",
+           "by_threads": sweep, "cpu": cpu["model_name"], "cpu_info": cpu,
+           "threads_note": "a one-GPU box grants 16 host CPUs to its GPU; the pool uses "
+                           "min(16, CPUs this process may run on)"}
+    return rec, out
 
 
 def main():
@@ -213,9 +244,13 @@ def main():
     ops = OPS_PER_KBIT_ITER * N_CB * K * ITERS
     achieved = ops / launch_s / 1e12
 
+    # the timed run's outputs, kept for the comparison with the oracle
+    bits6 = bits.cpu().numpy().copy()
+    ok6 = ok.cpu().numpy().copy()
+    it6 = it.cpu().numpy().copy()
     # correctness of the timed output against the transmitted payload
-    got = np.unpackbits(bits.cpu().numpy())
-    okh = ok.cpu().numpy()
+    got = np.unpackbits(bits6)
+    okh = ok6
     errs = int(np.count_nonzero(got.reshape(N_CB, -1)[:, :PAYLOAD] !=
                                 pay_bits.reshape(N_CB, PAYLOAD)))
     log(f"[bench] 6-iteration run: {value:.3f} Gbit/s, {ms_step:.3f} ms/step, "
@@ -247,14 +282,29 @@ def main():
         log(f"[bench] copy probe: {n} bytes read + {n} bytes written")
 
     cpu = None
+    parity = None
     # the packed int16 VALU rate this device delivers with the decoder's ACS
     # instructions (independent chains, every CU), beside the published peak
     valu_meas = max(T.probe_valu_int16(0) for _ in range(3))  # the first run is the lowest
     log(f"[bench] measured packed int16 VALU rate {valu_meas:.2f} TOP/s")
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except (AttributeError, OSError):
+            avail = os.cpu_count() or 1
+        threads = max(1, min(16, avail))
         log(f"[bench] CPU oracle baseline on {threads} threads, {args.cpu_sample} blocks")
-        cpu = cpu_baseline(llr_h, args.cpu_sample, threads)
+        cpu, ref = cpu_baseline(llr_h, args.cpu_sample, threads)
+        # every sampled block of the timed 6-iteration run against the oracle:
+        # payload bits, CRC flag and iteration count
+        per = PAYLOAD // 8
+        bad = [i for i, (ob, ook, oit) in enumerate(ref)
+               if not (np.array_equal(bits6[i * per:(i + 1) * per], ob) and ok6[i] == ook
+                       and it6[i] == oit)]
+        parity = {"blocks": len(ref), "mismatches": len(bad), "compared": "payload bits, CRC "
+                  "flag and iteration count of the timed 6-iteration run, block by block",
+                  "first_mismatches": bad[:8]}
+        log(f"[bench] parity against the oracle: {parity}")
 
     line = {
         "metric": "decoded info Gbit/s @6 iters",
@@ -281,10 +331,13 @@ def main():
                      "peak_measured": round(valu_meas, 2),
                      "frac_of_measured": round(achieved / valu_meas, 4)},
         "cpu_baseline": cpu,
+        "parity": parity,
         "as_configured": as_cfg,
         "kernel_ms": round(launch_s * 1e3, 4),
     }
     print(json.dumps(line), flush=True)
+    if parity and parity["mismatches"]:
+        sys.exit(3)
 
 
 if __name__ == "__main__":
