@@ -170,6 +170,42 @@ def cpu_baseline(llr, sample_cbs: int, threads: int):
     return rec, out
 
 
+def oracle_tb_reference(llr, lo, tbs, iters, early_stop, nws, threads):
+    """The cpu_baseline leg of the transport block workloads: the plain C
+    oracle decodes every transport block of a workload's pool once (one TB
+    per task on a thread pool) with the decoder's window counts per block.
+    Returns the timing record and, per TB, (payload bytes, tb_ok,
+    max_iters_used): the reference every served result is checked against."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as O
+    O.lib()
+    p = O.params(iters, early_stop, 0, 1)
+
+    def one(i):
+        t = int(tbs[i])
+        b, r = O.tb_decode_windows(llr[int(lo[i]):int(lo[i]) + O.tb_llr_count(t)], t, p, nws[i])
+        return b, int(r["tb_ok"]), int(r["max_iters_used"])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        out = list(ex.map(one, range(len(tbs))))
+    dt = time.perf_counter() - t0
+    rec = {"value": round(float(sum(int(t) for t in tbs)) / dt / 1e9, 6), "unit": "Gbit/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"the {len(tbs)} transport blocks of the pool once, {iters} iterations"
+                     f"{' with CRC stop' if early_stop else ' forced'}, the decoder's window "
+                     f"counts; {dt:.2f} s wall"}
+    return rec, out
+
+
+def oracle_threads():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +226,8 @@ def main():
     ap.add_argument("--min-w", type=int, default=0,
                     help="mixed/serving/cells: shortest window the autotuner may choose, in steps "
                          "(0: 32 for the mixed TTIs, 64 for serving and cells)")
+    ap.add_argument("--inflight", type=int, default=0,
+                    help="serving/cells: launches in flight at once (0: the server's default, 3)")
     ap.add_argument("--windows", default="tuned", choices=["tuned", "rule"],
                     help="serving/cells: autotuned window counts (latency objective) or the "
                          "library's built-in rule")
@@ -208,6 +246,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "uniform":
         import bench_workloads as BW
+        args.oracle_ref = oracle_tb_reference
+        args.oracle_threads = oracle_threads()
         line = getattr(BW, "run_" + args.workload)(args)
         print(json.dumps(line), flush=True)
         return
@@ -288,11 +328,7 @@ def main():
     valu_meas = max(T.probe_valu_int16(0) for _ in range(3))  # the first run is the lowest
     log(f"[bench] measured packed int16 VALU rate {valu_meas:.2f} TOP/s")
     if not args.no_cpu_baseline:
-        try:
-            avail = len(os.sched_getaffinity(0))
-        except (AttributeError, OSError):
-            avail = os.cpu_count() or 1
-        threads = max(1, min(16, avail))
+        threads = oracle_threads()
         log(f"[bench] CPU oracle baseline on {threads} threads, {args.cpu_sample} blocks")
         cpu, ref = cpu_baseline(llr_h, args.cpu_sample, threads)
         # every sampled block of the timed 6-iteration run against the oracle:

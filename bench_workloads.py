@@ -7,7 +7,6 @@ an LTE cell (100 PRB, FDD, 1 ms TTI).
 """
 from __future__ import annotations
 
-import gc
 import json
 import sys
 import time
@@ -200,7 +199,16 @@ def run_mixed(args):
         e1.record(st)
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
-    # check outputs against the transmitted payloads
+    # check outputs against the transmitted payloads and, every TB, against
+    # the oracle run with the same window counts
+    cpu = parity = None
+    ref = None
+    if getattr(args, "oracle_ref", None) is not None and not getattr(args, "no_cpu_baseline", False):
+        nws = [[D.pick_windows(K) for K, _ in T.cb_sizes(int(t))] for t in flat]
+        cpu, ref = args.oracle_ref(llr, lo, flat, 8, 1, nws, args.oracle_threads)
+        log(f"[mixed] oracle reference: {cpu}")
+        parity = {"tbs_checked": 0, "mismatches": 0, "compared": "payload bits, CRC24A flag and "
+                  "iteration count of every TB of every TTI (graph replay outputs)"}
     ok = errs_ok = 0
     iters = []
     for i, (bits, res, b_off, k0) in enumerate(outs):
@@ -208,6 +216,12 @@ def run_mixed(args):
         bb = bits.cpu().numpy()
         for j, t in enumerate(tbs[i]):
             iters.append(rr[j]["max_iters_used"])
+            if ref is not None:
+                ob, ook, oit = ref[k0 + j]
+                same = (rr[j]["tb_ok"] == ook and rr[j]["max_iters_used"] == oit and
+                        np.array_equal(bb[b_off[j]:b_off[j] + ob.size], ob))
+                parity["tbs_checked"] += 1
+                parity["mismatches"] += int(not same)
             if rr[j]["tb_ok"]:
                 ok += 1
                 got = np.unpackbits(bb[b_off[j]:b_off[j] + (t + 7) // 8])[:t]
@@ -270,6 +284,7 @@ def run_mixed(args):
                 "tb_per_tti_ms_p50": round(pct(lat_tb, 0.5), 4),
                 "tb_per_tti_ms_p99": round(pct(lat_tb, 0.99), 4),
                 "tb_results_equal": bool(same_tb)},
+            "parity": parity, "cpu_baseline": cpu,
             "autotune_s": round(tune_s, 2),
             "windows": {str(K): choice[K][0] for K in (40, 120, 504, 1024, 2048, 4096, 6144)
                         if K in choice},
@@ -514,61 +529,125 @@ def run_stop(args):
 
 
 # ----------------------------------------------------------------------------- c4 / c5
+class Checker:
+    """Checks served results against the oracle's decode of each pool entry:
+    every completed TB's CRC24A flag and iteration count, and the payload
+    bits of a seeded sample (`frac` of the TBs) plus every TB whose pool
+    entry fails in the oracle, up to `cap` TBs with bits per trial."""
+
+    def __init__(self, ref, pool_tbs, frac=0.05, cap=20000, seed=1905):
+        self.ok = np.array([r[1] for r in ref], np.int32)
+        self.iters = np.array([r[2] for r in ref], np.int32)
+        self.bits = [r[0] for r in ref]
+        self.fails = self.ok == 0
+        self.frac, self.cap, self.seed = frac, cap, seed
+        self.maxb = (int(np.max(pool_tbs)) + 7) // 8
+        self.buf = np.zeros((cap, self.maxb), np.uint8)
+
+    def start(self):
+        self.rng = np.random.default_rng(self.seed)
+        self.tag0 = None
+        self.idx = []       # pool indices of the measured submissions, in tag order
+        self.row_of = {}    # tag -> row of buf (TBs whose bits are kept)
+        self.results = []
+        self.rows = 0
+
+    def bits_ptrs(self, tags, idx):
+        """Payload buffer addresses for one submission (0: not kept)."""
+        if self.tag0 is None:
+            self.tag0 = int(tags[0]) if len(tags) else None
+        self.idx.append(np.asarray(idx, np.int64))
+        ptrs = np.zeros(len(idx), np.uint64)
+        take = (self.rng.random(len(idx)) < self.frac) | self.fails[idx]
+        base = self.buf.ctypes.data
+        for j in np.nonzero(take)[0]:
+            if self.rows >= self.cap:
+                break
+            self.row_of[int(tags[j])] = self.rows
+            ptrs[j] = base + self.rows * self.maxb
+            self.rows += 1
+        return ptrs
+
+    def finish(self):
+        r = np.concatenate(self.results) if self.results else None
+        pool_of = np.concatenate(self.idx) if self.idx else np.zeros(0, np.int64)
+        out = {"tbs_checked": 0, "tbs_bits_checked": 0, "flag_or_iteration_mismatches": 0,
+               "bit_mismatches": 0, "oracle_fail_tbs_served": 0, "first_mismatch_tags": []}
+        if r is None or self.tag0 is None:
+            return out
+        done = r[(r["status"] == 0) & (r["tag"] >= self.tag0) &
+                 (r["tag"] < self.tag0 + len(pool_of))]
+        pi = pool_of[done["tag"].astype(np.int64) - self.tag0]
+        bad = (done["tb_ok"] != self.ok[pi]) | (done["max_iters_used"] != self.iters[pi])
+        out["tbs_checked"] = int(len(done))
+        out["flag_or_iteration_mismatches"] = int(bad.sum())
+        out["oracle_fail_tbs_served"] = int(self.fails[pi].sum())
+        first = [int(t) for t in done["tag"][bad][:8]]
+        for t, i in zip(done["tag"], pi):
+            row = self.row_of.get(int(t))
+            if row is None:
+                continue
+            out["tbs_bits_checked"] += 1
+            ref = self.bits[int(i)]
+            if not np.array_equal(self.buf[row, :ref.size], ref):
+                out["bit_mismatches"] += 1
+                if len(first) < 8:
+                    first.append(int(t))
+        out["first_mismatch_tags"] = first
+        return out
+
+
 def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admission,
-          deadline_us=3000, budget=8 << 30, seed=0):
+          deadline_us=3000, budget=8 << 30, seed=0, checker=None, max_inflight=0):
     """Drive the serving loop with arrivals from lam_fn(rng) -> pool indices
-    per TTI; returns the stats of the measured TTIs."""
+    per TTI, submitted by the library's native load generator (one batch per
+    1 ms tick, no Python between ticks); returns the stats of the measured
+    TTIs (with `checker`, their results are checked against the oracle's)."""
     cfg = T.server_cfg(T.params(8, 1, 0, 1) if mode != "cells" else T.params(8, 0, 0, 1),
                        deadline_us=deadline_us, slot_budget_bytes=budget,
                        mode=T.SERVE_PER_TB if mode == "per-tb" else T.SERVE_CONTINUOUS,
-                       admission=admission)
-    srv = T.Server(D, cfg)
+                       admission=admission, max_inflight=max_inflight)
     rng = np.random.default_rng(seed)
-    tag = 0
-    late_max = 0  # how far behind its TTI clock this generator submitted
-    sub_t = []    # duration of each measured submit call (s)
-    # no collector pauses in the generator while it keeps the TTI clock
-    gc.collect()
-    gc.freeze()
-    gc.disable()
+    # the whole schedule, drawn before the clock starts
+    idx_w = [np.asarray(lam_fn(rng), np.int64) for _ in range(warm)]
+    idx_m = [np.asarray(lam_fn(rng), np.int64) for _ in range(n_ttis)]
+    cw = np.array([len(v) for v in idx_w], np.int32)
+    cm = np.array([len(v) for v in idx_m], np.int32)
+    iw = np.concatenate(idx_w) if idx_w else np.zeros(0, np.int64)
+    im = np.concatenate(idx_m) if idx_m else np.zeros(0, np.int64)
+    tag0 = int(iw.size)
+    bp = None
+    if checker is not None:
+        checker.start()
+        bp = checker.bits_ptrs(np.arange(tag0, tag0 + im.size), im)
+    srv = T.Server(D, cfg)
     try:
-        t_next = T.now_ns() + TTI_NS
-        for tti in range(warm + n_ttis):
-            if tti == warm:
-                srv.drain(10000)
-                while srv.discard() == 65536:
-                    pass
-                srv.reset_stats()
-                t_begin = T.now_ns()
-            idx = lam_fn(rng)
-            while T.now_ns() < t_next:
-                pass
-            if tti >= warm:
-                late_max = max(late_max, T.now_ns() - t_next)
-            if len(idx):
-                ts = time.perf_counter()
-                srv.submit(np.arange(tag, tag + len(idx)), pool_tbs[idx], pool_llr_ptr[idx],
-                           None, t_next, device=True)
-                if tti >= warm:
-                    sub_t.append(time.perf_counter() - ts)
-                tag += len(idx)
-            if tti % 16 == 0:
-                srv.discard()
-            t_next += TTI_NS
-        srv.drain(60000)
-        t_end = T.now_ns()
+        late_w, _ = srv.replay(cw, pool_tbs[iw], pool_llr_ptr[iw], None, TTI_NS, None, 0)
+        srv.drain(10000)
         while srv.discard() == 65536:
             pass
+        srv.reset_stats()
+        t_begin = T.now_ns() + TTI_NS
+        late_m, smax = srv.replay(cm, pool_tbs[im], pool_llr_ptr[im], bp, TTI_NS, t_begin, tag0)
+        srv.drain(60000)
+        t_end = T.now_ns()
+        while True:
+            if checker is not None:
+                a = srv.poll_array()
+                checker.results.append(a)
+                if len(a) < 65536:
+                    break
+            elif srv.discard() < 65536:
+                break
         s = srv.stats()
         s["launches"] = srv.launches()
     finally:
-        gc.enable()
-        gc.unfreeze()
         srv.close()
     s["wall_s"] = (t_end - t_begin) / 1e9
-    s["gen_late_max_ms"] = late_max / 1e6
-    s["submit_ms"] = [round(1e3 * float(np.mean(sub_t)), 3) if sub_t else 0.0,
-                      round(1e3 * float(np.max(sub_t)), 3) if sub_t else 0.0]
+    s["gen_late_max_ms"] = late_m / 1e6
+    s["submit_max_ms"] = round(smax / 1e6, 3)
+    if checker is not None:
+        s["parity"] = checker.finish()
     return s
 
 
@@ -589,6 +668,16 @@ def log_slowest(recs, tag, k=3):
                 f"{r['copy_ns'] / 1e3:.0f}), idle before "
                 f"{gap:.0f} us, oldest waited {r['oldest_wait_ns'] / 1e3:.0f} us, "
                 f"{r['n_tb']} TBs / {r['n_cb']} CBs")
+
+
+def parity_sum(rows):
+    """Totals of the rows' oracle checks (None when nothing was checked)."""
+    ps = [r["parity"] for r in rows if r.get("parity")]
+    if not ps:
+        return None
+    keys = ("tbs_checked", "tbs_bits_checked", "flag_or_iteration_mismatches", "bit_mismatches",
+            "oracle_fail_tbs_served")
+    return {k: int(sum(p[k] for p in ps)) for k in keys}
 
 
 GEN_LATE_MS = 1.0  # a trial whose load generator fell this far behind is repeated
@@ -626,7 +715,19 @@ def serving_pool(D, torch, n, mod, lo_db, hi_db, seed, fixed_tbs=None):
     h2d = 3 * llr.nbytes / (time.perf_counter() - t0) / 1e9
     log(f"[pool] {n} TBs, {llr.nbytes / 1e6:.1f} MB of LLRs; pinned host-to-device {h2d:.1f} GB/s")
     ptrs = (d.data_ptr() + 2 * lo).astype(np.uint64)
-    return d, np.array(tbs, np.int32), ptrs, pays, h2d
+    return d, np.array(tbs, np.int32), ptrs, pays, h2d, llr, lo
+
+
+def pool_checker(args, D, llr, lo, ptbs, iters, early_stop, tag):
+    """The oracle's decode of every pool entry (bench.py's oracle leg, with
+    the decoder's window counts) and a Checker over it; None when the bench
+    runs without the oracle."""
+    if getattr(args, "oracle_ref", None) is None or getattr(args, "no_cpu_baseline", False):
+        return None, None
+    nws = [[D.pick_windows(K) for K, _ in T.cb_sizes(int(t))] for t in ptbs]
+    rec, ref = args.oracle_ref(llr, lo, ptbs, iters, early_stop, nws, args.oracle_threads)
+    log(f"[{tag}] oracle reference of the pool: {rec}")
+    return rec, Checker(ref, ptbs)
 
 
 def min_w(args, default):
@@ -652,11 +753,12 @@ def tune_windows(D, args, Ks, iters, batch_bits=0, default_min_w=64):
 def run_serving(args):
     import torch
     D = T.Decoder(0, 2 << 30)
-    h, ptbs, ptrs, _, h2d = serving_pool(D, torch, 2048, "64qam", 12.0, 22.0, 0)
+    h, ptbs, ptrs, _, h2d, llr_h, lo_h = serving_pool(D, torch, 2048, "64qam", 12.0, 22.0, 0)
     # launches hold hundreds to thousands of TBs here, so windows shorter than
     # 64 steps cost more in throughput than they save in latency
     tune_windows(D, args, [k for t in set(ptbs.tolist()) for k, _ in T.cb_sizes(int(t))], 8,
                  default_min_w=64)
+    cpu, checker = pool_checker(args, D, llr_h, lo_h, ptbs, 8, 1, "serving")
     mean_tbs = float(np.mean(ptbs))
     lam1 = 40 * MAX_TB / mean_tbs  # TBs per TTI at rho = 1 (40 cells at full load)
     rows = []
@@ -664,7 +766,8 @@ def run_serving(args):
         lam = lam1 * rho
         s = serve_checked("serving", T, D, torch, ptrs, ptbs,
                           lambda r: r.integers(0, len(ptbs), r.poisson(lam)),
-                          args.ttis, 300, args.mode, T.ADMIT_BUDGET | T.ADMIT_DEADLINE)
+                          args.ttis, 300, args.mode, T.ADMIT_BUDGET | T.ADMIT_DEADLINE,
+                          checker=checker, max_inflight=args.inflight)
         row = {"rho": rho, "tb_per_tti": round(lam, 1),
                "offered_gbit_s": round(lam * mean_tbs / 1e6, 3),
                "served_gbit_s": round(s["payload_bits"] / s["wall_s"] / 1e9, 3),
@@ -679,7 +782,7 @@ def run_serving(args):
                                              round(s["mean_post_ns"] / 1e3, 1)],
                "gen_late_max_ms": round(s["gen_late_max_ms"], 3),
                "gen_stall_repeats": s["gen_stall_repeats"],
-               "submit_ms_mean_max": s["submit_ms"]}
+               "submit_max_ms": s["submit_max_ms"], "parity": s.get("parity")}
         log(f"[serving] {row}")
         rows.append(row)
     top = rows[-1]
@@ -691,8 +794,9 @@ def run_serving(args):
                                    "8 GB slot budget, pool of 2048 distinct TBs resident in "
                                    "device memory",
                        "mode": args.mode, "ttis": args.ttis, "windows": args.windows,
-                       "min_window_steps": min_w(args, 64),
+                       "min_window_steps": min_w(args, 64), "max_inflight": args.inflight,
                        "pool_h2d_gbit_s": round(8 * h2d, 1)},
+            "parity": parity_sum(rows), "cpu_baseline": cpu,
             "rows": rows}
 
 
@@ -729,13 +833,19 @@ def run_cells(args):
         else:
             lo_db = mid
     esn0 = hi_db
-    h, ptbs, ptrs, _, h2d = serving_pool(D, torch, 256, "256qam", esn0, esn0, 0, fixed_tbs=MAX_TB)
+    h, ptbs, ptrs, _, h2d, llr_h, lo_h = serving_pool(D, torch, 256, "256qam", esn0, esn0, 0,
+                                                      fixed_tbs=MAX_TB)
+    cpu, checker = pool_checker(args, D, llr_h, lo_h, ptbs, 8, 0, "cells")
 
     def trial(n_cells):
         s = serve_checked("cells", T, D, torch, ptrs, ptbs,
                           lambda r: r.integers(0, len(ptbs), 2 * n_cells), args.ttis, 200,
-                          "cells", T.ADMIT_BUDGET)
+                          "cells", T.ADMIT_BUDGET, checker=checker, max_inflight=args.inflight)
         okk = s["lat_p99_ns"] <= 3_000_000 and s["rej_budget"] == 0
+        okk = okk and (s.get("parity") is None or
+                       (s["parity"]["flag_or_iteration_mismatches"] == 0 and
+                        s["parity"]["bit_mismatches"] == 0))
+        log(f"[cells] {n_cells} cells: parity {s.get('parity')}")
         log(f"[cells] {n_cells} cells: p99 {s['lat_p99_ns'] / 1e6:.3f} ms, "
             f"busy {s['busy_ns'] / 1e9 / s['wall_s']:.2f}, batch {s['mean_batch_tbs']:.1f} TBs, "
             f"pre/coding/post {s['mean_pre_ns'] / 1e3:.0f}/{s['mean_coding_ns'] / 1e3:.0f}/"
@@ -773,7 +883,8 @@ def run_cells(args):
                                               round(s["mean_coding_ns"] / 1e3, 1),
                                               round(s["mean_post_ns"] / 1e3, 1)],
                 "gen_late_max_ms": round(s["gen_late_max_ms"], 3),
-                "gen_stall_repeats": s["gen_stall_repeats"]},
+                "gen_stall_repeats": s["gen_stall_repeats"], "parity": s.get("parity")},
+            "cpu_baseline": cpu, "max_inflight": args.inflight,
             "pool_h2d_gbit_s": round(8 * h2d, 1)}
 
 

@@ -5,34 +5,52 @@
  * "Thread-pool", Sec. IV-C "Queuing principles", Algorithms 1 and 2): every
  * TTI a batch of transport blocks arrives; the paper queues their code blocks
  * and lets free cores pick them up in FIFO order, each running a whole decode
- * without preemption.  Here a native worker thread takes everything that is
- * waiting and decodes it as one persistent launch (code block parallelism
- * inside the launch, as in the paper's finest granularity), then hands the
- * bits and flags back in host memory.  The paper's performance captor
- * (Sec. IV-D) becomes the per-TB latency record: arrival to results in host
- * memory, with p50/p99 and the count of deadline misses.
+ * without preemption.  Here a native dispatcher thread takes everything that
+ * is waiting and decodes it as one persistent launch (code block parallelism
+ * inside the launch, as in the paper's finest granularity), without waiting
+ * for the launches already running: up to max_inflight launches are in
+ * flight at once, each on a lane of its own (a decoder context with its own
+ * workspace, a stream, mapped result staging).  The next batch is taken and
+ * enqueued while the launch before it still runs (once that launch is
+ * predicted to end within a quarter of its length, at most 200 us), with no
+ * host round trip between the two on the device.  Behind a launch of at
+ * most 256 transport blocks, its work groups take the compute units as the
+ * finishing launch's work groups leave them (its persistent grid leaves
+ * free the few slots that the finishing launch's transport block assembly
+ * needs); behind a larger launch its decode kernel waits on the device for
+ * that launch's assembly.  A completer thread hands each launch's bits and
+ * flags back in host memory as soon as it finishes, in any order.  The paper's performance captor (Sec. IV-D) becomes the per-TB
+ * latency record: arrival to results in host memory, with p50/p99 and the
+ * count of deadline misses.
  *
  * Admission happens at submission:
  *   - budget: the TB's LLRs must fit in the server's device-resident slot
  *     arena (hbm budget); otherwise it is rejected (TDEC_SERVE_REJ_BUDGET);
  *   - deadline: with admission bit TDEC_ADMIT_DEADLINE set, a TB whose
- *     predicted completion (queue ahead of it plus its own decode, from a
- *     service-time model learned from past launches) lies beyond its arrival
- *     plus deadline_us is rejected (TDEC_SERVE_REJ_DEADLINE).  A TB that is
+ *     predicted completion (the work in flight and queued ahead of it plus
+ *     its own decode, from a service-time model learned from past launches)
+ *     lies beyond its arrival plus 0.9 deadline_us is rejected
+ *     (TDEC_SERVE_REJ_DEADLINE); the last tenth is a guard against the
+ *     prediction's error.  An idle server admits any block.  A TB that is
  *     admitted and still finishes late counts as a deadline miss.
  * Admitted TBs have their LLRs copied asynchronously into their slot on a
  * copy stream; the decode launch waits for those copies on the device.
  *
  * Threading: submit, poll and stats may be called from any host thread (the
- * server serialises them); the server's worker thread is the only user of
- * the decoder context it was given, which must not be used by anyone else
- * while the server exists.
+ * server serialises them); the server's threads are the only users of the
+ * decoder context it was given, which must not be used by anyone else while
+ * the server exists (lanes past the first get contexts the server creates
+ * with the same workspace budget and window choices, so tune the context's
+ * windows before creating the server).
  *
  * Modelled executor: tdec_server_create_model runs the same queueing,
- * admission, batching and statistics with no device at all; a "launch"
- * sleeps for max(lat_ns, ns_per_kbit * K-kbits of the batch) and reports
- * every TB as decoded (tb_ok = 1).  It exists to test the scheduler and to
- * plan capacity on a host without a GPU.
+ * admission, batching and statistics with no device at all.  Its device runs
+ * the launches' work one after another at ns_per_kbit per 1000 code block
+ * bits, and no launch ends before lat_ns after it was dispatched: a launch
+ * dispatched at t ends at max(t + lat_ns, max(t, end of the work before it)
+ * + ns_per_kbit * K-kbits / 1000).  Every TB is reported decoded (tb_ok = 1).
+ * It exists to test the scheduler and to plan capacity on a host without a
+ * GPU.
  */
 #ifndef TDEC_SERVER_H
 #define TDEC_SERVER_H
@@ -47,7 +65,7 @@ extern "C" {
 #endif
 
 enum {
-    TDEC_SERVE_CONTINUOUS = 0, /* decode everything waiting as one launch whenever the GPU is free */
+    TDEC_SERVE_CONTINUOUS = 0, /* decode everything waiting as one launch whenever a lane is free */
     TDEC_SERVE_PER_TB = 1      /* one launch per TB in arrival order (the plain form, for comparison) */
 };
 enum { TDEC_ADMIT_BUDGET = 1, TDEC_ADMIT_DEADLINE = 2 };
@@ -68,6 +86,9 @@ typedef struct {
     int64_t model_lat_ns;     /* service model prior: duration of a small launch */
     int64_t model_ns_per_kbit;/* service model prior: ns per 1000 code block bits */
     tdec_params params;       /* decoder parameters of every launch */
+    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2); the
+                                 per-TB mode always runs one at a time */
+    int32_t rsv;
 } tdec_server_cfg;
 
 typedef struct {
@@ -86,7 +107,8 @@ typedef struct {
     int64_t submitted, admitted, rej_budget, rej_deadline, rej_invalid;
     int64_t completed, tb_fail, deadline_miss, batches;
     int64_t payload_bits;      /* sum of tbs over completed TBs */
-    int64_t busy_ns;           /* sum of launch-to-results time over launches */
+    int64_t busy_ns;           /* time with at least one launch in flight (the union
+                                  of the launches' take-to-results intervals) */
     int64_t lat_p50_ns, lat_p99_ns, lat_p999_ns, lat_max_ns, lat_mean_ns; /* completed TBs */
     int64_t model_lat_ns, model_ns_per_kbit;  /* the service model as learned so far */
     int64_t slots_in_use_bytes, slots_peak_bytes;
@@ -98,16 +120,19 @@ typedef struct {
 } tdec_serve_stats;
 
 /* One launch of the serving loop, as the paper's performance captor
- * (Sec. IV-D) records a processed subframe: when the worker took the batch,
- * the three delays, and what the batch held. */
+ * (Sec. IV-D) records a processed subframe: when the dispatcher took the
+ * batch, the three delays, and what the batch held.  Records of launches in
+ * flight at the same time overlap in time. */
 typedef struct {
-    int64_t t_start_ns;     /* worker took the batch (tdec_now_ns clock) */
+    int64_t t_start_ns;     /* dispatcher took the batch (tdec_now_ns clock) */
     int64_t t_end_ns;       /* results in host memory */
     int64_t pre_ns, coding_ns, post_ns; /* as in tdec_serve_stats */
     int64_t copy_ns;        /* part of post_ns spent in the copies back to host memory */
     int64_t oldest_wait_ns; /* t_start_ns minus the arrival of the batch's oldest TB */
     int32_t n_tb, n_cb;
     int64_t cb_bits;        /* sum of K over the batch's code blocks */
+    int64_t copyout_ns;     /* host copy of the payload bits into the callers' buffers
+                               (part of t_end_ns - t_start_ns, after post_ns) */
 } tdec_launch_rec;
 
 typedef struct tdec_server tdec_server;
@@ -145,6 +170,22 @@ int32_t tdec_server_submit_dev(tdec_server *s, int32_t n, const uint64_t *tags,
                                const int32_t *tbs, const int16_t *const *d_llr,
                                uint8_t *const *h_bits, int64_t t_arrive_ns, int32_t *status);
 
+/* Load generator for measurements: submit a precomputed arrival schedule of
+ * device-resident transport blocks from the calling thread, one arrival
+ * batch per tick, with no interpreter or other host work between ticks.
+ * Tick k is at t_first_ns + k * period_ns (tdec_now_ns clock); the thread
+ * spins until each tick and submits counts[k] blocks stamped with the tick
+ * as their arrival time, through tdec_server_submit_dev.  tbs, d_llr and
+ * h_bits (may be NULL, and may hold NULL entries) have one entry per
+ * arrival, all ticks' arrivals in order; arrival i gets tag tag_base + i.
+ * late_max_ns (may be NULL): how far after its tick the latest batch went
+ * in; submit_max_ns (may be NULL): the longest submission call.  Returns
+ * after the last tick's submission (results are polled as usual). */
+tdec_status tdec_server_replay(tdec_server *s, int32_t n_ticks, int64_t t_first_ns,
+                               int64_t period_ns, const int32_t *counts, const int32_t *tbs,
+                               const int16_t *const *d_llr, uint8_t *const *h_bits,
+                               uint64_t tag_base, int64_t *late_max_ns, int64_t *submit_max_ns);
+
 /* Move up to `max` finished results (completion order) into out; waits up
  * to wait_us for the first one when none is ready.  Returns the count. */
 int32_t tdec_server_poll(tdec_server *s, tdec_server_result *out, int32_t max, int32_t wait_us);
@@ -163,7 +204,7 @@ void tdec_server_reset_stats(tdec_server *s);
  * tdec_server_reset_stats).  Returns the count, or a negative tdec_status. */
 int32_t tdec_server_launches(tdec_server *s, tdec_launch_rec *out, int32_t max);
 
-/* Drain, stop the worker and free the server's device memory. */
+/* Drain, stop the server's threads and free its device memory and contexts. */
 void tdec_server_destroy(tdec_server *s);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
            "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch",
            "tdec_server_launches", "tdec_probe_valu_int16", "tdec_probe_hbm",
-           "tdec_probe_launch")
+           "tdec_probe_launch", "tdec_server_replay")
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -61,7 +61,7 @@ class ServerCfg(ct.Structure):
     _fields_ = [("slot_budget_bytes", ct.c_size_t), ("deadline_us", ct.c_int32),
                 ("max_batch_cb", ct.c_int32), ("mode", ct.c_int32), ("admission", ct.c_int32),
                 ("model_lat_ns", ct.c_int64), ("model_ns_per_kbit", ct.c_int64),
-                ("params", Params)]
+                ("params", Params), ("max_inflight", ct.c_int32), ("rsv", ct.c_int32)]
 
 
 class ServeResult(ct.Structure):
@@ -87,7 +87,8 @@ class LaunchRec(ct.Structure):
     _fields_ = [(n, ct.c_int64) for n in (
         "t_start_ns", "t_end_ns", "pre_ns", "coding_ns", "post_ns", "copy_ns",
         "oldest_wait_ns")] + [
-        ("n_tb", ct.c_int32), ("n_cb", ct.c_int32), ("cb_bits", ct.c_int64)]
+        ("n_tb", ct.c_int32), ("n_cb", ct.c_int32), ("cb_bits", ct.c_int64),
+        ("copyout_ns", ct.c_int64)]
 
 
 class RmDesc(ct.Structure):
@@ -166,6 +167,7 @@ def lib():
         L.tdec_server_submit.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
         L.tdec_server_submit_dev.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
         L.tdec_server_poll.argtypes = [vp, vp, i32, i32]
+        L.tdec_server_replay.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp, ct.c_uint64, vp, vp]
         L.tdec_server_drain.argtypes = [vp, i32]
         L.tdec_server_stats.argtypes = [vp, P(ServeStats)]
         L.tdec_server_reset_stats.argtypes = [vp]
@@ -538,9 +540,9 @@ def now_ns() -> int:
 
 def server_cfg(params: Params, deadline_us=3000, slot_budget_bytes=0, max_batch_cb=0,
                mode=SERVE_CONTINUOUS, admission=ADMIT_BUDGET, model_lat_ns=0,
-               model_ns_per_kbit=0) -> ServerCfg:
+               model_ns_per_kbit=0, max_inflight=0) -> ServerCfg:
     return ServerCfg(slot_budget_bytes, deadline_us, max_batch_cb, mode, admission,
-                     model_lat_ns, model_ns_per_kbit, params)
+                     model_lat_ns, model_ns_per_kbit, params, max_inflight, 0)
 
 
 class Server:
@@ -590,6 +592,28 @@ class Server:
             raise TdecError("tdec_server_submit", k)
         return k, st
 
+    def replay(self, counts, tbs, llr_ptrs, bits_ptrs=None, period_ns=1_000_000,
+               t_first_ns=None, tag_base=0):
+        """Submit a precomputed schedule from a native loop (device LLRs):
+        counts[k] arrivals at tick k, tbs / llr_ptrs / bits_ptrs one entry
+        per arrival.  Returns (max lateness of a tick, longest submit) in ns."""
+        counts = np.ascontiguousarray(counts, np.int32)
+        tbs = np.ascontiguousarray(tbs, np.int32)
+        lp = np.ascontiguousarray(llr_ptrs, np.uint64)
+        n = int(counts.sum())
+        if tbs.size != n or lp.size != n:
+            raise ValueError("tbs and llr_ptrs need one entry per arrival")
+        bp = None if bits_ptrs is None else np.ascontiguousarray(bits_ptrs, np.uint64)
+        if bp is not None and bp.size != n:
+            raise ValueError("bits_ptrs needs one entry per arrival")
+        late, smax = ct.c_int64(), ct.c_int64()
+        t = now_ns() + period_ns if t_first_ns is None else int(t_first_ns)
+        _check("tdec_server_replay",
+               lib().tdec_server_replay(self._h, counts.size, t, int(period_ns), _np_ptr(counts),
+                                        _np_ptr(tbs), _np_ptr(lp), _np_ptr(bp), int(tag_base),
+                                        ct.byref(late), ct.byref(smax)))
+        return late.value, smax.value
+
     def poll(self, max_n=4096, wait_us=0) -> list[dict]:
         buf = (ServeResult * max_n)()
         k = lib().tdec_server_poll(self._h, ct.cast(buf, ct.c_void_p), max_n, int(wait_us))
@@ -608,6 +632,17 @@ class Server:
             self._rawbuf = (ServeResult * max_n)()
         return int(lib().tdec_server_poll(self._h, ct.cast(self._rawbuf, ct.c_void_p), max_n,
                                           int(wait_us)))
+
+    def poll_array(self, max_n=65536, wait_us=0) -> np.ndarray:
+        """Up to max_n finished results as a numpy structured array (fields of
+        tdec_server_result), without a Python object per result (for load
+        generators that keep a clock).  Buffers passed with `keep` stay
+        referenced, as with discard()."""
+        if getattr(self, "_rawbuf", None) is None or len(self._rawbuf) < max_n:
+            self._rawbuf = (ServeResult * max_n)()
+        k = int(lib().tdec_server_poll(self._h, ct.cast(self._rawbuf, ct.c_void_p), max_n,
+                                       int(wait_us)))
+        return np.ctypeslib.as_array(self._rawbuf)[:k].copy()
 
     def launches(self, max_n=4096) -> list[dict]:
         """Records of the most recent launches, oldest first (the server

@@ -38,6 +38,7 @@ struct PlanSlot {
     uint64_t last_use = 0;
     // decoded plan
     int n_items = 0, grid = 0, wg = 0, lds = 0;
+    int resident = 0;   // work groups the device holds at once (occupancy x CUs)
     int64_t stride = 0;
     int n_cb = 0, n_tb = 0;
     int asm_words = 0;  // largest (B + 31) / 32 of the plan's transport blocks
@@ -88,6 +89,8 @@ struct tdec_ctx {
     std::map<int64_t, RmTab> rm_tabs;
     int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
+    int launch_reserve = 0;      // resident slots a launch leaves free (launch lanes)
+    bool small_asm = false;      // transport block assembly in kAsmGrid small work groups
 };
 
 namespace {
@@ -331,6 +334,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
     ps.asm_words = 0;
     for (size_t t = 0; t < ntb; ++t) ps.asm_words = std::max(ps.asm_words, ((*tbs)[t].B + 31) / 32);
     ps.grid = grid;
+    ps.resident = (int)std::min<int64_t>((int64_t)occ * ctx->num_cus, 1 << 30);
     ps.wg = wg;
     ps.lds = lds;
     ps.state_slots = max_n;
@@ -402,7 +406,9 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     // the fixed counters start every call at zero (another call may have
     // left them set if it overlapped this one, which the header forbids)
     if (fixed && launch_zero_words((uint32_t *)fixed, kCtrBytes / 4, st)) return TDEC_EDEVICE;
-    if (launch_decode(a, ps->uneven, ps->exact, ps->mi, ps->grid, ps->wg, ps->lds, st))
+    int grid = ps->grid;
+    if (ctx->launch_reserve > 0) grid = std::max(1, std::min(grid, ps->resident - ctx->launch_reserve));
+    if (launch_decode(a, ps->uneven, ps->exact, ps->mi, grid, ps->wg, ps->lds, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }
@@ -529,7 +535,8 @@ tdec_status launch_tb_plan(tdec_ctx *ctx, PlanSlot *ps, char *d_plan, const int1
     if (s != TDEC_OK) return s;
     if (ev_mid && hipEventRecord(ev_mid, st) != hipSuccess) return TDEC_EDEVICE;
     if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ps->asm_words,
-                           ctx->d_hard, ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res, st))
+                           ctx->d_hard, ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res,
+                           ctx->small_asm, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }
@@ -752,6 +759,30 @@ void tdec_destroy(tdec_ctx *c)
     }
     delete c;
 }
+
+}  // extern "C"
+
+void tdec::ctx_set_launch_reserve(tdec_ctx *ctx, int n, bool small_asm)
+{
+    if (!ctx) return;
+    ctx->launch_reserve = std::max(0, n);
+    ctx->small_asm = small_asm;
+}
+
+tdec_status tdec::ctx_clone(const tdec_ctx *src, tdec_ctx **out)
+{
+    if (!src || !out) return TDEC_EINVAL;
+    tdec_status s = tdec_create(src->device, src->budget, out);
+    if (s != TDEC_OK) return s;
+    tdec_ctx *c = *out;
+    c->lds_budget = src->lds_budget;
+    c->grid_cap = src->grid_cap;
+    for (int i = 0; i < kNumK; ++i) c->tuned_nw[i] = src->tuned_nw[i];
+    ++c->tune_gen;
+    return TDEC_OK;
+}
+
+extern "C" {
 
 int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K)
 {

@@ -1242,17 +1242,20 @@ __device__ __forceinline__ uint32_t take_bits(const uint32_t *h, int pos, int n)
     return n >= 32 ? x : (x & ~(0xFFFFFFFFu >> n));
 }
 
-// One work group per transport block.  The B = tbs + 24 reassembled bits
-// (every block's bits F..K-L-1, in block order) are gathered into LDS words;
-// the CRC24A remainder of that message, zero-padded to whole words, is the
-// XOR of each thread's word-chunk remainder times x^(32 * words after the
-// chunk) (table X32).  Padding multiplies the remainder by a power of x,
-// which is invertible modulo the generator (its constant term is 1), so the
-// padded remainder is zero exactly when the message's is.
-__global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, const uint32_t *hard,
-                                                          const uint8_t *crc_ok,
-                                                          const uint8_t *iters, uint8_t *bits,
-                                                          TbRes *res, const uint32_t *x32)
+
+// The B = tbs + 24 reassembled bits of a transport block (every block's bits
+// F..K-L-1, in block order) are gathered into LDS words; the CRC24A
+// remainder of that message, zero-padded to whole words, is the XOR of each
+// thread's word-chunk remainder times x^(32 * words after the chunk) (table
+// X32).  Padding multiplies the remainder by a power of x, which is
+// invertible modulo the generator (its constant term is 1), so the padded
+// remainder is zero exactly when the message's is.
+__global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, int n_tb,
+                                                                  const uint32_t *hard,
+                                                                  const uint8_t *crc_ok,
+                                                                  const uint8_t *iters,
+                                                                  uint8_t *bits, TbRes *res,
+                                                                  const uint32_t *x32)
 {
     extern __shared__ uint32_t msg[];
     __shared__ int64_t s_hoff[64];   // hard word offset of each block
@@ -1260,106 +1263,144 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, c
     __shared__ int32_t s_F[64];
     __shared__ uint32_t s_t8[256];   // byte table of CRC24A
     __shared__ uint32_t s_crc;
-    const TbItem tb = items[blockIdx.x];
     const int tid = threadIdx.x, nthr = blockDim.x;
-    if (tid == 0) {
-        int64_t h = tb.hard_off;
-        int32_t st = 0;
-        for (int r = 0; r < tb.C; ++r) {
-            const int32_t K = r < tb.Cminus ? tb.Kminus : tb.Kplus;
-            const int32_t F = r == 0 ? tb.F : 0;
-            s_hoff[r] = h;
-            s_start[r] = st;
-            s_F[r] = F;
-            h += hard_words(K);
-            st += K - F - tb.L;
-        }
-        s_start[tb.C] = st;  // = B
-        s_crc = 0;
-    }
-    {
-        // byte step of the MSB-first CRC: the remainder of t * x^24 after 8 shifts
-        uint32_t r = (uint32_t)tid << 16;
+    for (int e = tid; e < 256; e += nthr) {
+        // byte step of the MSB-first CRC: the remainder of e * x^24 after 8 shifts
+        uint32_t r = (uint32_t)e << 16;
         for (int k = 0; k < 8; ++k) r = ((r << 1) & 0xFFFFFFu) ^ ((r & 0x800000u) ? kPoly24A : 0u);
-        if (tid < 256) s_t8[tid] = r;
+        s_t8[e] = r;
     }
-    __syncthreads();
-    const int B = tb.B;
-    const int nwd = (B + 31) >> 5;
-    for (int w = tid; w < nwd; w += nthr) {
-        int b = w << 5;
-        // block holding message bit b: the last r with s_start[r] <= b
-        int lo = 0, hi = tb.C - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_start[mid] <= b) lo = mid;
-            else hi = mid - 1;
+    for (int t = blockIdx.x; t < n_tb; t += gridDim.x) {
+        const TbItem tb = items[t];
+        if (tid == 0) {
+            int64_t h = tb.hard_off;
+            int32_t st = 0;
+            for (int r = 0; r < tb.C; ++r) {
+                const int32_t K = r < tb.Cminus ? tb.Kminus : tb.Kplus;
+                const int32_t F = r == 0 ? tb.F : 0;
+                s_hoff[r] = h;
+                s_start[r] = st;
+                s_F[r] = F;
+                h += hard_words(K);
+                st += K - F - tb.L;
+            }
+            s_start[tb.C] = st;  // = B
+            s_crc = 0;
         }
-        int r = lo, got = 0;
-        uint32_t v = 0;
-        while (got < 32 && b < B) {
-            const int n = min(32 - got, s_start[r + 1] - b);
-            const uint32_t c = take_bits(hard + s_hoff[r], s_F[r] + (b - s_start[r]), n);
-            v |= c >> got;
-            got += n;
-            b += n;
-            ++r;
-        }
-        msg[w] = v;
-    }
-    __syncthreads();
-    // payload bytes (the first tbs bits)
-    if (tb.bits_off >= 0 && bits) {
-        const int nbytes = (tb.tbs + 7) >> 3;
-        for (int q = tid; q < nbytes; q += nthr) {
-            uint32_t v = (msg[q >> 2] >> (24 - 8 * (q & 3))) & 0xFFu;
-            const int keep = tb.tbs - 8 * q;  // payload bits in this byte
-            if (keep < 8) v &= 0xFFu << (8 - keep);
-            bits[tb.bits_off + q] = (uint8_t)v;
-        }
-    }
-    // CRC24A over the zero-padded message: word chunks per thread
-    const int cw = (nwd + nthr - 1) / nthr;
-    const int w0 = tid * cw, w1 = min(nwd, w0 + cw);
-    if (w0 < w1) {
-        uint32_t r = 0;
-        for (int w = w0; w < w1; ++w) {
-            const uint32_t v = msg[w];
+        __syncthreads();
+        const int B = tb.B;
+        const int nwd = (B + 31) >> 5;
+        // each thread builds a run of consecutive message words (the run it
+        // takes for the CRC below): a run inside one block reads its hard
+        // words in order, eight at a time with every load issued before the
+        // first is used; runs across a block boundary go word by word
+        const int cw0 = (nwd + nthr - 1) / nthr;
+        const int g0 = tid * cw0, g1 = min(nwd, g0 + cw0);
+        if (g0 < g1) {
+            const int b0 = g0 << 5;
+            int lo = 0, hi = tb.C - 1;  // block holding bit b0: the last r with s_start[r] <= b0
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[mid] <= b0) lo = mid;
+                else hi = mid - 1;
+            }
+            if (min(B, g1 << 5) <= s_start[lo + 1]) {
+                const int pos = s_F[lo] + (b0 - s_start[lo]);
+                const uint32_t *h = hard + s_hoff[lo] + (pos >> 5);
+                const int sh = pos & 31;
+                // the last word may read past the block's bits: the extra
+                // bits are dropped below, and the block's spare word keeps
+                // the read inside its hard-decision words
+                for (int w = g0; w < g1; w += 8) {
+                    uint32_t hw[9];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t byte = (v >> (24 - 8 * k)) & 0xFFu;
-                r = ((r << 8) & 0xFFFFFFu) ^ s_t8[((r >> 16) ^ byte) & 0xFFu];
+                    for (int k = 0; k < 9; ++k) hw[k] = (w + k <= g1) ? h[w - g0 + k] : 0u;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if (w + k >= g1) break;
+                        uint32_t v = sh ? (hw[k] << sh) | (hw[k + 1] >> (32 - sh)) : hw[k];
+                        const int left = B - ((w + k) << 5);  // message bits from this word on
+                        if (left < 32) v &= ~(0xFFFFFFFFu >> left);
+                        msg[w + k] = v;
+                    }
+                }
+            } else {
+                for (int w = g0; w < g1; ++w) {
+                    int b = w << 5;
+                    int r = lo;
+                    while (s_start[r + 1] <= b) ++r;
+                    int got = 0;
+                    uint32_t v = 0;
+                    while (got < 32 && b < B) {
+                        const int n = min(32 - got, s_start[r + 1] - b);
+                        const uint32_t c = take_bits(hard + s_hoff[r], s_F[r] + (b - s_start[r]), n);
+                        v |= c >> got;
+                        got += n;
+                        b += n;
+                        ++r;
+                    }
+                    msg[w] = v;
+                }
             }
         }
-        if (r) r = gf_mulmod(r, x32[nwd - w1], kPoly24A);
-        if (r) atomicXor(&s_crc, r);
-    }
-    __syncthreads();
-    if (tid < 64) {
-        TbRes &o = res[tb.res_idx];
-        const int r = tid;
-        o.cb_ok[r] = r < tb.C ? crc_ok[tb.cb_idx0 + r] : 0;
-        o.cb_iters[r] = r < tb.C ? iters[tb.cb_idx0 + r] : 0;
-        int mx = r < tb.C ? (int)iters[tb.cb_idx0 + r] : 0;
-        // wave-wide maximum (the 64 threads are one wave)
-        for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
-        if (tid == 0) {
-            o.tb_ok = s_crc == 0;
-            o.max_iters_used = mx;
-            o.C = tb.C;
-            o.rsv = 0;
+        __syncthreads();
+        // payload bytes (the first tbs bits)
+        if (tb.bits_off >= 0 && bits) {
+            const int nbytes = (tb.tbs + 7) >> 3;
+            for (int q = tid; q < nbytes; q += nthr) {
+                uint32_t v = (msg[q >> 2] >> (24 - 8 * (q & 3))) & 0xFFu;
+                const int keep = tb.tbs - 8 * q;  // payload bits in this byte
+                if (keep < 8) v &= 0xFFu << (8 - keep);
+                bits[tb.bits_off + q] = (uint8_t)v;
+            }
         }
+        // CRC24A over the zero-padded message: word chunks per thread
+        const int cw = (nwd + nthr - 1) / nthr;
+        const int w0 = tid * cw, w1 = min(nwd, w0 + cw);
+        if (w0 < w1) {
+            uint32_t r = 0;
+            for (int w = w0; w < w1; ++w) {
+                const uint32_t v = msg[w];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t byte = (v >> (24 - 8 * k)) & 0xFFu;
+                    r = ((r << 8) & 0xFFFFFFu) ^ s_t8[((r >> 16) ^ byte) & 0xFFu];
+                }
+            }
+            if (r) r = gf_mulmod(r, x32[nwd - w1], kPoly24A);
+            if (r) atomicXor(&s_crc, r);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            TbRes &o = res[tb.res_idx];
+            const int r = tid;
+            o.cb_ok[r] = r < tb.C ? crc_ok[tb.cb_idx0 + r] : 0;
+            o.cb_iters[r] = r < tb.C ? iters[tb.cb_idx0 + r] : 0;
+            int mx = r < tb.C ? (int)iters[tb.cb_idx0 + r] : 0;
+            // wave-wide maximum (the 64 threads are one wave)
+            for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+            if (tid == 0) {
+                o.tb_ok = s_crc == 0;
+                o.max_iters_used = mx;
+                o.C = tb.C;
+                o.rsv = 0;
+            }
+        }
+        __syncthreads();  // the shared state is rewritten for the next block
     }
 }
 
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
-                       uint8_t *bits, void *res, void *stream)
+                       uint8_t *bits, void *res, bool small_grid, void *stream)
 {
     if (n_tb <= 0) return 0;
-    hipLaunchKernelGGL(tb_assemble_kernel, dim3(n_tb), dim3(256), (size_t)max_words * 4,
-                       (hipStream_t)stream, items, hard, crc_ok, iters, bits, (TbRes *)res,
-                       crc_tab + 2 * kCrcTabN);
+    // one work group of 256 threads per transport block, or kAsmGrid work
+    // groups of two waves (each fits the slot of a decode work group)
+    const int grid = small_grid ? min(n_tb, kAsmGrid) : n_tb;
+    hipLaunchKernelGGL(tb_assemble_kernel, dim3(grid), dim3(small_grid ? 128 : 256),
+                       (size_t)max_words * 4, (hipStream_t)stream, items, n_tb, hard, crc_ok, iters,
+                       bits, (TbRes *)res, crc_tab + 2 * kCrcTabN);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -4,11 +4,15 @@
 // The paper runs channel decoding as jobs of a thread pool fed by a FIFO
 // queue (Sec. IV-B "Thread-pool", Algorithm 1 appends the code blocks of
 // every UE's transport block; Sec. IV-C, Algorithm 2 lets the next free core
-// take the next job and run it to completion).  On one GPU the natural unit
-// of dispatch is a launch, not a core: one worker thread drains the queue
-// into a single persistent decode launch whenever the previous one has
-// finished, so code block parallelism happens inside the launch and the
-// queue never holds more than one launch's worth of waiting time.
+// take the next job and run it to completion).  On one GPU the unit of
+// dispatch is a launch, not a core: a dispatcher thread drains the queue
+// into a persistent decode launch on whichever launch lane is free, without
+// waiting for the launches already in flight, and a completer thread
+// retires each launch the moment its events say it has finished.  Blocks
+// that arrive while launches run therefore go out at once on another lane,
+// and the hardware dispatcher starts their work groups as the earlier
+// launches' work groups leave the compute units: the device is shared by
+// every launch in flight, as the paper's cores are shared by its jobs.
 #include <hip/hip_runtime.h>
 #include <string.h>
 #include <time.h>
@@ -119,6 +123,37 @@ struct Pending {
 
 constexpr int kCopyEvents = 64;
 constexpr int64_t kLaunchRing = 4096;  // launch records kept
+constexpr int kMaxLanes = 8;
+// Result staging: pinned host memory mapped into the device (the assembly
+// kernel writes it over PCIe) and coarse-grained, so that the host reads it
+// through its caches; the writes are visible to the host once the launch's
+// completion event has fired (the kernel's end releases them at system scope).
+constexpr unsigned kStageFlags = hipHostMallocMapped | hipHostMallocNonCoherent;
+
+// One launch lane: a decoder context (workspace), a stream, events and
+// mapped result staging of its own, so that the launches of different lanes
+// can be in flight -- and run on the device -- at the same time.
+struct Lane {
+    tdec_ctx *ctx = nullptr;
+    bool own_ctx = false;  // lanes past the first use contexts the server made
+    hipStream_t st = nullptr;
+    hipEvent_t ev_s = nullptr, ev_m = nullptr;  // around the decode kernel (timing)
+    hipEvent_t ev_c = nullptr;                  // after the assembly kernel (timing)
+    hipEvent_t done_ev = nullptr;
+    // results land in mapped pinned host memory: the assembly kernel writes
+    // the payload bits and per-TB records straight over PCIe (device
+    // addresses hd_*), so no copy back follows the launch
+    uint8_t *h_bits = nullptr, *hd_bits = nullptr;
+    tdec_tb_result *h_res = nullptr, *hd_res = nullptr;
+    // the launch in flight (owned by the dispatcher until `launched`, then
+    // by the completer until the lane is free again)
+    bool busy = false, launched = false, ok = true;
+    bool small_asm = false;  // its transport blocks are assembled in kAsmGrid work groups
+    std::vector<Pending> b;
+    std::vector<int64_t> bo;  // byte offset of each TB's bits in h_bits
+    int64_t t0 = 0, t_enq = 0, kb = 0, cbs = 0, model_end = 0;
+    uint64_t seq = 0;  // dispatch order
+};
 
 }  // namespace
 
@@ -127,26 +162,21 @@ struct tdec_server {
     tdec_ctx *ctx = nullptr;
     bool model = false;
     int64_t sim_lat = 0, sim_npk = 0;
+    int64_t sim_busy_until = 0;  // modelled device: when its queued work ends
     int device = 0;
     // device resources
     int16_t *d_arena = nullptr;
-    hipStream_t copy_st = nullptr, dec_st = nullptr;
+    hipStream_t copy_st = nullptr;
     hipEvent_t copy_ev[kCopyEvents] = {};
-    hipEvent_t done_ev = nullptr;
-    hipEvent_t ev_s = nullptr, ev_m = nullptr;  // around the decode kernel (timing)
-    hipEvent_t ev_c = nullptr;                  // after the assembly kernel (timing)
     uint64_t copy_seq = 0;  // events recorded so far
-    // Results land in mapped pinned host memory: the assembly kernel writes the
-    // payload bits and per-TB records straight over PCIe (device addresses
-    // hd_*), so no copy back follows the launch.
-    uint8_t *h_bits_stage = nullptr, *hd_bits = nullptr;
     size_t bits_cap = 0;
-    tdec_tb_result *h_res = nullptr, *hd_res = nullptr;
     int32_t res_cap = 0;
+    int n_lanes = 1;
+    Lane lanes[kMaxLanes];
     std::mutex submit_mu;  // serialises submitters (held across their copies)
     // queue state (under mu)
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_retire;
     std::deque<Pending> queue;
     std::deque<tdec_server_result> done;
     Arena arena;
@@ -154,7 +184,13 @@ struct tdec_server {
     int64_t queued_kbits = 0;   // bits of code blocks waiting in the queue
     int64_t queued_dur_ns = 0;  // per-TB mode: predicted durations of the queue
     int64_t queued_cbs = 0;
-    int64_t run_end_pred = 0;   // predicted end of the running launch (0 = idle)
+    int64_t lanes_busy = 0;
+    int64_t gpu_end_pred = 0;   // predicted end of the launches in flight (0 = idle)
+    int64_t gpu_begin = 0;      // dispatch of the oldest launch in flight
+    uint64_t dispatch_seq = 0;
+    int last_lane = -1;         // lane of the most recent dispatch
+    int64_t last_retire = 0;    // completion time of the last retired launch
+    int64_t busy_until = 0;     // end of the union of launch intervals so far
     double m_lat = 0, m_npk = 0;  // service model: max(m_lat, m_npk * kbits)
     // statistics (under mu)
     tdec_serve_stats st{};
@@ -164,11 +200,23 @@ struct tdec_server {
     std::vector<tdec_launch_rec> ring;  // last kLaunchRing launches
     int64_t ring_n = 0;                 // launches recorded since the last reset
     bool stop = false;
-    std::thread worker;
+    std::thread dispatcher, completer;
 
     int64_t dur(int64_t kbits) const
     {
         return (int64_t)std::max(m_lat, m_npk * (double)kbits / 1000.0);
+    }
+    // how long before the predicted end of the work in flight the next
+    // launch may be dispatched: a quarter of that work, at most 200 us
+    int64_t lead() const
+    {
+        return std::min<int64_t>(200000, std::max<int64_t>(0, gpu_end_pred - gpu_begin) / 4);
+    }
+    int free_lane() const
+    {
+        for (int i = 0; i < n_lanes; ++i)
+            if (!lanes[i].busy) return i;
+        return -1;
     }
 };
 
@@ -189,170 +237,317 @@ bool seg_of(int32_t tbs, Segm *o)
     return true;
 }
 
-// Run one launch over `b` on the device; fills per-block results and the
-// launch's pre-processing (host: batch, plan, enqueue), coding (decode
-// kernel) and post-processing (assembly, copies back, copy-out) delays.
-void run_device(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
-                int64_t t0, int64_t lat[4])
+// Enqueue lane L's batch on its stream: wait for the batch's slot copies
+// and (`after`, may be null) for an earlier launch's assembly, then decode +
+// transport block assembly into the lane's mapped staging, events for the
+// delays and the completion.  Returns without waiting.
+void enqueue_device(tdec_server *s, Lane &L, hipEvent_t after)
 {
-    const int n = (int)b.size();
+    const int n = (int)L.b.size();
     std::vector<int32_t> tbs(n);
-    std::vector<int64_t> lo(n), bo(n);
+    std::vector<int64_t> lo(n);
+    L.bo.resize(n);
     uint64_t seq = 0;
     int64_t bytes = 0;
     for (int i = 0; i < n; ++i) {
-        tbs[i] = b[i].tbs;
-        lo[i] = b[i].slot_off / 2;
-        bo[i] = bytes;
-        bytes += (b[i].tbs + 7) / 8;
-        seq = std::max(seq, b[i].copy_seq);
+        tbs[i] = L.b[i].tbs;
+        lo[i] = L.b[i].slot_off / 2;
+        L.bo[i] = bytes;
+        bytes += (L.b[i].tbs + 7) / 8;
+        seq = std::max(seq, L.b[i].copy_seq);
     }
-    bool ok = hipStreamWaitEvent(s->dec_st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
-    ok = ok && tdec::tb_decode_batch_timed(s->ctx, n, tbs.data(), lo.data(), bo.data(), s->d_arena,
-                                           &s->cfg.params, s->hd_bits, s->hd_res, s->dec_st,
-                                           s->ev_s, s->ev_m) == TDEC_OK;
-    const int64_t t_enq = mono_ns();
-    ok = ok && hipEventRecord(s->ev_c, s->dec_st) == hipSuccess;
-    ok = ok && hipEventRecord(s->done_ev, s->dec_st) == hipSuccess;
-    ok = ok && hipEventSynchronize(s->done_ev) == hipSuccess;
+    bool ok = hipStreamWaitEvent(L.st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
+    if (after) ok = ok && hipStreamWaitEvent(L.st, after, 0) == hipSuccess;
+    ok = ok && tdec::tb_decode_batch_timed(L.ctx, n, tbs.data(), lo.data(), L.bo.data(),
+                                           s->d_arena, &s->cfg.params, L.hd_bits, L.hd_res, L.st,
+                                           L.ev_s, L.ev_m) == TDEC_OK;
+    L.t_enq = mono_ns();
+    ok = ok && hipEventRecord(L.ev_c, L.st) == hipSuccess;
+    ok = ok && hipEventRecord(L.done_ev, L.st) == hipSuccess;
+    L.ok = ok;
+}
+
+// Has lane L's launch finished?  (A launch whose enqueue failed has.)
+bool lane_finished(const tdec_server *s, const Lane &L, int64_t now)
+{
+    if (s->model) return now >= L.model_end;
+    if (!L.ok) return true;
+    const hipError_t e = hipEventQuery(L.done_ev);
+    return e != hipErrorNotReady;
+}
+
+// Results of lane L's finished launch into `res`; lat = pre-processing,
+// coding, post-processing and copy delays; t1 = when the results are in
+// host memory.
+void collect(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res, int64_t lat[5],
+             int64_t *t1)
+{
+    const int n = (int)L.b.size();
+    res.assign((size_t)n, tdec_server_result{});
+    if (s->model) {
+        for (auto &r : res) {
+            r.status = TDEC_SERVE_DONE;
+            r.tb_ok = 1;
+            r.max_iters_used = s->cfg.params.max_iters;
+        }
+        *t1 = mono_ns();
+        lat[0] = lat[2] = lat[3] = lat[4] = 0;
+        lat[1] = *t1 - L.t0;
+        return;
+    }
+    bool ok = L.ok && hipEventSynchronize(L.done_ev) == hipSuccess;
     float coding_ms = 0.f, post_ms = 0.f, copy_ms = 0.f;
     if (ok) {
-        (void)hipEventElapsedTime(&coding_ms, s->ev_s, s->ev_m);
-        (void)hipEventElapsedTime(&post_ms, s->ev_m, s->done_ev);
-        (void)hipEventElapsedTime(&copy_ms, s->ev_c, s->done_ev);
+        (void)hipEventElapsedTime(&coding_ms, L.ev_s, L.ev_m);
+        (void)hipEventElapsedTime(&post_ms, L.ev_m, L.done_ev);
+        (void)hipEventElapsedTime(&copy_ms, L.ev_c, L.done_ev);
     }
+    const int64_t tc = mono_ns();
     for (int i = 0; i < n; ++i) {
         tdec_server_result &r = res[i];
         if (!ok) {
             r.status = TDEC_SERVE_ERROR;
             continue;
         }
-        if (b[i].h_bits) memcpy(b[i].h_bits, s->h_bits_stage + bo[i], (size_t)(b[i].tbs + 7) / 8);
+        if (L.b[i].h_bits)
+            memcpy(L.b[i].h_bits, L.h_bits + L.bo[i], (size_t)(L.b[i].tbs + 7) / 8);
         r.status = TDEC_SERVE_DONE;
-        r.tb_ok = s->h_res[i].tb_ok;
-        r.max_iters_used = s->h_res[i].max_iters_used;
+        r.tb_ok = L.h_res[i].tb_ok;
+        r.max_iters_used = L.h_res[i].max_iters_used;
     }
-    lat[0] = t_enq - t0;
+    *t1 = mono_ns();
+    lat[4] = *t1 - tc;
+    lat[0] = L.t_enq - L.t0;
     lat[1] = (int64_t)(coding_ms * 1e6f);
     lat[2] = (int64_t)(post_ms * 1e6f);
     lat[3] = (int64_t)(copy_ms * 1e6f);
 }
 
-void run_model(tdec_server *s, std::vector<Pending> &b, std::vector<tdec_server_result> &res,
-               int64_t t0)
+// The dispatcher: whenever blocks wait and a lane is free, it forms a batch
+// and enqueues it on that lane, without waiting for any launch to finish --
+// blocks that arrive while launches run go out on the next free lane and
+// their work shares the device with the launches already there.
+void dispatcher_main(tdec_server *s)
 {
-    int64_t kb = 0;
-    for (auto &p : b) kb += p.kbits;
-    const int64_t d = std::max<int64_t>(s->sim_lat, (int64_t)((double)s->sim_npk * kb / 1000.0));
-    std::this_thread::sleep_for(std::chrono::nanoseconds(std::max<int64_t>(0, t0 + d - mono_ns())));
-    for (auto &r : res) {
-        r.status = TDEC_SERVE_DONE;
-        r.tb_ok = 1;
-        r.max_iters_used = s->cfg.params.max_iters;
+    if (!s->model) (void)hipSetDevice(s->device);
+    for (;;) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        // A waiting batch goes out on a free lane when nothing is in flight,
+        // or once the work in flight is predicted to end within the lead:
+        // its work groups then take the compute units that the finishing
+        // launches leave (the hand-over from one launch to the next is
+        // hidden) without sharing them with those launches for long, which
+        // would delay their older blocks.
+        const auto ready = [&] {
+            if (s->stop || s->queue.empty() || s->free_lane() < 0) return s->stop;
+            return s->lanes_busy == 0 || mono_ns() >= s->gpu_end_pred - s->lead();
+        };
+        while (!ready()) {
+            if (!s->queue.empty() && s->free_lane() >= 0 && s->lanes_busy > 0)
+                s->cv_work.wait_for(lk, std::chrono::nanoseconds(
+                                            std::max<int64_t>(s->gpu_end_pred - s->lead() - mono_ns(), 1000)));
+            else
+                s->cv_work.wait(lk);
+        }
+        if (s->queue.empty()) {
+            if (s->stop) break;
+            continue;
+        }
+        Lane &L = s->lanes[s->free_lane()];
+        L.b.clear();
+        int64_t kb = 0, cbs = 0;
+        // Take the oldest block, then more while the launch stays within
+        // max_batch_cb and is predicted to end before the oldest block's
+        // deadline (if even that block alone cannot make it, its deadline
+        // is lost anyway and the launch is filled for throughput).  The
+        // prediction queues the launch behind the work already in flight.
+        const int64_t now = mono_ns();
+        const int64_t start = std::max(now, s->gpu_end_pred);
+        const int64_t dl = s->queue.front().t_arrive + (int64_t)s->cfg.deadline_us * 1000;
+        const bool feasible = start + s->dur(s->queue.front().kbits) <= dl;
+        do {
+            const Pending &p = s->queue.front();
+            L.b.push_back(p);
+            kb += p.kbits;
+            cbs += p.C;
+            s->queue.pop_front();
+        } while (s->cfg.mode == TDEC_SERVE_CONTINUOUS && !s->queue.empty() &&
+                 cbs + s->queue.front().C <= s->cfg.max_batch_cb &&
+                 (!feasible || start + s->dur(kb + s->queue.front().kbits) <= dl));
+        s->queued_kbits -= kb;
+        s->queued_cbs -= cbs;
+        if (s->cfg.mode == TDEC_SERVE_PER_TB)
+            for (auto &p : L.b) s->queued_dur_ns -= p.pred_dur;
+        L.busy = true;
+        L.launched = false;
+        L.kb = kb;
+        L.cbs = cbs;
+        L.t0 = mono_ns();
+        L.seq = ++s->dispatch_seq;
+        if (s->lanes_busy == 0) s->gpu_begin = L.t0;
+        s->gpu_end_pred = std::max(L.t0, s->gpu_end_pred) + s->dur(kb);
+        // A launch with few transport blocks assembles them in kAsmGrid small
+        // work groups, and a launch dispatched while it runs leaves that many
+        // slots of its persistent grid free: its work groups then take the
+        // compute units as the running launch's leave, and the running
+        // launch's assembly never waits for them.  Behind a launch with many
+        // transport blocks (whose assembly needs the whole device to be
+        // quick) the next decode kernel waits on the device for that
+        // assembly to end instead: the host side of the next launch still
+        // overlaps, and no host round trip separates the two.
+        L.small_asm = s->n_lanes > 1 && (int)L.b.size() <= 4 * tdec::kAsmGrid;
+        int reserve = 0;
+        hipEvent_t after = nullptr;
+        if (s->lanes_busy > 0 && s->last_lane >= 0 && s->lanes[s->last_lane].busy) {
+            const Lane &P = s->lanes[s->last_lane];
+            if (P.small_asm) reserve = tdec::kAsmGrid;
+            else after = P.ev_c;
+        }
+        s->last_lane = (int)(&L - s->lanes);
+        ++s->lanes_busy;
+        lk.unlock();
+        if (s->model) {
+            // the modelled device: a launch takes at least sim_lat and the
+            // device completes sim_npk ns of work per kbit, launches in turn
+            s->sim_busy_until = std::max(L.t0 + s->sim_lat,
+                                         std::max(s->sim_busy_until, L.t0) +
+                                             (int64_t)((double)s->sim_npk * kb / 1000.0));
+            L.model_end = s->sim_busy_until;
+        } else {
+            tdec::ctx_set_launch_reserve(L.ctx, reserve, L.small_asm);
+            enqueue_device(s, L, after);
+        }
+        lk.lock();
+        L.launched = true;
+        lk.unlock();
+        s->cv_retire.notify_one();
     }
 }
 
-void worker_main(tdec_server *s)
+// Account one finished launch (under mu): results, slots, statistics,
+// launch record, service model.
+void retire_locked(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res,
+                   const int64_t lat3[5], int64_t t1)
+{
+    const std::vector<Pending> &b = L.b;
+    for (size_t i = 0; i < b.size(); ++i) {
+        tdec_server_result &r = res[i];
+        r.tag = b[i].tag;
+        r.tbs = b[i].tbs;
+        r.C = b[i].C;
+        r.batch_tbs = (int32_t)b.size();
+        r.t_arrive_ns = b[i].t_arrive;
+        r.t_done_ns = t1;
+        s->arena.release(b[i].slot_off, b[i].slot_bytes);
+        if (r.status == TDEC_SERVE_DONE) {
+            ++s->st.completed;
+            s->st.payload_bits += r.tbs;
+            if (!r.tb_ok) ++s->st.tb_fail;
+            const int64_t l = t1 - r.t_arrive_ns;
+            s->lat.push_back(l);
+            if (l > (int64_t)s->cfg.deadline_us * 1000) ++s->st.deadline_miss;
+        }
+        s->done.push_back(r);
+    }
+    s->inflight -= (int64_t)b.size();
+    ++s->st.batches;
+    s->batch_tbs_sum += (int64_t)b.size();
+    s->batch_cbs_sum += L.cbs;
+    // busy time: the union of the launches' [take, results] intervals
+    s->st.busy_ns += std::max<int64_t>(0, t1 - std::max(L.t0, s->busy_until));
+    s->busy_until = std::max(s->busy_until, t1);
+    s->pre_sum += lat3[0];
+    s->coding_sum += lat3[1];
+    s->post_sum += lat3[2];
+    tdec_launch_rec lr{};
+    lr.t_start_ns = L.t0;
+    lr.t_end_ns = t1;
+    lr.pre_ns = lat3[0];
+    lr.coding_ns = lat3[1];
+    lr.post_ns = lat3[2];
+    lr.copy_ns = lat3[3];
+    lr.copyout_ns = lat3[4];
+    int64_t oldest = L.t0;
+    for (const Pending &p : b) oldest = std::min(oldest, p.t_arrive);
+    lr.oldest_wait_ns = L.t0 - oldest;
+    lr.n_tb = (int32_t)b.size();
+    lr.n_cb = (int32_t)L.cbs;
+    lr.cb_bits = L.kb;
+    s->ring[(size_t)(s->ring_n++ % kLaunchRing)] = lr;
+    // service model: the launch's own share of the time, from when its
+    // oldest block arrived or the previous launch finished, whichever is
+    // later (the time before that belonged to the launches ahead of it; the
+    // hand-over from a finished launch to the next dispatch is counted, as
+    // the blocks wait through it).  One observation moves the model by at
+    // most a factor of 4 (a cold first launch must not stall admission for
+    // long).
+    const int64_t own = t1 - std::max(oldest, s->last_retire);
+    s->last_retire = std::max(s->last_retire, t1);
+    const double d = std::min((double)std::max<int64_t>(own, 1), 4.0 * (double)s->dur(L.kb));
+    if (s->m_npk * (double)L.kb / 1000.0 < s->m_lat)
+        s->m_lat = 0.8 * s->m_lat + 0.2 * d;
+    else
+        s->m_npk = 0.8 * s->m_npk + 0.2 * d * 1000.0 / (double)std::max<int64_t>(L.kb, 1);
+    L.busy = false;
+    L.launched = false;
+    if (--s->lanes_busy == 0) s->gpu_end_pred = 0;
+}
+
+// The completer: watches the lanes' launches, oldest first, and retires each
+// as soon as it finishes (in whatever order they finish).
+void completer_main(tdec_server *s)
 {
     if (!s->model) (void)hipSetDevice(s->device);
-    std::vector<Pending> b;
     std::vector<tdec_server_result> res;
+    std::vector<int> cand;
     for (;;) {
-        b.clear();
-        int64_t kb = 0, cbs = 0, t0 = 0;
+        cand.clear();
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-            if (s->queue.empty()) break;
-            // Take the oldest block, then more while the launch stays within
-            // max_batch_cb and is predicted to end before the oldest block's
-            // deadline (if even that block alone cannot make it, its deadline
-            // is lost anyway and the launch is filled for throughput).
+            s->cv_retire.wait(lk, [&] {
+                for (int i = 0; i < s->n_lanes; ++i)
+                    if (s->lanes[i].launched) return true;
+                return s->stop && s->lanes_busy == 0;
+            });
+            for (int i = 0; i < s->n_lanes; ++i)
+                if (s->lanes[i].launched) cand.push_back(i);
+            if (cand.empty()) break;  // stop, nothing in flight
+        }
+        std::sort(cand.begin(), cand.end(),
+                  [&](int a, int b) { return s->lanes[a].seq < s->lanes[b].seq; });
+        // wait for the first of them to finish: spin on the events (a launch
+        // lasts tens of microseconds to milliseconds); the modelled device
+        // sleeps until its earliest completion
+        int fin = -1;
+        for (int spins = 0; fin < 0; ++spins) {
             const int64_t now = mono_ns();
-            const int64_t dl = s->queue.front().t_arrive + (int64_t)s->cfg.deadline_us * 1000;
-            const bool feasible = now + s->dur(s->queue.front().kbits) <= dl;
-            do {
-                const Pending &p = s->queue.front();
-                b.push_back(p);
-                kb += p.kbits;
-                cbs += p.C;
-                s->queue.pop_front();
-            } while (s->cfg.mode == TDEC_SERVE_CONTINUOUS && !s->queue.empty() &&
-                     cbs + s->queue.front().C <= s->cfg.max_batch_cb &&
-                     (!feasible || now + s->dur(kb + s->queue.front().kbits) <= dl));
-            s->queued_kbits -= kb;
-            s->queued_cbs -= cbs;
-            if (s->cfg.mode == TDEC_SERVE_PER_TB)
-                for (auto &p : b) s->queued_dur_ns -= p.pred_dur;
-            t0 = mono_ns();
-            s->run_end_pred = t0 + s->dur(kb);
+            int64_t soonest = INT64_MAX;
+            for (int i : cand) {
+                if (lane_finished(s, s->lanes[i], now)) {
+                    fin = i;
+                    break;
+                }
+                soonest = std::min(soonest, s->lanes[i].model_end);
+            }
+            if (fin >= 0) break;
+            if (s->model) {
+                std::this_thread::sleep_for(std::chrono::nanoseconds(std::max<int64_t>(soonest - now, 1000)));
+            } else if (spins > 64) {
+                // a newer launch may have joined the lanes being watched
+                std::this_thread::yield();
+                if (spins % 256 == 0) break;
+            }
         }
-        res.assign(b.size(), tdec_server_result{});
-        int64_t lat3[4] = {0, 0, 0, 0};
-        if (s->model)
-            run_model(s, b, res, t0);
-        else
-            run_device(s, b, res, t0, lat3);
-        const int64_t t1 = mono_ns();
-        if (s->model) lat3[1] = t1 - t0;
-        for (size_t i = 0; i < b.size(); ++i) {
-            tdec_server_result &r = res[i];
-            r.tag = b[i].tag;
-            r.tbs = b[i].tbs;
-            r.C = b[i].C;
-            r.batch_tbs = (int32_t)b.size();
-            r.t_arrive_ns = b[i].t_arrive;
-            r.t_done_ns = t1;
-        }
+        if (fin < 0) continue;
+        Lane &L = s->lanes[fin];
+        int64_t lat3[5] = {0, 0, 0, 0, 0};
+        int64_t t1 = 0;
+        collect(s, L, res, lat3, &t1);
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            for (size_t i = 0; i < b.size(); ++i) {
-                const tdec_server_result &r = res[i];
-                s->arena.release(b[i].slot_off, b[i].slot_bytes);
-                if (r.status == TDEC_SERVE_DONE) {
-                    ++s->st.completed;
-                    s->st.payload_bits += r.tbs;
-                    if (!r.tb_ok) ++s->st.tb_fail;
-                    const int64_t l = t1 - r.t_arrive_ns;
-                    s->lat.push_back(l);
-                    if (l > (int64_t)s->cfg.deadline_us * 1000) ++s->st.deadline_miss;
-                }
-                s->done.push_back(r);
-            }
-            s->inflight -= (int64_t)b.size();
-            ++s->st.batches;
-            s->batch_tbs_sum += (int64_t)b.size();
-            s->batch_cbs_sum += cbs;
-            s->st.busy_ns += t1 - t0;
-            s->pre_sum += lat3[0];
-            s->coding_sum += lat3[1];
-            s->post_sum += lat3[2];
-            {
-                tdec_launch_rec lr{};
-                lr.t_start_ns = t0;
-                lr.t_end_ns = t1;
-                lr.pre_ns = lat3[0];
-                lr.coding_ns = lat3[1];
-                lr.post_ns = lat3[2];
-                lr.copy_ns = lat3[3];
-                int64_t oldest = t0;
-                for (const Pending &p : b) oldest = std::min(oldest, p.t_arrive);
-                lr.oldest_wait_ns = t0 - oldest;
-                lr.n_tb = (int32_t)b.size();
-                lr.n_cb = (int32_t)cbs;
-                lr.cb_bits = kb;
-                s->ring[(size_t)(s->ring_n++ % kLaunchRing)] = lr;
-            }
-            // service model update: the regime the prediction was in learns
-            // one observation moves the model by at most a factor of 4 (a
-            // cold first launch must not stall admission for long)
-            const double d = std::min((double)(t1 - t0), 4.0 * (double)s->dur(kb));
-            if (s->m_npk * (double)kb / 1000.0 < s->m_lat)
-                s->m_lat = 0.8 * s->m_lat + 0.2 * d;
-            else
-                s->m_npk = 0.8 * s->m_npk + 0.2 * d * 1000.0 / (double)std::max<int64_t>(kb, 1);
-            s->run_end_pred = 0;
+            retire_locked(s, L, res, lat3, t1);
         }
+        s->cv_work.notify_one();
         s->cv_done.notify_all();
     }
 }
@@ -361,17 +556,22 @@ void free_device(tdec_server *s)
 {
     if (s->model) return;
     (void)hipSetDevice(s->device);
+    for (int i = 0; i < kMaxLanes; ++i) {
+        Lane &L = s->lanes[i];
+        if (L.st) (void)hipStreamSynchronize(L.st);
+        if (L.h_bits) (void)hipHostFree(L.h_bits);
+        if (L.h_res) (void)hipHostFree(L.h_res);
+        for (hipEvent_t e : {L.ev_s, L.ev_m, L.ev_c, L.done_ev})
+            if (e) (void)hipEventDestroy(e);
+        if (L.st) (void)hipStreamDestroy(L.st);
+        if (L.own_ctx && L.ctx) tdec_destroy(L.ctx);
+        else if (L.ctx) tdec::ctx_set_launch_reserve(L.ctx, 0, false);  // the caller's context
+        L = Lane{};
+    }
     if (s->d_arena) (void)hipFree(s->d_arena);
-    if (s->h_bits_stage) (void)hipHostFree(s->h_bits_stage);
-    if (s->h_res) (void)hipHostFree(s->h_res);
     for (auto &e : s->copy_ev)
         if (e) (void)hipEventDestroy(e);
-    if (s->done_ev) (void)hipEventDestroy(s->done_ev);
-    if (s->ev_s) (void)hipEventDestroy(s->ev_s);
-    if (s->ev_m) (void)hipEventDestroy(s->ev_m);
-    if (s->ev_c) (void)hipEventDestroy(s->ev_c);
     if (s->copy_st) (void)hipStreamDestroy(s->copy_st);
-    if (s->dec_st) (void)hipStreamDestroy(s->dec_st);
 }
 
 tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
@@ -379,18 +579,27 @@ tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
     if (!cfg || cfg->deadline_us <= 0 || cfg->max_batch_cb < 0 ||
         (cfg->mode != TDEC_SERVE_CONTINUOUS && cfg->mode != TDEC_SERVE_PER_TB) ||
         !tdec::params_valid(&cfg->params) || cfg->model_lat_ns < 0 ||
-        cfg->model_ns_per_kbit < 0)
+        cfg->model_ns_per_kbit < 0 || cfg->max_inflight < 0 || cfg->max_inflight > kMaxLanes)
         return TDEC_EINVAL;
     s->cfg = *cfg;
     if (!s->cfg.slot_budget_bytes) s->cfg.slot_budget_bytes = (size_t)1 << 30;
     if (!s->cfg.max_batch_cb) s->cfg.max_batch_cb = 8192;
     s->cfg.max_batch_cb = std::max(s->cfg.max_batch_cb, 64);  // a TB has at most 64 blocks
+    // the plain per-TB form runs one launch at a time
+    s->n_lanes = s->cfg.mode == TDEC_SERVE_PER_TB ? 1 : (s->cfg.max_inflight ? s->cfg.max_inflight : 2);
+    s->cfg.max_inflight = s->n_lanes;
     s->arena.init((int64_t)s->cfg.slot_budget_bytes);
     s->m_lat = (double)(cfg->model_lat_ns ? cfg->model_lat_ns : 300000);
     s->m_npk = (double)(cfg->model_ns_per_kbit ? cfg->model_ns_per_kbit : 50);
     s->lat.reserve(1 << 16);
     s->ring.resize((size_t)kLaunchRing);
     return TDEC_OK;
+}
+
+void start_threads(tdec_server *s)
+{
+    s->dispatcher = std::thread(dispatcher_main, s);
+    s->completer = std::thread(completer_main, s);
 }
 
 }  // namespace
@@ -417,25 +626,37 @@ tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_s
     s->bits_cap = (size_t)s->cfg.max_batch_cb * 768 + 64;
     s->res_cap = s->cfg.max_batch_cb;
     bool ok = hipMalloc(&s->d_arena, s->cfg.slot_budget_bytes) == hipSuccess &&
-              hipHostMalloc(&s->h_bits_stage, s->bits_cap, hipHostMallocMapped) == hipSuccess &&
-              hipHostMalloc(&s->h_res, sizeof(tdec_tb_result) * (size_t)s->res_cap,
-                            hipHostMallocMapped) == hipSuccess &&
-              hipHostGetDevicePointer((void **)&s->hd_bits, s->h_bits_stage, 0) == hipSuccess &&
-              hipHostGetDevicePointer((void **)&s->hd_res, s->h_res, 0) == hipSuccess &&
-              hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&s->dec_st, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreate(&s->done_ev) == hipSuccess && hipEventCreate(&s->ev_s) == hipSuccess &&
-              hipEventCreate(&s->ev_m) == hipSuccess && hipEventCreate(&s->ev_c) == hipSuccess;
+              hipStreamCreateWithFlags(&s->copy_st, hipStreamNonBlocking) == hipSuccess;
     for (auto &e : s->copy_ev)
         ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     // every copy event starts recorded, so that a wait on it never blocks on nothing
     for (auto &e : s->copy_ev) ok = ok && hipEventRecord(e, s->copy_st) == hipSuccess;
+    tdec_status cs = TDEC_OK;
+    for (int i = 0; i < s->n_lanes && ok; ++i) {
+        Lane &L = s->lanes[i];
+        if (i == 0) {
+            L.ctx = ctx;
+        } else {
+            cs = tdec::ctx_clone(ctx, &L.ctx);
+            ok = cs == TDEC_OK;
+            L.own_ctx = ok;
+        }
+        ok = ok &&
+             hipHostMalloc(&L.h_bits, s->bits_cap, kStageFlags) == hipSuccess &&
+             hipHostMalloc(&L.h_res, sizeof(tdec_tb_result) * (size_t)s->res_cap,
+                           kStageFlags) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&L.hd_bits, L.h_bits, 0) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&L.hd_res, L.h_res, 0) == hipSuccess &&
+             hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreate(&L.done_ev) == hipSuccess && hipEventCreate(&L.ev_s) == hipSuccess &&
+             hipEventCreate(&L.ev_m) == hipSuccess && hipEventCreate(&L.ev_c) == hipSuccess;
+    }
     if (!ok) {
         free_device(s);
         delete s;
-        return TDEC_ENOMEM;
+        return cs == TDEC_EDEVICE ? TDEC_EDEVICE : TDEC_ENOMEM;
     }
-    s->worker = std::thread(worker_main, s);
+    start_threads(s);
     *out = s;
     return TDEC_OK;
 }
@@ -454,17 +675,17 @@ tdec_status tdec_server_create_model(const tdec_server_cfg *cfg, int64_t lat_ns,
     s->model = true;
     s->sim_lat = lat_ns;
     s->sim_npk = ns_per_kbit;
-    s->worker = std::thread(worker_main, s);
+    start_threads(s);
     *out = s;
     return TDEC_OK;
 }
 
-// Submission runs in three steps so that the worker never waits behind the
+// Submission runs in three steps so that the dispatcher never waits behind the
 // copies: (1) under the server mutex, admission and slot allocation (the
 // admitted blocks already count in the queue's totals); (2) under the
 // submitters' own mutex only, the copies into the slots and the event that
 // covers them; (3) under the server mutex again, the blocks join the queue,
-// each naming that event, so the worker can only launch them behind it.
+// each naming that event, so the dispatcher can only launch them behind it.
 static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, const int32_t *tbs,
                            const int16_t *const *h_llr, uint8_t *const *h_bits,
                            int64_t t_arrive_ns, int32_t *status, bool dev)
@@ -508,7 +729,7 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
             if (why == TDEC_SERVE_DONE && (s->cfg.admission & TDEC_ADMIT_DEADLINE)) {
                 // the block joins the next launch after the running one (or
                 // a later one once the queue exceeds a launch)
-                const int64_t start = std::max(now, s->run_end_pred);
+                const int64_t start = std::max(now, s->gpu_end_pred);
                 int64_t pred;
                 int64_t limit = deadline;
                 if (s->cfg.mode == TDEC_SERVE_CONTINUOUS) {
@@ -531,8 +752,11 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 // an idle server always admits: the prediction only judges
                 // the wait behind other work (and an overestimating model
                 // must still see launches to correct itself)
-                const bool busy = s->run_end_pred != 0 || !s->queue.empty() || !adm.empty();
-                if (busy && pred > limit) {
+                const bool busy = s->lanes_busy != 0 || !s->queue.empty() || !adm.empty();
+                // a tenth of the deadline is kept in hand: blocks go out at
+                // once on free lanes, so admission alone decides how close
+                // to the deadline a launch ends, and the prediction is noisy
+                if (busy && pred > limit - (int64_t)s->cfg.deadline_us * 100) {
                     why = TDEC_SERVE_REJ_DEADLINE;
                     s->arena.release(off, bytes);
                 }
@@ -591,7 +815,7 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 g0 = k + 1;
             }
         }
-        // record after this call's copies; the worker waits for it before
+        // record after this call's copies; the dispatcher waits for it before
         // it launches any of these blocks
         seq = ++s->copy_seq;
         if (hipEventRecord(s->copy_ev[seq % kCopyEvents], s->copy_st) != hipSuccess)
@@ -635,6 +859,40 @@ int32_t tdec_server_submit_dev(tdec_server *s, int32_t n, const uint64_t *tags,
                                uint8_t *const *h_bits, int64_t t_arrive_ns, int32_t *status)
 {
     return submit_impl(s, n, tags, tbs, d_llr, h_bits, t_arrive_ns, status, true);
+}
+
+tdec_status tdec_server_replay(tdec_server *s, int32_t n_ticks, int64_t t_first_ns,
+                               int64_t period_ns, const int32_t *counts, const int32_t *tbs,
+                               const int16_t *const *d_llr, uint8_t *const *h_bits,
+                               uint64_t tag_base, int64_t *late_max_ns, int64_t *submit_max_ns)
+{
+    if (!s || n_ticks < 0 || period_ns <= 0 || (n_ticks && (!counts || !tbs || !d_llr)))
+        return TDEC_EINVAL;
+    int64_t total = 0;
+    for (int32_t k = 0; k < n_ticks; ++k) {
+        if (counts[k] < 0) return TDEC_EINVAL;
+        total += counts[k];
+    }
+    std::vector<uint64_t> tags((size_t)std::max<int64_t>(total, 1));
+    for (int64_t i = 0; i < total; ++i) tags[(size_t)i] = tag_base + (uint64_t)i;
+    int64_t late = 0, smax = 0, at = 0;
+    for (int32_t k = 0; k < n_ticks; ++k) {
+        const int64_t tick = t_first_ns + (int64_t)k * period_ns;
+        while (mono_ns() < tick) {
+        }
+        late = std::max(late, mono_ns() - tick);
+        if (counts[k]) {
+            const int64_t t0 = mono_ns();
+            const int32_t r = submit_impl(s, counts[k], tags.data() + at, tbs + at, d_llr + at,
+                                          h_bits ? h_bits + at : nullptr, tick, nullptr, true);
+            if (r < 0) return (tdec_status)r;
+            smax = std::max(smax, mono_ns() - t0);
+        }
+        at += counts[k];
+    }
+    if (late_max_ns) *late_max_ns = late;
+    if (submit_max_ns) *submit_max_ns = smax;
+    return TDEC_OK;
 }
 
 int32_t tdec_server_poll(tdec_server *s, tdec_server_result *out, int32_t max, int32_t wait_us)
@@ -733,7 +991,9 @@ void tdec_server_destroy(tdec_server *s)
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    s->cv_retire.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    if (s->completer.joinable()) s->completer.join();
     free_device(s);
     delete s;
 }

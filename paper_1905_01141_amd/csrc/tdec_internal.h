@@ -174,6 +174,18 @@ struct GatherArgs {
 };
 int launch_gather(const GatherArgs &g, void *stream);
 
+// Launches of ctx leave `n` resident work group slots free for the launches
+// beside them (the serving loop's launch lanes): the persistent decode grid
+// is at most the resident capacity minus n.  small_asm: transport block
+// assembly in kAsmGrid small work groups, which fit the slots that such a
+// launch leaves.
+void ctx_set_launch_reserve(tdec_ctx *ctx, int n, bool small_asm);
+
+// A new context on src's device with src's workspace budget and window
+// choices (the serving loop's further launch lanes, each with a workspace of
+// its own so that their launches can run at the same time).
+tdec_status ctx_clone(const tdec_ctx *src, tdec_ctx **out);
+
 // The ranges tdec.h gives for every field of tdec_params (the window count
 // is checked against each block size where it is used).
 bool params_valid(const tdec_params *p);
@@ -204,10 +216,18 @@ int static_scratch_init(int device);
 char *static_scratch_ptr(int device);
 // Zero n words with a fill kernel (no memset node when the stream is captured).
 int launch_zero_words(uint32_t *p, int n, void *stream);
+// Work groups of the assembly launch: each takes transport blocks t, t +
+// grid, ...  So few small work groups fit the compute unit slots that a
+// decode launch beside them leaves free (the serving loop keeps that many
+// free), and the assembly of one launch never waits for the decode of the
+// next.
+constexpr int kAsmGrid = 64;
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
+// small_grid: kAsmGrid work groups of 128 threads (launch lanes) instead of
+// one of 256 threads per transport block.
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
-                       uint8_t *bits, void *res, void *stream);
+                       uint8_t *bits, void *res, bool small_grid, void *stream);
 int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
                   const uint32_t *crc_tab, void *stream);
 int launch_tb_crc_attach(const uint8_t *payload, int32_t tbs, uint8_t *stream_bits,

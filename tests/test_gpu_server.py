@@ -174,3 +174,72 @@ def test_launch_records_on_the_device(dev):
         assert b["t_start_ns"] >= a["t_end_ns"]
     for i, t in enumerate(tbs_list):
         assert np.array_equal(outs[i], out[i]), i
+
+
+def test_arrivals_during_a_long_launch_overlap_on_the_device(dev):
+    """Continuous batching: transport blocks submitted while a long launch
+    runs are taken and enqueued on a second lane before the first launch has
+    finished (their work groups take the compute units the first launch's
+    leave, with no host round trip between); every result equals its decode
+    alone (a direct call) and the oracle's."""
+    T, D, torch = dev
+    big = [75376] * 160          # 2080 code blocks, 8 forced iterations: a long launch
+    small = [40, 1000, 6121, 20000]
+    tbs_list = big + small
+    say(f"[server] overlap: {len(big)} x 75376 then {small}")
+    esn0 = [14.0] * len(big) + [3.0] * len(small)
+    llr, pays, lo, bo = tb_batch(tbs_list, "64qam", esn0, 12)
+    x = torch.from_numpy(llr).cuda()
+    torch.cuda.synchronize()
+    p = T.params(8, 0, 0, 1)
+    # each group alone, direct calls
+    nb = int(bo[-1] + (tbs_list[-1] + 7) // 8)
+    eb = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    er = torch.zeros(len(tbs_list) * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    nbig = len(big)
+    D.tb_decode_batch(big, lo[:nbig], bo[:nbig], x, p, eb, er[:nbig * T.TB_RESULT_BYTES])
+    D.tb_decode_batch(small, lo[nbig:], bo[nbig:] - bo[nbig], x, p, eb[int(bo[nbig]):],
+                      er[nbig * T.TB_RESULT_BYTES:])
+    torch.cuda.synchronize()
+    alone_b = eb.cpu().numpy()
+    alone_r = T.parse_tb_results(er.cpu().numpy())
+    out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+    srv = T.Server(D, T.server_cfg(p, deadline_us=10_000_000))
+    try:
+        srv.submit(list(range(nbig)), big, [x.data_ptr() + 2 * int(lo[i]) for i in range(nbig)],
+                   [out[i].ctypes.data for i in range(nbig)], device=True)
+        time.sleep(0.0002)
+        idx = list(range(nbig, len(tbs_list)))
+        srv.submit(idx, small, [x.data_ptr() + 2 * int(lo[i]) for i in idx],
+                   [out[i].ctypes.data for i in idx], device=True)
+        srv.drain(60000)
+        res, t0 = [], time.monotonic()
+        while len(res) < len(tbs_list) and time.monotonic() - t0 < 30:
+            res += srv.poll(4096, 100000)
+        recs = srv.launches()
+    finally:
+        srv.close()
+    res = {r["tag"]: r for r in res}
+    assert len(recs) == 2, recs
+    a, b = sorted(recs, key=lambda r: r["t_start_ns"])
+    assert a["n_tb"] == nbig and b["n_tb"] == len(small)
+    # the second launch was enqueued while the first one's decode kernel ran
+    assert b["t_start_ns"] + b["pre_ns"] < a["t_start_ns"] + a["pre_ns"] + a["coding_ns"], \
+        "the second launch waited for the first"
+    say(f"[server] big launch {(a['t_end_ns'] - a['t_start_ns']) / 1e3:.0f} us (coding "
+        f"{a['coding_ns'] / 1e3:.0f}), small one taken {(b['t_start_ns'] - a['t_start_ns']) / 1e3:.0f}"
+        f" us after it, {(b['t_end_ns'] - b['t_start_ns']) / 1e3:.0f} us (coding "
+        f"{b['coding_ns'] / 1e3:.0f})")
+    for i, t in enumerate(tbs_list):
+        r = res[i]
+        assert r["status"] == T.SERVE_DONE
+        assert r["tb_ok"] == alone_r[i]["tb_ok"], i
+        assert r["max_iters_used"] == alone_r[i]["max_iters_used"] == 8, i
+        assert np.array_equal(out[i], alone_b[bo[i]:bo[i] + (t + 7) // 8]), i
+    op = O.params(8, 0, 0, 1)
+    for i in [0, nbig - 1] + idx:
+        t = tbs_list[i]
+        ob, ores = O.tb_decode_windows(llr[lo[i]:lo[i] + O.tb_llr_count(t)], t, op,
+                                       [D.pick_windows(K) for K, _ in O.cb_sizes(t)])
+        assert res[i]["tb_ok"] == ores["tb_ok"], i
+        assert np.array_equal(out[i], ob), i

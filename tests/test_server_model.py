@@ -225,8 +225,9 @@ def test_per_tb_mode_deadline_admission_bounds_the_queue():
 
 def test_launch_records_account_for_every_block():
     """The per-launch record (the paper's performance captor, Sec. IV-D):
-    launches in time order, their TB and code block counts add up to what
-    completed, each covers its coding delay, and a reset empties the ring."""
+    launches in completion order, their TB and code block counts add up to
+    what completed, each covers its coding delay, and a reset empties the
+    ring."""
     cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=100000, model_lat_ns=500_000)
     srv = T.Server.model(cfg, 500_000, 0)
     try:
@@ -250,7 +251,7 @@ def test_launch_records_account_for_every_block():
                T.segment(t)["Cminus"] * T.segment(t)["Kminus"] for t in tbs) * 4
     assert sum(r["cb_bits"] for r in recs) == bits
     for a, b in zip(recs, recs[1:]):
-        assert b["t_start_ns"] >= a["t_end_ns"]
+        assert b["t_end_ns"] >= a["t_end_ns"]
     for r in recs:
         assert r["t_end_ns"] - r["t_start_ns"] >= 500_000
         assert r["coding_ns"] == r["t_end_ns"] - r["t_start_ns"]
@@ -314,3 +315,79 @@ def test_creation_checks_every_decoder_parameter():
             T.Server.model(T.server_cfg(p), 100_000, 0)
     srv = T.Server.model(T.server_cfg(T.params(8, T.STOP_MI | T.STOP_CRC, 0, 1, 1)), 100_000, 0)
     srv.close()
+
+
+def test_arrivals_during_a_launch_go_out_on_another_lane():
+    """Continuous batching across launches: a batch that arrives while a
+    long launch runs is dispatched on a free lane shortly before that launch
+    is predicted to end (its lead: a quarter of the launch, at most 200 us),
+    so the two launches are in flight together and the hand-over is hidden;
+    with one lane it waits for the first launch's results."""
+    def run(max_inflight):
+        cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=1_000_000,
+                           model_lat_ns=20_000_000, max_inflight=max_inflight)
+        srv = T.Server.model(cfg, 20_000_000, 0)
+        try:
+            _submit(srv, list(range(5)), [6000] * 5)
+            time.sleep(0.004)
+            _submit(srv, list(range(5, 8)), [3000] * 3)
+            srv.drain(10000)
+            res = {r["tag"]: r for r in _collect(srv, 8)}
+            recs = srv.launches()
+            s = srv.stats()
+        finally:
+            srv.close()
+        return res, recs, s
+
+    res, recs, s = run(0)
+    assert s["batches"] == 2 and len(recs) == 2
+    first = min(recs, key=lambda r: r["t_start_ns"])
+    second = max(recs, key=lambda r: r["t_start_ns"])
+    assert first["n_tb"] == 5 and second["n_tb"] == 3
+    assert second["t_start_ns"] < first["t_end_ns"]                        # in flight together
+    assert second["t_start_ns"] >= first["t_start_ns"] + 20_000_000 - 200_000 - 50_000  # the lead
+    assert s["busy_ns"] < sum(r["t_end_ns"] - r["t_start_ns"] for r in recs)
+    res1, recs1, s1 = run(1)
+    a, b = sorted(recs1, key=lambda r: r["t_start_ns"])
+    assert b["t_start_ns"] >= a["t_end_ns"]                                # one lane: one after the other
+
+
+def test_max_inflight_range():
+    for m in (-1, 9):
+        with pytest.raises(T.TdecError):
+            T.Server.model(T.server_cfg(T.params(8, 1, 0, 1), max_inflight=m), 100_000, 0)
+    for m in (1, 8):
+        T.Server.model(T.server_cfg(T.params(8, 1, 0, 1), max_inflight=m), 100_000, 0).close()
+
+
+def test_replay_submits_each_tick_at_its_time():
+    """The native load generator: counts[k] arrivals at tick k, stamped with
+    the tick, tags in arrival order."""
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=1_000_000)
+    srv = T.Server.model(cfg, 100_000, 0)
+    bufs = [np.zeros(T.tb_llr_count(t), np.int16) for t in (40, 1000, 6121)]
+    counts = [3, 0, 2, 4]
+    tbs = [40, 1000, 6121, 40, 1000, 6121, 40, 1000, 6121]
+    ptrs = [bufs[i % 3].ctypes.data for i in range(9)]
+    try:
+        t_first = T.now_ns() + 2_000_000
+        late, smax = srv.replay(counts, tbs, ptrs, period_ns=2_000_000, t_first_ns=t_first,
+                                tag_base=100)
+        srv.drain(10000)
+        res = _collect(srv, 9)
+    finally:
+        srv.close()
+    assert late >= 0 and smax > 0
+    by = {r["tag"]: r for r in res}
+    assert sorted(by) == list(range(100, 109))
+    ticks = [0, 0, 0, 2, 2, 3, 3, 3, 3]
+    for i in range(9):
+        r = by[100 + i]
+        assert r["status"] == T.SERVE_DONE and r["tbs"] == tbs[i]
+        assert r["t_arrive_ns"] == t_first + ticks[i] * 2_000_000
+    with pytest.raises(T.TdecError):
+        srv2 = T.Server.model(cfg, 100_000, 0)
+        try:
+            srv2.replay([1, -1], [], [])
+        finally:
+            srv2.close()
