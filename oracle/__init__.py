@@ -86,6 +86,10 @@ def lib():
             fn.argtypes = [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32,
                            ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p] + \
                           ([ct.c_void_p] if fn is L.or16_constituent else [])
+        L.or16_constituent_sched.argtypes = [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                             ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                             ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32,
+                                             ct.c_void_p]
         L.or_cb_decode_ex.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, P(Params),
                                       ct.c_void_p, ct.c_void_p, P(ct.c_int32), P(ct.c_int32),
                                       ct.c_int32, ct.c_void_p]
@@ -221,8 +225,10 @@ def mi_converged(s, s_prev, it, K, eps) -> bool:
     return bool(lib().or_mi_converged(s, s_prev, it, K, eps))
 
 
-def constituent(lsa, lp, tail, n_windows=1, a_in=None, b_in=None, use16=False):
-    """One max-log-MAP pass; returns (le, a_out, b_out[, sat])."""
+def constituent(lsa, lp, tail, n_windows=1, a_in=None, b_in=None, use16=False, periods=(4, 2)):
+    """One max-log-MAP pass; returns (le, a_out, b_out[, sat]).  use16: the
+    int16 twin, shifting the forward / backward metrics every periods[0] /
+    periods[1] steps."""
     lsa = np.ascontiguousarray(lsa, np.int64)
     lp = np.ascontiguousarray(lp, np.int64)
     tail = np.ascontiguousarray(tail, np.int64)
@@ -235,8 +241,9 @@ def constituent(lsa, lp, tail, n_windows=1, a_in=None, b_in=None, use16=False):
     le = np.zeros(K, np.int64)
     if use16:
         sat = np.zeros(1, np.int64)
-        rc = lib().or16_constituent(K, _ptr(lsa), _ptr(lp), _ptr(tail), nw, _ptr(a_in),
-                                    _ptr(b_in), _ptr(a_out), _ptr(b_out), _ptr(le), _ptr(sat))
+        rc = lib().or16_constituent_sched(K, _ptr(lsa), _ptr(lp), _ptr(tail), nw, _ptr(a_in),
+                                          _ptr(b_in), _ptr(a_out), _ptr(b_out), _ptr(le),
+                                          int(periods[0]), int(periods[1]), _ptr(sat))
     else:
         rc = lib().or_constituent(K, _ptr(lsa), _ptr(lp), _ptr(tail), nw, _ptr(a_in),
                                   _ptr(b_in), _ptr(a_out), _ptr(b_out), _ptr(le))

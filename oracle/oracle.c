@@ -419,9 +419,18 @@ int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64
 /* ===================================================================== */
 /* Same recursion with every metric stored in int16:
  *  - candidate sums (metric + gamma) saturate to [-32768, 32767];
- *  - a state vector is shifted so that its maximum is 0 after steps 1 and 2
- *    of a window and after every even step, and left alone after odd steps
- *    from the third on (the schedule the GPU kernel uses);
+ *  - a state vector is shifted so that its maximum is 0 after every step
+ *    whose count from the window edge is a multiple of the recursion's
+ *    period (period 2: also after steps 1 and 2), and left alone after the
+ *    others.
+ *    The GPU kernel shifts the recursion that runs beside the extrinsic
+ *    every 2 steps and the recursion it recomputes from checkpoints every 4
+ *    (forward or backward, depending on the lane), so the twin runs with
+ *    the periods (4, 2) and (2, 4) for (forward, backward).  The largest
+ *    extrinsic sum is then 6141 (one unshifted step) + 3 * 6141 (three) +
+ *    6141 (the branch) = 30705, and a winning one is at least -32752, so no
+ *    value that decides a result leaves int16 -- the twin counts any that
+ *    would;
  *  - minus infinity is -32768; in window 0 the states that cannot be reached
  *    after one step (all but 0 and 4) and after two steps (odd states) are
  *    pinned back to -32768;
@@ -447,12 +456,27 @@ static void or16_normalise(int16_t v[8])
     }
 }
 
-static int or16_norm_step(int32_t t) { return t <= 2 || (t & 1) == 0; }
+/* Shift after step t (counted from 1 at the window edge) of a recursion
+ * with the given period: period 2 also shifts after steps 1 and 2, a longer
+ * period only after its multiples. */
+static int or16_norm_step(int32_t t, int32_t period)
+{
+    return period <= 2 ? (t <= 2 || t % 2 == 0) : t % period == 0;
+}
 
 int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64_t tail[6],
                      int32_t nw, const int64_t *a_in, const int64_t *b_in,
                      int64_t *a_out, int64_t *b_out, int64_t *le, int64_t *sat)
 {
+    return or16_constituent_sched(K, lsa, lp, tail, nw, a_in, b_in, a_out, b_out, le, 4, 2, sat);
+}
+
+int or16_constituent_sched(int32_t K, const int64_t *lsa, const int64_t *lp,
+                           const int64_t tail[6], int32_t nw, const int64_t *a_in,
+                           const int64_t *b_in, int64_t *a_out, int64_t *b_out, int64_t *le,
+                           int32_t a_period, int32_t b_period, int64_t *sat)
+{
+    if (a_period < 1 || b_period < 1) return -1;
     if (nw > 1 && (!a_in || !b_in)) return -1;
     const int32_t W = or_win_len(K, nw);
     if (!W) return -1;
@@ -494,7 +518,7 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
                 int pinned = w == 0 && ((i == 0 && s != 0 && s != 4) || (i == 1 && (s & 1)));
                 if (!pinned && (int32_t)nx[s] != ex[s]) ++nsat;
             }
-            if (or16_norm_step(i + 1)) or16_normalise(nx);
+            if (or16_norm_step(i + 1, a_period)) or16_normalise(nx);
             if (w == 0 && i == 0)
                 for (int s = 0; s < 8; ++s) if (s != 0 && s != 4) nx[s] = -32768;
             if (w == 0 && i == 1)
@@ -548,7 +572,7 @@ int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int
                 int32_t e = ecand[s][0] > ecand[s][1] ? ecand[s][0] : ecand[s][1];
                 if ((int32_t)nb[s] != e) ++nsat;
             }
-            if (or16_norm_step(n - i)) or16_normalise(nb);
+            if (or16_norm_step(n - i, b_period)) or16_normalise(nb);
             memcpy(Bt[i], nb, sizeof nb);
         }
         if (b_out && w > 0) {

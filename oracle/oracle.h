@@ -151,10 +151,17 @@ int or_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64
 
 /* The int16 twin of or_constituent: identical interface, metrics stored in
  * int16 with saturating candidate adds and renormalisation.  *sat_count is
- * increased by the number of saturated values that could decide a result. */
+ * increased by the number of saturated values that could decide a result.
+ * The forward metric is shifted to maximum 0 after every a_period-th step
+ * of a window (with period 2 also after steps 1 and 2), the backward metric
+ * likewise with b_period; or16_constituent uses (4, 2). */
 int or16_constituent(int32_t K, const int64_t *lsa, const int64_t *lp, const int64_t tail[6],
                      int32_t nw, const int64_t *a_in, const int64_t *b_in,
                      int64_t *a_out, int64_t *b_out, int64_t *le, int64_t *sat_count);
+int or16_constituent_sched(int32_t K, const int64_t *lsa, const int64_t *lp,
+                           const int64_t tail[6], int32_t nw, const int64_t *a_in,
+                           const int64_t *b_in, int64_t *a_out, int64_t *b_out, int64_t *le,
+                           int32_t a_period, int32_t b_period, int64_t *sat_count);
 
 /* Decode one code block.
  *   llr      : [3][K+4] int16 channel LLRs (clamped here to +-2047; the F

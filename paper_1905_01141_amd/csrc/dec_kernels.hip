@@ -195,11 +195,19 @@ __device__ __forceinline__ void unpack4(uint4 u, s2 V[4])
 }
 
 // Forward step i = i0 + t + 1 (counted from the window start) is normalised
-// for i <= 2 and for even i; in window 0 the states that cannot be reached
-// after 1 and 2 steps are pinned back to minus infinity.
+// for i <= 2 and for even i -- or, SPARSE, only for i a multiple of 4; in
+// window 0 the states that cannot be reached after 1 and 2 steps are pinned
+// back to minus infinity.  The recursion that runs beside the extrinsic is
+// dense; phase 1 and the recomputation from checkpoints are sparse: an
+// extrinsic sum then holds one metric at most 1 step and the other at most
+// 3 steps past its last shift (or its normalised start), at most 6141 +
+// 3 * 6141 + 6141 = 30705 and, for a winning sum, at least -32752
+// (checkpoints and window ends, multiples of 8 steps from the window edges,
+// are shifted in both forms).
+template <bool SPARSE = false>
 __device__ __forceinline__ void fwd_post(s2 A[4], int i0, int t, bool first)
 {
-    if ((t & 1) || (i0 == 0 && t == 0)) normalise(A);
+    if (SPARSE ? (t & 3) == 3 : ((t & 1) != 0 || (i0 == 0 && t == 0))) normalise(A);
     if (i0 == 0 && t < 2 && first) {
         const s2 neg = (s2){kNeg, kNeg};
         A[1] = neg;
@@ -209,8 +217,13 @@ __device__ __forceinline__ void fwd_post(s2 A[4], int i0, int t, bool first)
 }
 
 // Backward metric at local position i = i0 + t is normalised when W - i <= 2
-// or W - i is even (W and i0 are multiples of 8).
-__device__ __forceinline__ bool bwd_norm(int i0, int t, int W) { return !(t & 1) || (i0 == W - S && t >= S - 2); }
+// or W - i is even -- or, SPARSE, a multiple of 4 (W and i0 are multiples
+// of 8; the forms are used as in fwd_post).
+template <bool SPARSE = false>
+__device__ __forceinline__ bool bwd_norm(int i0, int t, int W)
+{
+    return SPARSE ? (t & 3) == 0 : ((t & 1) == 0 || (i0 == W - S && t >= S - 2));
+}
 
 // Everything a lane needs for one constituent pass over its window.
 struct Win {
@@ -303,7 +316,7 @@ __device__ void ph1_fwd(const Win &c, s2 A[4])
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             acs_fwd(A, mk_g00(g[t]), g[t]);
-            fwd_post(A, i0, t, c.first);
+            fwd_post<true>(A, i0, t, c.first);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) r[t] = rn[t];
@@ -326,7 +339,7 @@ __device__ void ph1_bwd(const Win &c, s2 B[4])
 #pragma unroll
         for (int t = S - 1; t >= 0; --t) {
             acs_bwd(B, mk_g00(g[t]), g[t]);
-            if (bwd_norm(i0, t, c.W)) normalise(B);
+            if (bwd_norm<true>(i0, t, c.W)) normalise(B);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) r[t] = rn[t];
@@ -368,7 +381,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
             q_to_p(B, BP[t]);
             g0[t] = mk_g00(g[t]);
             acs_bwd(B, g0[t], g[t]);
-            if (bwd_norm(i0, t, c.W)) normalise(B);
+            if (bwd_norm<true>(i0, t, c.W)) normalise(B);
         }
     }
     // two segments per trip: the hand-over of the next segment's values
@@ -387,7 +400,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
             q_to_p(Bn, BPn[u]);
             g0n[u] = mk_g00(gn[u]);
             acs_bwd(Bn, g0n[u], gn[u]);
-            if (bwd_norm(i1, u, c.W)) normalise(Bn);
+            if (bwd_norm<true>(i1, u, c.W)) normalise(Bn);
             const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
             fwd_post(A, i0, t, c.first);
             emit<DEC, MI>(c, i0, t, r[t], g[t], le, acc);
@@ -438,7 +451,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
             p_to_q(A, AQ[t]);
             g0[t] = mk_g00(g[t]);
             acs_fwd(A, g0[t], g[t]);
-            fwd_post(A, i0, t, c.first);
+            fwd_post<true>(A, i0, t, c.first);
         }
     }
     // two segments per trip: the hand-over of the next segment's values
@@ -456,7 +469,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
             p_to_q(An, AQn[t]);  // recompute step of the next segment
             g0n[t] = mk_g00(gn[t]);
             acs_fwd(An, g0n[t], gn[t]);
-            fwd_post(An, i1, t, c.first);
+            fwd_post<true>(An, i1, t, c.first);
             const int u = S - 1 - t;
             const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
             if (bwd_norm(i0, u, c.W)) normalise(B);

@@ -146,18 +146,40 @@ def _adversarial_sets(rng, K):
     yield rng.integers(-60, 61, K), rng.integers(-60, 61, K), rng.integers(-60, 61, 6)
 
 
+@pytest.mark.parametrize("periods", [(4, 2), (2, 4), (2, 2)])
 @pytest.mark.parametrize("K,nw", [(40, 1), (192, 1), (192, 8), (6144, 32), (1056, 11),
                                   (488, 8), (6144, 31)])
-def test_int16_twin_equals_exact_constituent(orc, K, nw):
+def test_int16_twin_equals_exact_constituent(orc, K, nw, periods):
+    """Every shift schedule the GPU kernel uses (the recomputed recursion
+    every 4 steps, the one beside the extrinsic every 2; either direction)."""
     rng = np.random.default_rng(K * 7 + nw)
     for lsa, lp, tail in _adversarial_sets(rng, K):
         a64 = b64 = a16 = b16 = None
         for it in range(3):  # boundary metrics carried across passes
             le, a64, b64 = orc.constituent(lsa, lp, tail, nw, a64, b64)
-            le16, a16, b16, sat = orc.constituent(lsa, lp, tail, nw, a16, b16, use16=True)
+            le16, a16, b16, sat = orc.constituent(lsa, lp, tail, nw, a16, b16, use16=True,
+                                                  periods=periods)
             assert sat == 0
             assert np.array_equal(le, le16)
             lsa = np.clip(lsa + rng.integers(-300, 301, K), -4094, 4094)
+
+
+@pytest.mark.parametrize("periods", [(8, 2), (2, 8)])
+def test_int16_twin_counts_saturation_of_sparser_schedules(orc, periods):
+    """Shifting less often than the GPU kernel does lets winning sums leave
+    int16 on extreme inputs, and the twin counts it: the bound is tight
+    enough to matter (a control for the test above)."""
+    rng = np.random.default_rng(99)
+    K = 192
+    hits = 0
+    for _ in range(40):
+        lsa = rng.choice([-4094, 4094], K)
+        lp = rng.choice([-2047, 2047], K)
+        tail = rng.choice([-2047, 2047], 6)
+        hits += orc.constituent(lsa, lp, tail, 1, use16=True, periods=periods)[3]
+        hits += orc.constituent(np.full(K, 4094), np.full(K, 2047), np.full(6, 2047), 1,
+                                use16=True, periods=periods)[3]
+    assert hits > 0
 
 
 def test_int16_twin_worst_case_boundary_inits(orc):
@@ -174,8 +196,10 @@ def test_int16_twin_worst_case_boundary_inits(orc):
         a.reshape(nw, 8)[:, 0] = 0
         b.reshape(nw, 8)[:, 3] = 0
         le, _, _ = orc.constituent(lsa, lp, tail, nw, a, b)
-        le16, _, _, sat = orc.constituent(lsa, lp, tail, nw, a, b, use16=True)
-        assert sat == 0 and np.array_equal(le, le16)
+        for periods in ((4, 2), (2, 4)):
+            le16, _, _, sat = orc.constituent(lsa, lp, tail, nw, a, b, use16=True,
+                                              periods=periods)
+            assert sat == 0 and np.array_equal(le, le16)
 
 
 # ------------------------------------------------------------------ turbo
