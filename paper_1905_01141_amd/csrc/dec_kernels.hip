@@ -92,11 +92,11 @@ __device__ __forceinline__ void acs_fwd(s2 A[4], s2 g00, s2 g01)
     A[3] = n3;
 }
 
-// Forward step that also returns the extrinsic of the step: the candidate
-// sums alpha_k(p) + gamma(p -> n) of the recursion, plus beta_{k+1}(n) (P
-// layout), maximised per input bit u.  Le = M1 - M0 - Lsa modulo 2^16 (the
-// true value fits int16).
-__device__ __forceinline__ int acs_fwd_le(s2 A[4], s2 g00, s2 g01, const s2 BP[4])
+// Forward step that also returns the extrinsic maxima of the step: the
+// candidate sums alpha_k(p) + gamma(p -> n) of the recursion, plus
+// beta_{k+1}(n) (P layout), maximised per input bit u: (M0, M1).  The
+// extrinsic is Le = M1 - M0 - Lsa modulo 2^16 (the true value fits int16).
+__device__ __forceinline__ s2 acs_fwd_le(s2 A[4], s2 g00, s2 g01, const s2 BP[4])
 {
     const s2 t0 = adds(bcx(A[0]), g00), t1 = swp(adds(bcx(A[1]), g00));
     const s2 t2 = swp(adds(bcx(A[2]), g01)), t3 = adds(bcx(A[3]), g01);
@@ -110,7 +110,7 @@ __device__ __forceinline__ int acs_fwd_le(s2 A[4], s2 g00, s2 g01, const s2 BP[4
     A[1] = vmax(t2, t3);
     A[2] = vmax(t4, t5);
     A[3] = vmax(t6, t7);
-    return (int)(short)(m.y - m.x - g01.y);
+    return m;
 }
 
 // Backward step, Q layout in and out.
@@ -126,9 +126,9 @@ __device__ __forceinline__ void acs_bwd(s2 B[4], s2 g00, s2 g01)
     B[3] = vmax(c30, c31);
 }
 
-// Backward step that also returns the extrinsic from alpha_k (Q layout):
-// the candidate sums beta_{k+1}(n) + gamma(p -> n) plus alpha_k(p).
-__device__ __forceinline__ int acs_bwd_le(s2 B[4], const s2 AQ[4], s2 g00, s2 g01)
+// Backward step that also returns the extrinsic maxima from alpha_k (Q
+// layout): the candidate sums beta_{k+1}(n) + gamma(p -> n) plus alpha_k(p).
+__device__ __forceinline__ s2 acs_bwd_le(s2 B[4], const s2 AQ[4], s2 g00, s2 g01)
 {
     const s2 c00 = adds(bcx(B[0]), g00), c01 = swp(adds(bcx(B[2]), g00));
     const s2 c10 = swp(adds(bcy(B[0]), g01)), c11 = adds(bcy(B[2]), g01);
@@ -143,7 +143,7 @@ __device__ __forceinline__ int acs_bwd_le(s2 B[4], const s2 AQ[4], s2 g00, s2 g0
     B[1] = vmax(c10, c11);
     B[2] = vmax(c20, c21);
     B[3] = vmax(c30, c31);
-    return (int)(short)(m.y - m.x - g01.y);
+    return m;
 }
 
 // Shift a metric vector so that its maximum is 0.
@@ -171,15 +171,6 @@ __device__ __forceinline__ void q_to_p(const s2 Q[4], s2 P[4])
     P[1] = (s2){Q[0].y, Q[2].y};
     P[2] = (s2){Q[1].x, Q[3].x};
     P[3] = (s2){Q[1].y, Q[3].y};
-}
-
-// 0.75 * e truncated toward zero, clamped to +-2047.  Clamping e to +-2730
-// first gives the same value; 0.75 * e is exact in fp32 and the conversion
-// back truncates toward zero.
-__device__ __forceinline__ int scale_ext(int e)
-{
-    e = max(-2730, min(2730, e));
-    return (int)((float)e * 0.75f);
 }
 
 __device__ __forceinline__ uint4 pack4(const s2 V[4])
@@ -274,26 +265,45 @@ __device__ __forceinline__ void gammas(const Win &c, int i0, const uint32_t r[S]
     }
 }
 
-// Output of one step: decoder 1 stores Ls + scaled Le (decoder 2's
-// systematic + a-priori) at its natural position; decoder 2 stores twice the
-// scaled Le (decoder 1's next a-priori) plus the hard decision of pi(k) in
-// the low bit.  The hard decisions stay readable from the low bits until the
-// next decoder-1 pass, i.e. through the CRC check and the output.  With MI,
-// decoder 2 also adds the entropy of its hard decision, h(|L|) from the LDS
-// table (L = Ls + La + Le, the a-posteriori value), to the lane's sum.
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+// Output of two steps ta, ta + 1 from their extrinsic maxima pairs (M0, M1)
+// ma, mb, restaged words ra, rb and branch metric pairs ga, gb, both steps
+// packed in one register pair by pair:
+//   Le = M1 - M0 - Lsa, modulo 2^16 (the true values fit int16);
+//   q = 0.75 Le truncated toward zero and clamped to +-2047, formed as
+//       (3 (x + [x < 0])) >> 2 with x = Le clamped to +-2730 (for x < 0 the
+//       bias 3 turns the floor of 3x / 4 into its ceiling);
+//   decoder 1 stores Ls + q (decoder 2's systematic + a-priori) at the two
+//   natural positions, one 32-bit LDS store;
+//   decoder 2 stores 2 q + the hard decision of pi(k), [L > 0] for the
+//   a-posteriori L = Lsa + Le, at each step's LDS address.  The hard
+//   decisions stay readable from the low bits until the next decoder-1
+//   pass, i.e. through the CRC check and the output.  With MI, decoder 2
+//   also adds the entropy of its hard decisions, h(|L|) from the LDS table,
+//   to the lane's sum.
 template <int DEC, bool MI = false>
-__device__ __forceinline__ void emit(const Win &c, int i0, int t, uint32_t r, s2 g01, int le,
-                                     int &acc)
+__device__ __forceinline__ void emit2(const Win &c, int i0, int ta, uint32_t ra, uint32_t rb,
+                                      s2 ga, s2 gb, s2 ma, s2 mb, int &acc)
 {
-    const int q = scale_ext(le);
+    const s2 m1 = as_s2(__builtin_amdgcn_perm(as_u(mb), as_u(ma), 0x07060302u));   // (ma.y, mb.y)
+    const s2 m0 = as_s2(__builtin_amdgcn_perm(as_u(mb), as_u(ma), 0x05040100u));   // (ma.x, mb.x)
+    const s2 lsa = as_s2(__builtin_amdgcn_perm(as_u(gb), as_u(ga), 0x07060302u));  // (ga.y, gb.y)
+    const s2 le = m1 - m0 - lsa;
+    const s2 x = vmax(__builtin_elementwise_min(le, (s2){2730, 2730}), (s2){-2730, -2730});
+    const s2 neg = __builtin_bit_cast(s2, __builtin_bit_cast(u2, x) >> (u2){15, 15});
+    const s2 q = ((x + neg) * (s2){3, 3}) >> (s2){2, 2};
     if (DEC == 1) {
-        c.E[epad(c.lo + i0) + t] = (short)((int)(short)(r >> 16) + q);
+        const s2 ls = as_s2(__builtin_amdgcn_perm(rb, ra, 0x07060302u));  // (Ls_a, Ls_b)
+        *(s2 *)(c.E + epad(c.lo + i0) + ta) = ls + q;
     } else {
-        const uint32_t a = r >> 16;
-        const int lapp = (int)g01.y + le;
-        const int bit = lapp > 0;
-        *(short *)((char *)c.E + a) = (short)(2 * q + bit);
-        if (MI) acc += c.mit[min(abs(lapp), kMiTabN - 1)];
+        const s2 lapp = lsa + le;
+        const s2 bit = __builtin_bit_cast(s2, __builtin_bit_cast(u2, (s2){0, 0} - lapp) >> (u2){15, 15});
+        const s2 o = q * (s2){2, 2} + bit;
+        *(short *)((char *)c.E + (ra >> 16)) = o.x;
+        *(short *)((char *)c.E + (rb >> 16)) = o.y;
+        if (MI)
+            acc += c.mit[min(abs((int)lapp.x), kMiTabN - 1)] + c.mit[min(abs((int)lapp.y), kMiTabN - 1)];
     }
 }
 
@@ -368,7 +378,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
     const int last = c.W - S;
     int i0 = c.M;
     uint32_t r[S], rn[S], rnn[S];
-    s2 g[S], g0[S], BP[S][4];
+    s2 g[S], g0[S], BP[S][4], m[S];
     load_seg(c, i0, r);
     uint4 ckn = ck_at(c, min(i0 + S, last));
     load_seg(c, min(i0 + S, last), rn);
@@ -401,9 +411,9 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
             g0n[u] = mk_g00(gn[u]);
             acs_bwd(Bn, g0n[u], gn[u]);
             if (bwd_norm<true>(i1, u, c.W)) normalise(Bn);
-            const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
+            m[t] = acs_fwd_le(A, g0[t], g[t], BP[t]);
             fwd_post(A, i0, t, c.first);
-            emit<DEC, MI>(c, i0, t, r[t], g[t], le, acc);
+            if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r[t - 1], r[t], g[t - 1], g[t], m[t - 1], m[t], acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -420,9 +430,9 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
     }
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-        const int le = acs_fwd_le(A, g0[t], g[t], BP[t]);
+        m[t] = acs_fwd_le(A, g0[t], g[t], BP[t]);
         fwd_post(A, i0, t, c.first);
-        emit<DEC, MI>(c, i0, t, r[t], g[t], le, acc);
+        if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r[t - 1], r[t], g[t - 1], g[t], m[t - 1], m[t], acc);
     }
     return acc;
 }
@@ -438,7 +448,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
     if (c.M <= 0) return acc;
     int i0 = c.M - S;
     uint32_t r[S], rn[S], rnn[S];
-    s2 g[S], g0[S], AQ[S][4];
+    s2 g[S], g0[S], AQ[S][4], m[S];
     load_seg(c, i0, r);
     uint4 ckn = ck_at(c, max(i0 - S, 0));
     load_seg(c, max(i0 - S, 0), rn);
@@ -471,9 +481,9 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
             acs_fwd(An, g0n[t], gn[t]);
             fwd_post<true>(An, i1, t, c.first);
             const int u = S - 1 - t;
-            const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
+            m[u] = acs_bwd_le(B, AQ[u], g0[u], g[u]);
             if (bwd_norm(i0, u, c.W)) normalise(B);
-            emit<DEC, MI>(c, i0, u, r[u], g[u], le, acc);
+            if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r[u], r[u + 1], g[u], g[u + 1], m[u], m[u + 1], acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -490,9 +500,9 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
     }
 #pragma unroll
     for (int u = S - 1; u >= 0; --u) {
-        const int le = acs_bwd_le(B, AQ[u], g0[u], g[u]);
+        m[u] = acs_bwd_le(B, AQ[u], g0[u], g[u]);
         if (bwd_norm(i0, u, c.W)) normalise(B);
-        emit<DEC, MI>(c, i0, u, r[u], g[u], le, acc);
+        if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r[u], r[u + 1], g[u], g[u + 1], m[u], m[u + 1], acc);
     }
     return acc;
 }
