@@ -166,39 +166,55 @@ def run_mixed(args):
     tune_s = time.perf_counter() - t0
     x = torch.from_numpy(llr).cuda()
     p = T.params(8, 1, 0, 1)
-    graphs, outs = [], []
+    st = torch.cuda.current_stream()
+    outs = []
     k = 0
     for i in range(n_tti):
         tl = tbs[i]
-        l_off = lo[k:k + len(tl)]
         b_off = np.concatenate([[0], np.cumsum([(t + 7) // 8 for t in tl])[:-1]]).astype(np.int64)
         bits = torch.zeros(int(b_off[-1] + (tl[-1] + 7) // 8), dtype=torch.uint8, device="cuda")
         res = torch.zeros(len(tl) * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
-        graphs.append(D.graph_tb_decode(tl, l_off, b_off, x, p, bits, res))
         outs.append((bits, res, b_off, k))
         k += len(tl)
-    st = torch.cuda.current_stream()
-    for gph in graphs:
-        gph.launch()
-    torch.cuda.synchronize()
-    # TTIs back to back
     reps = 4
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def graphs_run():
+        """Capture every TTI, replay them back to back (reps times), then
+        each alone between device events: (graphs, wall seconds, per-TTI ms)."""
+        graphs = []
+        for i, (bits, res, b_off, k0) in enumerate(outs):
+            graphs.append(D.graph_tb_decode(tbs[i], lo[k0:k0 + len(tbs[i])], b_off, x, p, bits, res))
         for gph in graphs:
             gph.launch()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    payload = sum(flat)
-    # per-TTI latency: each TTI alone, device events
-    lat = []
-    for gph in graphs:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        gph.launch()
-        e1.record(st)
         torch.cuda.synchronize()
-        lat.append(e0.elapsed_time(e1))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for gph in graphs:
+                gph.launch()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = []
+        for gph in graphs:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            gph.launch()
+            e1.record(st)
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        return graphs, wall, lat
+
+    payload = sum(flat)
+    # the built-in launch knobs (with the per-size windows above), then the
+    # knobs the batch tuner picks on the first TTI
+    graphs, wall_rule, lat_rule = graphs_run()
+    for gph in graphs:
+        gph.close()
+    t0 = time.perf_counter()
+    kt = D.autotune_batch(tbs[0], lo[:len(tbs[0])], x, p, min_W=min_w(args, 32))
+    tune_batch_s = time.perf_counter() - t0
+    log(f"[mixed] batch knobs: best {kt['best']} rule {kt['rule']} "
+        f"({len(kt['candidates'])} candidates, {tune_batch_s:.1f} s)")
+    graphs, wall, lat = graphs_run()
     # check outputs against the transmitted payloads and, every TB, against
     # the oracle run with the same window counts
     cpu = parity = None
@@ -286,9 +302,17 @@ def run_mixed(args):
                 "tb_results_equal": bool(same_tb)},
             "parity": parity, "cpu_baseline": cpu,
             "autotune_s": round(tune_s, 2),
-            "windows": {str(K): choice[K][0] for K in (40, 120, 504, 1024, 2048, 4096, 6144)
+            "launch_knobs": {
+                "tuned_on": f"TTI 0 ({len(tbs[0])} TBs), {len(kt['candidates'])} candidates, "
+                            f"{tune_batch_s:.1f} s",
+                "best": kt["best"], "rule": kt["rule"],
+                "gbit_s_rule": round(payload * reps / wall_rule / 1e9, 4),
+                "gbit_s_tuned": round(value, 4),
+                "latency_ms_p50_rule": round(pct(lat_rule, 0.5), 4),
+                "latency_ms_p99_rule": round(pct(lat_rule, 0.99), 4)},
+            "windows": {str(K): D.pick_windows(K) for K in (40, 120, 504, 1024, 2048, 4096, 6144)
                         if K in choice},
-            "max_window_steps": max(T.win_len(K, choice[K][0]) for K in choice)}
+            "max_window_steps": max(T.win_len(K, D.pick_windows(K)) for K in choice)}
     log(f"[mixed] {line}")
     return line
 

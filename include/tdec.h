@@ -286,8 +286,68 @@ void tdec_graph_destroy(tdec_graph *g);
 tdec_status tdec_autotune(tdec_ctx *ctx, int32_t n_k, const int32_t *Ks, int32_t min_W,
                           int32_t max_iters, int64_t batch_bits, int32_t *out_nw,
                           float *out_ns_per_kbit, void *stream);
-/* Forget every tuned choice (back to the built-in rule). */
+/* Forget every tuned choice (back to the built-in rule): window counts and
+ * the launch knobs below. */
 void tdec_autotune_reset(tdec_ctx *ctx);
+
+/* Launch knobs of a context: the planner choices that decide how one batch
+ * (the paper's code block parallelism inside a TTI, Sec. IV-B, with the
+ * FIFO queue of Algorithms 1 and 2 replaced by a persistent grid claiming
+ * work items) is spread over the compute units.
+ *   lds_budget  LDS bytes per work group the planner fills with code blocks
+ *               of one size (packing: more blocks per work item use more of
+ *               the work group's lanes but fewer work groups fit a compute
+ *               unit); 1..163840, default 30720;
+ *   order       order in which the grid claims the work items:
+ *               TDEC_ORDER_K_DESC (largest blocks first, the default),
+ *               TDEC_ORDER_K_ASC, or TDEC_ORDER_REQUEST (the request's own
+ *               order, as the paper's FIFO queue; equal neighbours still
+ *               share items);
+ *   win_target  window length target of every code block size: a size K
+ *               decodes in the most windows (<= 64) whose length is at least
+ *               win_target (one window if K is shorter); 0 = the built-in
+ *               rule; -1 = keep the per-size choices (tdec_autotune or the
+ *               rule).  Applies where tdec_params.n_windows is 0.
+ *   us          set by tdec_autotune_batch: that candidate's launch time in
+ *               microseconds (ignored by tdec_set_knobs). */
+enum { TDEC_ORDER_K_DESC = 0, TDEC_ORDER_K_ASC = 1, TDEC_ORDER_REQUEST = 2 };
+typedef struct {
+    int32_t lds_budget;
+    int32_t order;
+    int32_t win_target;
+    float us;
+} tdec_knobs;
+
+/* The built-in knobs: {30720, TDEC_ORDER_K_DESC, 0}. */
+void tdec_default_knobs(tdec_knobs *out);
+
+/* Set the knobs of a context (EINVAL when out of range: win_target must be
+ * -1, 0 or 8..6144).  Plans made afterwards follow them; the window counts
+ * win_target gives become what n_windows = 0 and tdec_pick_windows use. */
+tdec_status tdec_set_knobs(tdec_ctx *ctx, const tdec_knobs *k);
+
+/* The knobs in force (win_target reads -1: window counts are per size). */
+tdec_status tdec_get_knobs(const tdec_ctx *ctx, tdec_knobs *out);
+
+/* Choose the knobs by measurement on one representative batch of transport
+ * blocks (tbs, llr_off, d_llr as for tb_decode_batch, the LLRs real ones:
+ * the decode time depends on them where early stopping is on).  Every
+ * combination of lds_budget in {8192, 16384, 30720, 49152, 81920}, the three
+ * orders, and win_target in {-1, 0, and min_W times 1, 1.5, 2, 3, 4} (the
+ * window choices only where params->n_windows is 0; min_W >= 8) decodes the
+ * batch once untimed and three times timed on `stream`; the five fastest
+ * and the built-in knobs are timed again, ten launches each, and the
+ * fastest of those is set on the context as by tdec_set_knobs.  out (host,
+ * max_out entries, may be NULL) receives every candidate timed in the first
+ * pass with its time, *n_out (may be NULL) their count; *best and *rule
+ * (may be NULL) the chosen knobs and the built-in knobs with their
+ * second-pass times.  Synchronises `stream`; allocates and frees temporary
+ * device buffers for the bits and results. */
+tdec_status tdec_autotune_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                const int64_t *llr_off, const int16_t *d_llr,
+                                const tdec_params *params, int32_t min_W, tdec_knobs *out,
+                                int32_t max_out, int32_t *n_out, tdec_knobs *best,
+                                tdec_knobs *rule, void *stream);
 
 /* ---------------------------------------------------------------- rate matching */
 /* TS 36.212 5.1.4.1: the three coded streams of a block go through the

@@ -29,7 +29,9 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_graph_launch", "tdec_graph_destroy", "tdec_autotune", "tdec_autotune_reset",
            "tdec_server_submit_dev", "tdec_derate_batch", "tdec_rate_match_batch",
            "tdec_server_launches", "tdec_probe_valu_int16", "tdec_probe_hbm",
-           "tdec_probe_launch", "tdec_server_replay")
+           "tdec_probe_launch", "tdec_server_replay", "tdec_default_knobs", "tdec_set_knobs",
+           "tdec_get_knobs", "tdec_autotune_batch")
+ORDER_K_DESC, ORDER_K_ASC, ORDER_REQUEST = 0, 1, 2
 SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
@@ -45,6 +47,14 @@ class Params(ct.Structure):
     _fields_ = [("max_iters", ct.c_int32), ("early_stop", ct.c_int32),
                 ("n_windows", ct.c_int32), ("win_init", ct.c_int32),
                 ("mi_eps", ct.c_int32)]
+
+
+class Knobs(ct.Structure):
+    _fields_ = [("lds_budget", ct.c_int32), ("order", ct.c_int32), ("win_target", ct.c_int32),
+                ("us", ct.c_float)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class Seg(ct.Structure):
@@ -158,6 +168,12 @@ def lib():
         L.tdec_autotune.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.tdec_autotune_reset.argtypes = [vp]
         L.tdec_autotune_reset.restype = None
+        L.tdec_default_knobs.argtypes = [P(Knobs)]
+        L.tdec_default_knobs.restype = None
+        L.tdec_set_knobs.argtypes = [vp, P(Knobs)]
+        L.tdec_get_knobs.argtypes = [vp, P(Knobs)]
+        L.tdec_autotune_batch.argtypes = [vp, i32, vp, vp, vp, P(Params), i32, vp, i32, vp,
+                                          P(Knobs), P(Knobs), vp]
         L.tdec_derate_batch.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp]
         L.tdec_rate_match_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         L.tdec_now_ns.restype = i64
@@ -458,6 +474,34 @@ class Decoder:
 
     def autotune_reset(self):
         lib().tdec_autotune_reset(self._h)
+
+    def set_knobs(self, lds_budget=30720, order=ORDER_K_DESC, win_target=0):
+        k = Knobs(int(lds_budget), int(order), int(win_target), 0.0)
+        _check("tdec_set_knobs", lib().tdec_set_knobs(self._h, ct.byref(k)))
+
+    def get_knobs(self):
+        k = Knobs()
+        _check("tdec_get_knobs", lib().tdec_get_knobs(self._h, ct.byref(k)))
+        return k.as_dict()
+
+    def autotune_batch(self, tbs, llr_off, llr, p: Params, min_W=32, stream=None):
+        """Measure the launch knobs on one batch of transport blocks and set
+        the fastest; returns {"best", "rule", "candidates"} (knob dicts with
+        their launch time "us")."""
+        tbs = np.ascontiguousarray(tbs, np.int32)
+        llr_off = np.ascontiguousarray(llr_off, np.int64)
+        counts = np.array([tb_llr_count(int(t)) for t in tbs], np.int64)
+        _need(llr, "int16", int((llr_off + counts).max()), "llr")
+        cands = (Knobs * 256)()
+        n = ct.c_int32()
+        best, rule = Knobs(), Knobs()
+        _check("tdec_autotune_batch",
+               lib().tdec_autotune_batch(self._h, tbs.size, _np_ptr(tbs), _np_ptr(llr_off),
+                                         _dptr(llr), ct.byref(p), int(min_W), cands, 256,
+                                         ct.byref(n), ct.byref(best), ct.byref(rule),
+                                         _stream(stream)))
+        return {"best": best.as_dict(), "rule": rule.as_dict(),
+                "candidates": [cands[i].as_dict() for i in range(n.value)]}
 
     def derate_batch(self, descs, e, soft, combine: int, stream=None):
         """e: int8 or int16 CUDA tensor of soft values; soft: int16 CUDA

@@ -29,6 +29,7 @@ constexpr size_t kPlanSlotBytes = 8u << 20;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr size_t kQtabEntries = 4u << 20;  // QPP table arena (8 MiB): every size at ~11 window counts
 constexpr size_t kRmEntries = 8u << 20;    // rate matching table arena (16 MiB, >= 450 tables)
+constexpr int kDefaultLdsBudget = 30 * 1024;
 
 struct PlanSlot {
     std::string key;
@@ -87,7 +88,8 @@ struct tdec_ctx {
     uint16_t *h_rmtab = nullptr;
     size_t rm_cap = 0, rm_used = 0;
     std::map<int64_t, RmTab> rm_tabs;
-    int lds_budget = 30 * 1024;  // LDS bytes per work group the planner aims for
+    int lds_budget = kDefaultLdsBudget;  // LDS bytes per work group the planner aims for
+    int item_order = TDEC_ORDER_K_DESC;  // order of the work items (TDEC_ORDER_*)
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
     int launch_reserve = 0;      // resident slots a launch leaves free (launch lanes)
     bool small_asm = false;      // transport block assembly in kAsmGrid small work groups
@@ -207,11 +209,16 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
                               std::vector<char> &blob, const std::vector<TbItem> *tbs,
                               hipStream_t st, bool exact, bool mi, size_t scratch_cap)
 {
-    // group by (K, nw), biggest blocks first, request order within a group:
-    // a counting sort over the size table (a size has one window count per
-    // plan; mixed counts for one size fall back to a comparison sort)
+    // group by (K, nw), biggest blocks first (or smallest first), request
+    // order within a group: a counting sort over the size table (a size has
+    // one window count per plan; mixed counts for one size fall back to a
+    // comparison sort); or keep the request's order
     std::vector<int> order(reqs.size());
-    {
+    const bool asc = ctx->item_order == TDEC_ORDER_K_ASC;
+    if (ctx->item_order == TDEC_ORDER_REQUEST) {
+        // the request's own order: runs of equal (K, nw) become items
+        for (size_t i = 0; i < reqs.size(); ++i) order[i] = (int)i;
+    } else {
         int cnt[kNumK + 1] = {}, nw_of[kNumK];
         bool mixed = false;
         for (const CbReq &r : reqs) {
@@ -221,7 +228,8 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         }
         if (!mixed) {
             int pos[kNumK], at = 0;
-            for (int ki = kNumK - 1; ki >= 0; --ki) {
+            for (int j = 0; j < kNumK; ++j) {
+                const int ki = asc ? j : kNumK - 1 - j;
                 pos[ki] = at;
                 at += cnt[ki + 1];
             }
@@ -229,7 +237,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         } else {
             for (size_t i = 0; i < reqs.size(); ++i) order[i] = (int)i;
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                if (reqs[a].K != reqs[b].K) return reqs[a].K > reqs[b].K;
+                if (reqs[a].K != reqs[b].K) return asc ? reqs[a].K < reqs[b].K : reqs[a].K > reqs[b].K;
                 return reqs[a].nw < reqs[b].nw;
             });
         }
@@ -776,6 +784,7 @@ tdec_status tdec::ctx_clone(const tdec_ctx *src, tdec_ctx **out)
     if (s != TDEC_OK) return s;
     tdec_ctx *c = *out;
     c->lds_budget = src->lds_budget;
+    c->item_order = src->item_order;
     c->grid_cap = src->grid_cap;
     for (int i = 0; i < kNumK; ++i) c->tuned_nw[i] = src->tuned_nw[i];
     ++c->tune_gen;
@@ -1087,7 +1096,186 @@ void tdec_autotune_reset(tdec_ctx *ctx)
 {
     if (!ctx) return;
     for (auto &v : ctx->tuned_nw) v = 0;
+    ctx->lds_budget = kDefaultLdsBudget;
+    ctx->item_order = TDEC_ORDER_K_DESC;
     ++ctx->tune_gen;
+}
+
+void tdec_default_knobs(tdec_knobs *out)
+{
+    if (!out) return;
+    out->lds_budget = kDefaultLdsBudget;
+    out->order = TDEC_ORDER_K_DESC;
+    out->win_target = 0;
+    out->us = 0.f;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool knobs_ok(const tdec_knobs *k)
+{
+    return k && k->lds_budget >= 1 && k->lds_budget <= kLdsPerCu && k->order >= TDEC_ORDER_K_DESC &&
+           k->order <= TDEC_ORDER_REQUEST &&
+           (k->win_target == -1 || k->win_target == 0 || (k->win_target >= 8 && k->win_target <= 6144));
+}
+
+// The most windows (at most 128, valid partitions only) whose length is at
+// least `target` steps; one window for a block shorter than that.
+int32_t windows_for_target(int32_t K, int32_t target)
+{
+    for (int32_t nw = std::min(128, K / 8); nw > 1; --nw)
+        if (windows_ok(K, nw) && win_len(K, nw) >= target) return nw;
+    return 1;
+}
+
+// Apply knobs; `keep` holds the per-size window counts win_target = -1 keeps.
+void apply_knobs(tdec_ctx *ctx, const tdec_knobs &k, const int32_t *keep)
+{
+    ctx->lds_budget = k.lds_budget;
+    ctx->item_order = k.order;
+    if (k.win_target == 0) {
+        for (auto &v : ctx->tuned_nw) v = 0;
+    } else if (k.win_target > 0) {
+        for (int i = 0; i < kNumK; ++i) ctx->tuned_nw[i] = windows_for_target(k_of_index(i), k.win_target);
+    } else if (keep) {
+        for (int i = 0; i < kNumK; ++i) ctx->tuned_nw[i] = keep[i];
+    }
+    ++ctx->tune_gen;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdec_status tdec_set_knobs(tdec_ctx *ctx, const tdec_knobs *k)
+{
+    if (!ctx || !knobs_ok(k)) return TDEC_EINVAL;
+    apply_knobs(ctx, *k, nullptr);
+    return TDEC_OK;
+}
+
+tdec_status tdec_get_knobs(const tdec_ctx *ctx, tdec_knobs *out)
+{
+    if (!ctx || !out) return TDEC_EINVAL;
+    out->lds_budget = ctx->lds_budget;
+    out->order = ctx->item_order;
+    out->win_target = -1;
+    out->us = 0.f;
+    return TDEC_OK;
+}
+
+tdec_status tdec_autotune_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
+                                const int64_t *llr_off, const int16_t *d_llr,
+                                const tdec_params *params, int32_t min_W, tdec_knobs *out,
+                                int32_t max_out, int32_t *n_out, tdec_knobs *best,
+                                tdec_knobs *rule, void *stream)
+{
+    if (n_out) *n_out = 0;
+    if (!ctx || n_tb <= 0 || !tbs || !llr_off || !d_llr || !params_ok(params) || min_W < 8 ||
+        min_W > 6144 || max_out < 0 || (max_out > 0 && !out))
+        return TDEC_EINVAL;
+    for (int32_t i = 0; i < n_tb; ++i)
+        if (tbs[i] < 1) return TDEC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    // what the context holds now: restored on failure, and the per-size
+    // window counts that win_target = -1 keeps
+    int32_t keep[kNumK];
+    bool tuned = false;
+    for (int i = 0; i < kNumK; ++i) {
+        keep[i] = ctx->tuned_nw[i];
+        tuned = tuned || keep[i] > 0;
+    }
+    const tdec_knobs saved = {ctx->lds_budget, ctx->item_order, -1, 0.f};
+    std::vector<int64_t> bits_off((size_t)n_tb);
+    int64_t nbytes = 0;
+    for (int32_t i = 0; i < n_tb; ++i) {
+        bits_off[i] = nbytes;
+        nbytes += (tbs[i] + 7) / 8;
+    }
+    uint8_t *d_bits = nullptr;
+    tdec_tb_result *d_res = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tdec_status rs = TDEC_OK;
+    if (hipMalloc(&d_bits, (size_t)nbytes) != hipSuccess ||
+        hipMalloc(&d_res, (size_t)n_tb * sizeof(tdec_tb_result)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rs = TDEC_ENOMEM;
+    // one untimed launch (plan build and upload), then `reps` between a pair
+    // of events; <0: the knobs do not fit the workspace
+    auto time_knobs = [&](const tdec_knobs &k, int reps, float *us) -> tdec_status {
+        apply_knobs(ctx, k, keep);
+        tdec_status s = tb_decode_batch(ctx, n_tb, tbs, llr_off, bits_off.data(), d_llr, params,
+                                        d_bits, d_res, st);
+        if (s == TDEC_ENOMEM) {
+            *us = -1.f;
+            return TDEC_OK;
+        }
+        if (s != TDEC_OK) return s;
+        if (hipStreamSynchronize(st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess)
+            return TDEC_EDEVICE;
+        for (int r = 0; r < reps; ++r) {
+            s = tb_decode_batch(ctx, n_tb, tbs, llr_off, bits_off.data(), d_llr, params, d_bits,
+                                d_res, st);
+            if (s != TDEC_OK) return s;
+        }
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return TDEC_EDEVICE;
+        *us = ms * 1000.f / (float)reps;
+        return TDEC_OK;
+    };
+    std::vector<tdec_knobs> cand;
+    {
+        std::vector<int32_t> wins;
+        if (tuned) wins.push_back(-1);
+        wins.push_back(0);
+        if (params->n_windows == 0)
+            for (int f2 : {2, 3, 4, 6, 8}) wins.push_back(min_W * f2 / 2);
+        for (int32_t w : wins)
+            for (int32_t lb : {8192, 16384, kDefaultLdsBudget, 49152, 81920})
+                for (int32_t o : {TDEC_ORDER_K_DESC, TDEC_ORDER_K_ASC, TDEC_ORDER_REQUEST})
+                    cand.push_back({lb, o, std::min<int32_t>(w, 6144), 0.f});
+    }
+    for (size_t c = 0; c < cand.size() && rs == TDEC_OK; ++c) rs = time_knobs(cand[c], 3, &cand[c].us);
+    tdec_knobs def;
+    tdec_default_knobs(&def);
+    tdec_knobs pick = def;
+    if (rs == TDEC_OK) {
+        if (out)
+            for (size_t c = 0; c < cand.size() && (int32_t)c < max_out; ++c) out[c] = cand[c];
+        if (n_out) *n_out = (int32_t)std::min<size_t>(cand.size(), (size_t)max_out);
+        // second pass: the five fastest and the built-in knobs, ten launches each
+        std::vector<tdec_knobs> top;
+        for (const tdec_knobs &k : cand)
+            if (k.us > 0.f) top.push_back(k);
+        std::stable_sort(top.begin(), top.end(),
+                         [](const tdec_knobs &a, const tdec_knobs &b) { return a.us < b.us; });
+        if (top.size() > 5) top.resize(5);
+        rs = time_knobs(def, 10, &def.us);
+        pick = def;
+        for (size_t c = 0; c < top.size() && rs == TDEC_OK; ++c) {
+            rs = time_knobs(top[c], 10, &top[c].us);
+            if (rs == TDEC_OK && top[c].us > 0.f && (pick.us <= 0.f || top[c].us < pick.us))
+                pick = top[c];
+        }
+    }
+    if (rs == TDEC_OK) {
+        apply_knobs(ctx, pick, keep);
+        if (best) *best = pick;
+        if (rule) *rule = def;
+    } else {
+        apply_knobs(ctx, saved, keep);
+    }
+    (void)hipStreamSynchronize(st);
+    if (d_bits) (void)hipFree(d_bits);
+    if (d_res) (void)hipFree(d_res);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rs;
 }
 
 

@@ -7,7 +7,10 @@
 * the mixed-TTI shape: one TTI of 64 transport blocks of log-uniform sizes,
   window counts autotuned with windows down to 32 steps (uneven partitions
   included), captured into a graph and replayed, every replay checked
-  against the oracle run with the same per-block window counts."""
+  against the oracle run with the same per-block window counts;
+* the same TTI under the launch knobs (packing, item order, window length
+  target): the batch tuner's choice and a fixed non-default set, each
+  checked against the oracle with the window counts it gives."""
 import sys
 import time
 
@@ -90,12 +93,31 @@ def test_stress_shape_direct_and_served(dev):
         assert np.array_equal(out[i], ob), i
 
 
-def test_mixed_tti_tuned_windows_graph_replays(dev):
-    T, _, torch = dev
+def c3_shape():
     g = wl.rng(3, 77)
     tbs_list = [int(v) for v in wl.tbs_log_uniform(g, 64)]
     mods = [["qpsk", "16qam", "64qam"][i] for i in g.integers(0, 3, len(tbs_list))]
     esn0 = g.uniform(0.0, 18.0, len(tbs_list))
+    return tbs_list, mods, esn0
+
+
+def c3_tti(tbs_list, mods, esn0):
+    """The TTI's LLRs, laid out as tb_batch lays them out."""
+    parts, lo, bo, o, b = [], [], [], 0, 0
+    gch = wl.rng(3, 78)
+    for t, m, e in zip(tbs_list, mods, esn0):
+        d, _ = O.tb_encode(wl.random_bits(gch, t))
+        parts.append(wl.channel_blocks(d, O.cb_sizes(t), m, float(e), gch))
+        lo.append(o)
+        bo.append(b)
+        o += parts[-1].size
+        b += (t + 7) // 8
+    return np.concatenate(parts), np.array(lo), np.array(bo), b
+
+
+def test_mixed_tti_tuned_windows_graph_replays(dev):
+    T, _, torch = dev
+    tbs_list, mods, esn0 = c3_shape()
     Ks = sorted({K for t in tbs_list for K, _ in O.cb_sizes(t)})
     D2 = T.Decoder(0)
     try:
@@ -110,18 +132,7 @@ def test_mixed_tti_tuned_windows_graph_replays(dev):
         nws = [[choice[K][0] for K, _ in O.cb_sizes(t)] for t in tbs_list]
         p = T.params(8, 1, 0, 1)
         op = O.params(8, 1, 0, 1)
-        # the TTI's LLRs, laid out as tb_batch lays them out
-        parts, lo, bo, o, b = [], [], [], 0, 0
-        gch = wl.rng(3, 78)
-        for t, m, e in zip(tbs_list, mods, esn0):
-            d, _ = O.tb_encode(wl.random_bits(gch, t))
-            parts.append(wl.channel_blocks(d, O.cb_sizes(t), m, float(e), gch))
-            lo.append(o)
-            bo.append(b)
-            o += parts[-1].size
-            b += (t + 7) // 8
-        llr = np.concatenate(parts)
-        lo, bo = np.array(lo), np.array(bo)
+        llr, lo, bo, b = c3_tti(tbs_list, mods, esn0)
         x = torch.from_numpy(llr).cuda()
         gb = torch.zeros(b, dtype=torch.uint8, device="cuda")
         gr = torch.zeros(len(tbs_list) * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
@@ -145,5 +156,49 @@ def test_mixed_tti_tuned_windows_graph_replays(dev):
                 _ = (x[:1024].float() * 2).sum().item()
         finally:
             graph.close()
+    finally:
+        D2.close()
+
+
+def test_mixed_tti_launch_knobs(dev):
+    T, _, torch = dev
+    tbs_list, mods, esn0 = c3_shape()
+    llr, lo, bo, b = c3_tti(tbs_list, mods, esn0)
+    x = torch.from_numpy(llr).cuda()
+    p = T.params(8, 1, 0, 1)
+    op = O.params(8, 1, 0, 1)
+    sizes = [[K for K, _ in O.cb_sizes(t)] for t in tbs_list]
+    D2 = T.Decoder(0)
+    try:
+        say("[c3 knobs] batch tuner, windows >= 32 steps")
+        r = D2.autotune_batch(tbs_list, lo, x, p, min_W=32)
+        best, rule = r["best"], r["rule"]
+        say(f"[c3 knobs] {len(r['candidates'])} candidates; best {best}; rule {rule}")
+        assert len(r["candidates"]) == 5 * 3 * 6  # no per-size tuning: no -1 window choice
+        assert rule["lds_budget"] == 30720 and rule["order"] == T.ORDER_K_DESC
+        assert 0 < best["us"] <= rule["us"]
+        k = D2.get_knobs()
+        assert (k["lds_budget"], k["order"]) == (best["lds_budget"], best["order"])
+        knob_sets = [("tuned", None), ("fixed", (8192, T.ORDER_REQUEST, 48)),
+                     ("fixed", (81920, T.ORDER_K_ASC, 0))]
+        for name, ks in knob_sets:
+            if ks is not None:
+                D2.set_knobs(*ks)
+            nws = [[D2.pick_windows(K) for K in s] for s in sizes]
+            for s, n in zip(sizes, nws):
+                for K, nw in zip(s, n):
+                    assert nw == 1 or O.win_len(K, nw) >= 32, (K, nw)
+            say(f"[c3 knobs] {name} {ks}: decode and oracle")
+            gb = torch.full((b,), 0xA5, dtype=torch.uint8, device="cuda")
+            gr = torch.zeros(len(tbs_list) * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+            D2.tb_decode_batch(tbs_list, lo, bo, x, p, gb, gr)
+            torch.cuda.synchronize()
+            hb = gb.cpu().numpy()
+            hr = T.parse_tb_results(gr.cpu().numpy())
+            ref = oracle_tbs(llr, lo, tbs_list, op, nws)
+            for i, t in enumerate(tbs_list):
+                ob, ores = ref[i]
+                assert hr[i] == ores, (name, ks, i, t)
+                assert np.array_equal(hb[bo[i]:bo[i] + ob.size], ob), (name, ks, i, t)
     finally:
         D2.close()
