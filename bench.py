@@ -11,9 +11,12 @@ The LLRs are resident in device memory before the timed region starts.
 
 Also reported (stderr + extra JSON fields): the same batch as configured
 (at most 8 iterations with CRC24B early stop), the kernel's VALU roofline
-fraction, and the CPU oracle's throughput on a bounded sample.
+fraction, the CPU oracle's throughput on a bounded sample, and two short
+re-checks of the other workloads' headline figures (--no-checks skips them):
+the serving loop at rho = 1 and the cells count at its calibrated Es/N0,
+1000 TTIs each, every served TB checked against the oracle.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-checks]
        python bench.py --workload {tb,mixed,serving,cells} [options]
 
 The default workload is the uniform batch above; the others measure the
@@ -29,8 +32,9 @@ remaining configurations and print one JSON line each:
             TTI (64QAM, Es/N0 uniform in [12, 22] dB, 3 ms deadline, 8 GB
             slot budget): p50/p99 latency, misses, rejections, Gbit/s;
   cells   : cells of 2 layers x one 75376-bit TB per TTI at 256QAM near 30 %
-            TB error rate, 8 iterations forced: the most cells whose p99
-            latency stays within 3 ms (binary search).
+            TB error rate (Es/N0 calibrated on 2048 TBs per point), 8
+            iterations forced: the most cells whose p99 latency stays within
+            3 ms (binary search).
 """
 from __future__ import annotations
 
@@ -212,6 +216,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="uniform workload: skip the short serving (rho = 1) and cells re-checks")
     ap.add_argument("--cpu-sample", type=int, default=N_CB)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -342,6 +348,15 @@ def main():
                   "first_mismatches": bad[:8]}
         log(f"[bench] parity against the oracle: {parity}")
 
+    checks = None
+    if not args.no_checks:
+        import bench_workloads as BW
+        args.oracle_ref = None if args.no_cpu_baseline else oracle_tb_reference
+        args.oracle_threads = oracle_threads()
+        log("[bench] re-checks: serving at rho = 1 and the cells count, 1000 TTIs each")
+        checks = BW.default_checks(args)
+        log(f"[bench] re-checks: {checks}")
+
     line = {
         "metric": "decoded info Gbit/s @6 iters",
         "value": round(value, 4),
@@ -370,6 +385,7 @@ def main():
         "parity": parity,
         "as_configured": as_cfg,
         "kernel_ms": round(launch_s * 1e3, 4),
+        "checks": checks,
     }
     print(json.dumps(line), flush=True)
     if parity and parity["mismatches"]:

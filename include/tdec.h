@@ -308,6 +308,9 @@ void tdec_autotune_reset(tdec_ctx *ctx);
  *               win_target (one window if K is shorter); 0 = the built-in
  *               rule; -1 = keep the per-size choices (tdec_autotune or the
  *               rule).  Applies where tdec_params.n_windows is 0.
+ *   grid_cap    most work groups of a decode launch, 0 = as many as the
+ *               device holds at once (the default; the batch tuner keeps
+ *               it); the work groups claim the work items in turn.
  *   us          set by tdec_autotune_batch: that candidate's launch time in
  *               microseconds (ignored by tdec_set_knobs). */
 enum { TDEC_ORDER_K_DESC = 0, TDEC_ORDER_K_ASC = 1, TDEC_ORDER_REQUEST = 2 };
@@ -315,14 +318,15 @@ typedef struct {
     int32_t lds_budget;
     int32_t order;
     int32_t win_target;
+    int32_t grid_cap;
     float us;
 } tdec_knobs;
 
-/* The built-in knobs: {30720, TDEC_ORDER_K_DESC, 0}. */
+/* The built-in knobs: {30720, TDEC_ORDER_K_DESC, 0, 0}. */
 void tdec_default_knobs(tdec_knobs *out);
 
 /* Set the knobs of a context (EINVAL when out of range: win_target must be
- * -1, 0 or 8..6144).  Plans made afterwards follow them; the window counts
+ * -1, 0 or 8..6144, grid_cap >= 0).  Plans made afterwards follow them; the window counts
  * win_target gives become what n_windows = 0 and tdec_pick_windows use. */
 tdec_status tdec_set_knobs(tdec_ctx *ctx, const tdec_knobs *k);
 

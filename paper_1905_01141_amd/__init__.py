@@ -51,7 +51,7 @@ class Params(ct.Structure):
 
 class Knobs(ct.Structure):
     _fields_ = [("lds_budget", ct.c_int32), ("order", ct.c_int32), ("win_target", ct.c_int32),
-                ("us", ct.c_float)]
+                ("grid_cap", ct.c_int32), ("us", ct.c_float)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -475,8 +475,8 @@ class Decoder:
     def autotune_reset(self):
         lib().tdec_autotune_reset(self._h)
 
-    def set_knobs(self, lds_budget=30720, order=ORDER_K_DESC, win_target=0):
-        k = Knobs(int(lds_budget), int(order), int(win_target), 0.0)
+    def set_knobs(self, lds_budget=30720, order=ORDER_K_DESC, win_target=0, grid_cap=0):
+        k = Knobs(int(lds_budget), int(order), int(win_target), int(grid_cap), 0.0)
         _check("tdec_set_knobs", lib().tdec_set_knobs(self._h, ct.byref(k)))
 
     def get_knobs(self):

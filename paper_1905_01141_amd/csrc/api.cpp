@@ -268,7 +268,6 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
             const int sb = lds_slot_bytes(gK);
             cap = std::min(half / gnw, kMaxSlotsPerWg);
             cap = std::min(cap, std::max(1, ctx->lds_budget / sb));
-            cap = std::min(cap, 65536 / sb);  // decoder 2 keeps 16-bit LDS addresses
             proto.K = gK;
             proto.nw = gnw;
             proto.W = win_len(gK, gnw);
@@ -298,7 +297,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         const int lanes = n * nw;
         // restaged inputs, checkpoints, boundaries, and with exact boundaries
         // the transfer runs (2 directions x 8 states x 32 bytes per lane)
-        const int64_t need = (int64_t)lanes * W * 8 + (int64_t)(W / kSeg) * lanes * 16 +
+        const int64_t need = (int64_t)lanes * W * 6 + (int64_t)(W / kSeg) * lanes * 16 +
                              (int64_t)4 * lanes * 16 + (exact ? (int64_t)lanes * 512 : 0) + 256;
         stride = std::max(stride, (need + 255) & ~(int64_t)255);
     }
@@ -1098,6 +1097,7 @@ void tdec_autotune_reset(tdec_ctx *ctx)
     for (auto &v : ctx->tuned_nw) v = 0;
     ctx->lds_budget = kDefaultLdsBudget;
     ctx->item_order = TDEC_ORDER_K_DESC;
+    ctx->grid_cap = 0;
     ++ctx->tune_gen;
 }
 
@@ -1107,6 +1107,7 @@ void tdec_default_knobs(tdec_knobs *out)
     out->lds_budget = kDefaultLdsBudget;
     out->order = TDEC_ORDER_K_DESC;
     out->win_target = 0;
+    out->grid_cap = 0;
     out->us = 0.f;
 }
 
@@ -1118,7 +1119,8 @@ bool knobs_ok(const tdec_knobs *k)
 {
     return k && k->lds_budget >= 1 && k->lds_budget <= kLdsPerCu && k->order >= TDEC_ORDER_K_DESC &&
            k->order <= TDEC_ORDER_REQUEST &&
-           (k->win_target == -1 || k->win_target == 0 || (k->win_target >= 8 && k->win_target <= 6144));
+           (k->win_target == -1 || k->win_target == 0 || (k->win_target >= 8 && k->win_target <= 6144)) &&
+           k->grid_cap >= 0;
 }
 
 // The most windows (at most 128, valid partitions only) whose length is at
@@ -1135,6 +1137,7 @@ void apply_knobs(tdec_ctx *ctx, const tdec_knobs &k, const int32_t *keep)
 {
     ctx->lds_budget = k.lds_budget;
     ctx->item_order = k.order;
+    ctx->grid_cap = k.grid_cap;
     if (k.win_target == 0) {
         for (auto &v : ctx->tuned_nw) v = 0;
     } else if (k.win_target > 0) {
@@ -1162,6 +1165,7 @@ tdec_status tdec_get_knobs(const tdec_ctx *ctx, tdec_knobs *out)
     out->lds_budget = ctx->lds_budget;
     out->order = ctx->item_order;
     out->win_target = -1;
+    out->grid_cap = ctx->grid_cap;
     out->us = 0.f;
     return TDEC_OK;
 }
@@ -1188,7 +1192,7 @@ tdec_status tdec_autotune_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
         keep[i] = ctx->tuned_nw[i];
         tuned = tuned || keep[i] > 0;
     }
-    const tdec_knobs saved = {ctx->lds_budget, ctx->item_order, -1, 0.f};
+    const tdec_knobs saved = {ctx->lds_budget, ctx->item_order, -1, ctx->grid_cap, 0.f};
     std::vector<int64_t> bits_off((size_t)n_tb);
     int64_t nbytes = 0;
     for (int32_t i = 0; i < n_tb; ++i) {
@@ -1238,7 +1242,7 @@ tdec_status tdec_autotune_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
         for (int32_t w : wins)
             for (int32_t lb : {8192, 16384, kDefaultLdsBudget, 49152, 81920})
                 for (int32_t o : {TDEC_ORDER_K_DESC, TDEC_ORDER_K_ASC, TDEC_ORDER_REQUEST})
-                    cand.push_back({lb, o, std::min<int32_t>(w, 6144), 0.f});
+                    cand.push_back({lb, o, std::min<int32_t>(w, 6144), 0, 0.f});
     }
     for (size_t c = 0; c < cand.size() && rs == TDEC_OK; ++c) rs = time_knobs(cand[c], 3, &cand[c].us);
     tdec_knobs def;

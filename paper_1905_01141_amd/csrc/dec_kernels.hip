@@ -219,28 +219,52 @@ __device__ __forceinline__ bool bwd_norm(int i0, int t, int W)
 // Everything a lane needs for one constituent pass over its window.
 struct Win {
     int W, M, lo, wi, lanes;
+    int qs;              // units per row of the QPP address table (the item's window count)
     bool first, last;
-    short *E;            // LDS extrinsic array of the block (padded); for decoder 2
-                         // the LDS base, since its addresses include the slot offset
-    const uint4 *R;      // restaged input: [t/4][window] x 4 steps, one int32 per step
+    short *E;            // LDS extrinsic array of the block (padded)
+    const uint4 *R;      // restaged input of the decoder: decoder 1 [t/4][lane] x 4
+                         // steps of Lp1 | Ls << 16; decoder 2 [t/4][lane] x 4 int16 Lp2
+    const uint2 *qt;     // QPP address table of the shape at this lane's window:
+                         // unit t/4 at qt[(t/4) * qs], 4 LDS byte offsets in E
     uint4 *ck;           // checkpoints [segment][window]
     const unsigned short *mit;  // LDS entropy table (mutual-information stop only)
 };
 
-// The restaged inputs of 8 steps starting at local step i0.
+// The inputs of 8 steps starting at local step i0:
+//   decoder 1: r[t] = Lp1 | Ls << 16 of step t;
+//   decoder 2: r[0..3] = Lp2 of steps (0,1), (2,3), (4,5), (6,7) and r[4..7]
+//              the LDS byte offsets of E[pi(k)] of the same step pairs.
+template <int DEC>
 __device__ __forceinline__ void load_seg(const Win &c, int i0, uint32_t r[S])
 {
-    const uint4 q0 = c.R[(size_t)(i0 >> 2) * c.lanes + c.wi];
-    const uint4 q1 = c.R[(size_t)((i0 >> 2) + 1) * c.lanes + c.wi];
-    r[0] = q0.x; r[1] = q0.y; r[2] = q0.z; r[3] = q0.w;
-    r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w;
+    if (DEC == 1) {
+        const uint4 q0 = c.R[(size_t)(i0 >> 2) * c.lanes + c.wi];
+        const uint4 q1 = c.R[(size_t)((i0 >> 2) + 1) * c.lanes + c.wi];
+        r[0] = q0.x; r[1] = q0.y; r[2] = q0.z; r[3] = q0.w;
+        r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w;
+    } else {
+        const uint2 *R2 = (const uint2 *)c.R;
+        const uint2 p0 = R2[(size_t)(i0 >> 2) * c.lanes + c.wi];
+        const uint2 p1 = R2[(size_t)((i0 >> 2) + 1) * c.lanes + c.wi];
+        const uint2 a0 = c.qt[(i0 >> 2) * c.qs];
+        const uint2 a1 = c.qt[((i0 >> 2) + 1) * c.qs];
+        r[0] = p0.x; r[1] = p0.y; r[2] = p1.x; r[3] = p1.y;
+        r[4] = a0.x; r[5] = a0.y; r[6] = a1.x; r[7] = a1.y;
+    }
+}
+
+// LDS byte offset of step t's E[pi(k)] in a decoder-2 segment r.
+__device__ __forceinline__ uint32_t qaddr(const uint32_t r[S], int t)
+{
+    const uint32_t w = r[4 + (t >> 1)];
+    return (t & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
 // Branch metric pairs g01 = (Lp, Lsa) of 8 steps.
 //   decoder 1: r = Lp1 | Ls << 16 and Lsa = Ls + E[j] (natural order, one
 //              ds_read_b128 for the 8 steps);
-//   decoder 2: r = Lp2 | addr << 16 with addr the LDS byte offset of
-//              E[pi(k)], which holds Ls + La for decoder 2.
+//   decoder 2: Lp2 from r[t/2] and Lsa = E[pi(k)] (decoder 1 stored Ls + La
+//              there) at the step's LDS offset.
 template <int DEC>
 __device__ __forceinline__ void gammas(const Win &c, int i0, const uint32_t r[S], s2 g01[S])
 {
@@ -259,17 +283,17 @@ __device__ __forceinline__ void gammas(const Win &c, int i0, const uint32_t r[S]
     } else {
 #pragma unroll
         for (int t = 0; t < S; ++t) {
-            const uint32_t e = *(const uint16_t *)((const char *)c.E + (r[t] >> 16));
-            g01[t] = as_s2(__builtin_amdgcn_perm(e, r[t], 0x05040100u));
+            const uint32_t e = *(const uint16_t *)((const char *)c.E + qaddr(r, t));
+            g01[t] = as_s2(__builtin_amdgcn_perm(e, r[t >> 1], (t & 1) ? 0x05040302u : 0x05040100u));
         }
     }
 }
 
 typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 
-// Output of two steps ta, ta + 1 from their extrinsic maxima pairs (M0, M1)
-// ma, mb, restaged words ra, rb and branch metric pairs ga, gb, both steps
-// packed in one register pair by pair:
+// Output of two steps ta, ta + 1 (ta even) from their extrinsic maxima pairs
+// (M0, M1) ma, mb, the segment's inputs r and branch metric pairs ga, gb, both
+// steps packed in one register pair by pair:
 //   Le = M1 - M0 - Lsa, modulo 2^16 (the true values fit int16);
 //   q = 0.75 Le truncated toward zero and clamped to +-2047, formed as
 //       (3 (x + [x < 0])) >> 2 with x = Le clamped to +-2730 (for x < 0 the
@@ -283,7 +307,7 @@ typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 //   also adds the entropy of its hard decisions, h(|L|) from the LDS table,
 //   to the lane's sum.
 template <int DEC, bool MI = false>
-__device__ __forceinline__ void emit2(const Win &c, int i0, int ta, uint32_t ra, uint32_t rb,
+__device__ __forceinline__ void emit2(const Win &c, int i0, int ta, const uint32_t r[S],
                                       s2 ga, s2 gb, s2 ma, s2 mb, int &acc)
 {
     const s2 m1 = as_s2(__builtin_amdgcn_perm(as_u(mb), as_u(ma), 0x07060302u));   // (ma.y, mb.y)
@@ -294,14 +318,14 @@ __device__ __forceinline__ void emit2(const Win &c, int i0, int ta, uint32_t ra,
     const s2 neg = __builtin_bit_cast(s2, __builtin_bit_cast(u2, x) >> (u2){15, 15});
     const s2 q = ((x + neg) * (s2){3, 3}) >> (s2){2, 2};
     if (DEC == 1) {
-        const s2 ls = as_s2(__builtin_amdgcn_perm(rb, ra, 0x07060302u));  // (Ls_a, Ls_b)
+        const s2 ls = as_s2(__builtin_amdgcn_perm(r[ta + 1], r[ta], 0x07060302u));  // (Ls_a, Ls_b)
         *(s2 *)(c.E + epad(c.lo + i0) + ta) = ls + q;
     } else {
         const s2 lapp = lsa + le;
         const s2 bit = __builtin_bit_cast(s2, __builtin_bit_cast(u2, (s2){0, 0} - lapp) >> (u2){15, 15});
         const s2 o = q * (s2){2, 2} + bit;
-        *(short *)((char *)c.E + (ra >> 16)) = o.x;
-        *(short *)((char *)c.E + (rb >> 16)) = o.y;
+        *(short *)((char *)c.E + qaddr(r, ta)) = o.x;
+        *(short *)((char *)c.E + qaddr(r, ta + 1)) = o.y;
         if (MI)
             acc += c.mit[min(abs((int)lapp.x), kMiTabN - 1)] + c.mit[min(abs((int)lapp.y), kMiTabN - 1)];
     }
@@ -316,10 +340,10 @@ __device__ void ph1_fwd(const Win &c, s2 A[4])
 {
     if (c.M <= 0) return;
     uint32_t r[S];
-    load_seg(c, 0, r);
+    load_seg<DEC>(c, 0, r);
     for (int i0 = 0; i0 < c.M; i0 += S) {
         uint32_t rn[S];
-        load_seg(c, min(i0 + S, c.M - S), rn);
+        load_seg<DEC>(c, min(i0 + S, c.M - S), rn);
         c.ck[(size_t)(i0 / S) * c.lanes + c.wi] = pack4(A);
         s2 g[S];
         gammas<DEC>(c, i0, r, g);
@@ -339,10 +363,10 @@ template <int DEC>
 __device__ void ph1_bwd(const Win &c, s2 B[4])
 {
     uint32_t r[S];
-    load_seg(c, c.W - S, r);
+    load_seg<DEC>(c, c.W - S, r);
     for (int i0 = c.W - S; i0 >= c.M; i0 -= S) {
         uint32_t rn[S];
-        load_seg(c, max(i0 - S, c.M), rn);
+        load_seg<DEC>(c, max(i0 - S, c.M), rn);
         c.ck[(size_t)(i0 / S) * c.lanes + c.wi] = pack4(B);
         s2 g[S];
         gammas<DEC>(c, i0, r, g);
@@ -379,9 +403,9 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
     int i0 = c.M;
     uint32_t r[S], rn[S], rnn[S];
     s2 g[S], g0[S], BP[S][4], m[S];
-    load_seg(c, i0, r);
+    load_seg<DEC>(c, i0, r);
     uint4 ckn = ck_at(c, min(i0 + S, last));
-    load_seg(c, min(i0 + S, last), rn);
+    load_seg<DEC>(c, min(i0 + S, last), rn);
     {
         s2 B[4];
         unpack4(ck_at(c, i0), B);
@@ -399,7 +423,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
 #pragma unroll 2
     for (; i0 < last; i0 += S) {
         const int i1 = i0 + S;
-        load_seg(c, min(i1 + S, last), rnn);
+        load_seg<DEC>(c, min(i1 + S, last), rnn);
         const uint4 cknn = ck_at(c, min(i1 + S, last));
         s2 Bn[4], gn[S], g0n[S], BPn[S][4];
         unpack4(ckn, Bn);
@@ -413,7 +437,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
             if (bwd_norm<true>(i1, u, c.W)) normalise(Bn);
             m[t] = acs_fwd_le(A, g0[t], g[t], BP[t]);
             fwd_post(A, i0, t, c.first);
-            if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r[t - 1], r[t], g[t - 1], g[t], m[t - 1], m[t], acc);
+            if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r, g[t - 1], g[t], m[t - 1], m[t], acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -432,7 +456,7 @@ __device__ int ph2_fwd(const Win &c, s2 A[4])
     for (int t = 0; t < S; ++t) {
         m[t] = acs_fwd_le(A, g0[t], g[t], BP[t]);
         fwd_post(A, i0, t, c.first);
-        if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r[t - 1], r[t], g[t - 1], g[t], m[t - 1], m[t], acc);
+        if (t & 1) emit2<DEC, MI>(c, i0, t - 1, r, g[t - 1], g[t], m[t - 1], m[t], acc);
     }
     return acc;
 }
@@ -449,9 +473,9 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
     int i0 = c.M - S;
     uint32_t r[S], rn[S], rnn[S];
     s2 g[S], g0[S], AQ[S][4], m[S];
-    load_seg(c, i0, r);
+    load_seg<DEC>(c, i0, r);
     uint4 ckn = ck_at(c, max(i0 - S, 0));
-    load_seg(c, max(i0 - S, 0), rn);
+    load_seg<DEC>(c, max(i0 - S, 0), rn);
     {
         s2 A[4];
         unpack4(ck_at(c, i0), A);
@@ -469,7 +493,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
 #pragma unroll 2
     for (; i0 > 0; i0 -= S) {
         const int i1 = i0 - S;
-        load_seg(c, max(i1 - S, 0), rnn);
+        load_seg<DEC>(c, max(i1 - S, 0), rnn);
         const uint4 cknn = ck_at(c, max(i1 - S, 0));
         s2 An[4], gn[S], g0n[S], AQn[S][4];
         unpack4(ckn, An);
@@ -483,7 +507,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
             const int u = S - 1 - t;
             m[u] = acs_bwd_le(B, AQ[u], g0[u], g[u]);
             if (bwd_norm(i0, u, c.W)) normalise(B);
-            if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r[u], r[u + 1], g[u], g[u + 1], m[u], m[u + 1], acc);
+            if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r, g[u], g[u + 1], m[u], m[u + 1], acc);
         }
 #pragma unroll
         for (int t = 0; t < S; ++t) {
@@ -502,7 +526,7 @@ __device__ int ph2_bwd(const Win &c, s2 B[4])
     for (int u = S - 1; u >= 0; --u) {
         m[u] = acs_bwd_le(B, AQ[u], g0[u], g[u]);
         if (bwd_norm(i0, u, c.W)) normalise(B);
-        if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r[u], r[u + 1], g[u], g[u + 1], m[u], m[u + 1], acc);
+        if (!(u & 1)) emit2<DEC, MI>(c, i0, u, r, g[u], g[u + 1], m[u], m[u + 1], acc);
     }
     return acc;
 }
@@ -561,10 +585,10 @@ __device__ void tf_fwd(const Win &c, uint4 *out)
                         (short)((r == (i & 3) && i >= 4) ? 0 : kNeg)};
         int acc = 0;
         uint32_t r0[S];
-        load_seg(c, 0, r0);
+        load_seg<DEC>(c, 0, r0);
         for (int i0 = 0; i0 < c.W; i0 += S) {
             uint32_t rn[S];
-            load_seg(c, min(i0 + S, c.W - S), rn);
+            load_seg<DEC>(c, min(i0 + S, c.W - S), rn);
             s2 g[S];
             gammas<DEC>(c, i0, r0, g);
 #pragma unroll
@@ -598,10 +622,10 @@ __device__ void tf_bwd(const Win &c, uint4 *out)
                         (short)((r == (j >> 1) && (j & 1)) ? 0 : kNeg)};
         int acc = 0;
         uint32_t r0[S];
-        load_seg(c, c.W - S, r0);
+        load_seg<DEC>(c, c.W - S, r0);
         for (int i0 = c.W - S; i0 >= 0; i0 -= S) {
             uint32_t rn[S];
-            load_seg(c, max(i0 - S, 0), rn);
+            load_seg<DEC>(c, max(i0 - S, 0), rn);
             s2 g[S];
             gammas<DEC>(c, i0, r0, g);
 #pragma unroll
@@ -680,21 +704,29 @@ __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, 
 // window is shorter than the others, so window lengths are per lane; the
 // even instantiation keeps them uniform (scalar loop bounds).
 // Four consecutive int16 LLRs (8 bytes); one 8-byte load when the address is
-// 8-byte aligned, else four 2-byte loads.
+// 8-byte aligned, else four 2-byte loads.  The channel LLRs are read once per
+// launch, so the loads are non-temporal: they do not displace the restaged
+// inputs and checkpoints that the iterations re-read from the caches.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint2 load4(const int16_t *p, bool aligned)
 {
-    if (aligned) return *(const uint2 *)p;
-    return make_uint2((uint16_t)p[0] | ((uint32_t)(uint16_t)p[1] << 16),
-                      (uint16_t)p[2] | ((uint32_t)(uint16_t)p[3] << 16));
+    if (aligned) {
+        const u32x2_t v = __builtin_nontemporal_load((const u32x2_t *)p);
+        return make_uint2(v.x, v.y);
+    }
+    const uint32_t a = (uint16_t)__builtin_nontemporal_load(p);
+    const uint32_t b = (uint16_t)__builtin_nontemporal_load(p + 1);
+    const uint32_t c = (uint16_t)__builtin_nontemporal_load(p + 2);
+    const uint32_t d = (uint16_t)__builtin_nontemporal_load(p + 3);
+    return make_uint2(a | (b << 16), c | (d << 16));
 }
 
 // One restaged unit: 4 steps starting at natural position pos, from the
-// systematic, parity 1 and parity 2 LLRs v[0..2] (4 int16 each) and the two
-// QPP address pairs q.  Clamps to +-2047, overrides filler positions (known
-// zeros: -2047 on systematic and parity 1), and writes decoder 1's word
-// Lp1 | Ls << 16 and decoder 2's word Lp2 | LDS address << 16 per step.
-__device__ __forceinline__ void restage_unit(const uint2 v[3], uint2 q, int pos, int F,
-                                             uint32_t so2, uint4 *r1, uint4 *r2)
+// systematic, parity 1 and parity 2 LLRs v[0..2] (4 int16 each).  Clamps to
+// +-2047, overrides filler positions (known zeros: -2047 on systematic and
+// parity 1), and writes decoder 1's word Lp1 | Ls << 16 per step and
+// decoder 2's four Lp2 (its QPP addresses come from the shape's table).
+__device__ __forceinline__ void restage_unit(const uint2 v[3], int pos, int F, uint4 *r1, uint2 *r2)
 {
     const s2 lo = (s2){(short)-kLlrMax, (short)-kLlrMax};
     const s2 hi = (s2){(short)kLlrMax, (short)kLlrMax};
@@ -715,15 +747,104 @@ __device__ __forceinline__ void restage_unit(const uint2 v[3], uint2 q, int pos,
                 lp[j >> 1] = (lp[j >> 1] & ~msk) | neg;
             }
     }
-    const uint32_t qa0 = q.x + so2, qa1 = q.y + so2;
     *r1 = make_uint4(__builtin_amdgcn_perm(ls[0], lp[0], 0x05040100u),
                      __builtin_amdgcn_perm(ls[0], lp[0], 0x07060302u),
                      __builtin_amdgcn_perm(ls[1], lp[1], 0x05040100u),
                      __builtin_amdgcn_perm(ls[1], lp[1], 0x07060302u));
-    *r2 = make_uint4(__builtin_amdgcn_perm(qa0, z[0], 0x05040100u),
-                     __builtin_amdgcn_perm(qa0, z[0], 0x07060302u),
-                     __builtin_amdgcn_perm(qa1, z[1], 0x05040100u),
-                     __builtin_amdgcn_perm(qa1, z[1], 0x07060302u));
+    *r2 = make_uint2(z[0], z[1]);
+}
+
+// Rows of the restage tile: the largest power of two R <= 32 with 4R <= W
+// whose tile (3 streams x nw windows x (R + 1) uint2) fits `tile_words`
+// 8-byte words; 0 when none does (the direct form is used then).
+__device__ __forceinline__ int restage_rows(int tile_words, int nw, int W)
+{
+    const int maxR = tile_words / (3 * nw) - 1;
+    int R = 0;
+    for (int r = 1; r <= 32 && r <= maxR && 4 * r <= W; r <<= 1) R = r;
+    return R;
+}
+
+// Restage one code block (LLRs at src, [3][K+4] int16, F filler bits) into
+// the item's inputs R1v / R2v ([t/4][lane], lanes per row; the block's
+// windows are lanes lane0 .. lane0 + nw - 1).  One unit = 4 trellis steps of
+// one window, written as one 16-byte word (decoder 1) and one 8-byte word
+// (decoder 2) so that the iterations read them coalesced.  Tiled form
+// (R > 0): a chunk of 4R steps of every window and stream is read with
+// contiguous loads into the LDS tile, then turned into units with
+// consecutive threads on consecutive windows (rows of R uint2 plus one of
+// padding).  Direct form (R = 0): consecutive threads take consecutive
+// windows.  Every thread of the work group calls it (it holds barriers).
+__device__ void restage_block(const int16_t *src, int K, int F, int nw, int W, int lanes,
+                              int lane0, uint4 *R1v, uint2 *R2v, uint2 *tile, int R, int tid,
+                              int nthr)
+{
+    const int N = K + 4;
+    // every load address is src plus a multiple of 4 elements
+    const bool aligned = (((uintptr_t)src) & 7) == 0;
+    if (R > 0) {
+        const int lg = __builtin_ctz((unsigned)R), rs = R + 1, nl = nw * R;
+        for (int c0 = 0; c0 < W; c0 += 4 * R) {
+            const int Rc = min(R, (W - c0) >> 2);
+            // the three streams' loads of 4 rows are all issued
+            // before the first LDS store (12 loads in flight)
+            for (int e0 = tid; e0 < nl; e0 += 4 * nthr) {
+                uint2 v[3][4];
+#pragma unroll
+                for (int st = 0; st < 3; ++st)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int e = e0 + m * nthr;
+                        const int ww = e >> lg, j = e & (R - 1);
+                        const int p = ww * W + c0 + 4 * j;
+                        v[st][m] = make_uint2(0u, 0u);
+                        if (e < nl && j < Rc && p < K) v[st][m] = load4(src + st * N + p, aligned);
+                    }
+#pragma unroll
+                for (int st = 0; st < 3; ++st)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int e = e0 + m * nthr;
+                        const int ww = e >> lg, j = e & (R - 1);
+                        if (e < nl && j < Rc) tile[(st * nw + ww) * rs + j] = v[st][m];
+                    }
+            }
+            __syncthreads();
+            const int nu = nw * Rc;
+            for (int e = tid; e < nu; e += nthr) {
+                const int jj = e / nw, ww = e - jj * nw;
+                const int t4 = (c0 >> 2) + jj;
+                const uint2 v[3] = {tile[ww * rs + jj], tile[(nw + ww) * rs + jj],
+                                    tile[(2 * nw + ww) * rs + jj]};
+                restage_unit(v, ww * W + 4 * t4, F, R1v + (size_t)t4 * lanes + lane0 + ww,
+                             R2v + (size_t)t4 * lanes + lane0 + ww);
+            }
+            __syncthreads();
+        }
+    } else {
+        // 4 units of loads in flight
+        const int units = (nw * W) >> 2;
+        for (int u0 = tid; u0 < units; u0 += 4 * nthr) {
+            uint2 v[4][3];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int u = min(u0 + m * nthr, units - 1);
+                const int t4 = u / nw, ww = u - t4 * nw;
+                const int p = ww * W + 4 * t4;
+#pragma unroll
+                for (int st = 0; st < 3; ++st)
+                    v[m][st] = p < K ? load4(src + st * N + p, aligned) : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int u = u0 + m * nthr;
+                if (u >= units) break;
+                const int t4 = u / nw, ww = u - t4 * nw;
+                restage_unit(v[m], ww * W + 4 * t4, F, R1v + (size_t)t4 * lanes + lane0 + ww,
+                             R2v + (size_t)t4 * lanes + lane0 + ww);
+            }
+        }
+    }
 }
 
 template <bool UNEVEN, bool EXACT, bool MI>
@@ -775,118 +896,24 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         // checkpoints, window boundary metrics
         const int64_t rsz = (int64_t)lanes * W;                  // padded steps of the item
         uint32_t *R1 = (uint32_t *)scr;                          // rsz int32
-        uint32_t *R2 = R1 + rsz;                                 // rsz int32
-        uint4 *ck = (uint4 *)(R2 + rsz);                         // (W/S)*lanes
+        uint32_t *R2 = R1 + rsz;                                 // rsz int16
+        uint4 *ck = (uint4 *)(R2 + rsz / 2);                     // (W/S)*lanes
         uint4 *bnd = ck + (int64_t)(W / S) * lanes;              // [4][lanes]
         // exact boundaries only: transfer runs, [lanes][8 states][2] each
         uint4 *tfA = bnd + (int64_t)4 * lanes;
         uint4 *tfB = tfA + (int64_t)16 * lanes;
 
-        // ---- restage the channel LLRs, clear LDS.  One unit = 4 trellis
-        // steps of one window, written as one 16-byte word per decoder at
-        // [t/4][window] so that the iterations read it coalesced.
+        // ---- restage the channel LLRs, clear LDS.  The tile of the restage
+        // is the item's extrinsic slots, unused until the iterations.
         {
             const int esz = lds_e_bytes(K);
-            const uint2 *qt = (const uint2 *)(a.qtab + it.qtab);
-            uint4 *R1v = (uint4 *)R1, *R2v = (uint4 *)R2;
-            // Tiled form: a chunk of 4R steps of every window and stream is
-            // read with contiguous loads into LDS (the item's extrinsic slots,
-            // unused until the iterations), then turned into units with
-            // consecutive threads on consecutive windows.  Rows of R uint2
-            // plus one of padding; R is a power of two that fits.
-            const int maxR = (ncb * it.lds_slot) / (24 * nw) - 1;
-            int R = 0;
-            for (int r = 1; r <= 32 && r <= maxR && 4 * r <= W; r <<= 1) R = r;
+            uint4 *R1v = (uint4 *)R1;
+            uint2 *R2v = (uint2 *)R2;
+            const int R = restage_rows((ncb * it.lds_slot) / 8, nw, W);
             for (int cs = 0; cs < ncb; ++cs) {
                 const DecCb cb = a.cbs[it.cb0 + cs];
-                const int16_t *src = a.llr + cb.llr_off;
-                const int N = K + 4;
-                // every load address is src plus a multiple of 4 elements
-                const bool aligned = (((uintptr_t)src) & 7) == 0;
-                const uint32_t so = (uint32_t)(cs * it.lds_slot);
-                const uint32_t so2 = so | (so << 16);
-                if (R > 0) {
-                    uint2 *tile = (uint2 *)lds;
-                    const int lg = __builtin_ctz((unsigned)R), rs = R + 1, nl = nw * R;
-                    for (int c0 = 0; c0 < W; c0 += 4 * R) {
-                        const int Rc = min(R, (W - c0) >> 2);
-                        // the three streams' loads of 4 rows are all issued
-                        // before the first LDS store (12 loads in flight)
-                        for (int e0 = tid; e0 < nl; e0 += 4 * nthr) {
-                            uint2 v[3][4];
-#pragma unroll
-                            for (int st = 0; st < 3; ++st)
-#pragma unroll
-                                for (int m = 0; m < 4; ++m) {
-                                    const int e = e0 + m * nthr;
-                                    const int ww = e >> lg, j = e & (R - 1);
-                                    const int p = ww * W + c0 + 4 * j;
-                                    v[st][m] = make_uint2(0u, 0u);
-                                    if (e < nl && j < Rc && p < K)
-                                        v[st][m] = load4(src + st * N + p, aligned);
-                                }
-#pragma unroll
-                            for (int st = 0; st < 3; ++st)
-#pragma unroll
-                                for (int m = 0; m < 4; ++m) {
-                                    const int e = e0 + m * nthr;
-                                    const int ww = e >> lg, j = e & (R - 1);
-                                    if (e < nl && j < Rc) tile[(st * nw + ww) * rs + j] = v[st][m];
-                                }
-                        }
-                        __syncthreads();
-                        // four units per trip: their QPP address loads first
-                        const int nu = nw * Rc;
-                        for (int e0 = tid; e0 < nu; e0 += 4 * nthr) {
-                            uint2 q[4];
-#pragma unroll
-                            for (int m = 0; m < 4; ++m) {
-                                const int e = min(e0 + m * nthr, nu - 1);
-                                const int jj = e / nw, ww = e - jj * nw;
-                                q[m] = qt[((c0 >> 2) + jj) * nw + ww];
-                            }
-#pragma unroll
-                            for (int m = 0; m < 4; ++m) {
-                                const int e = e0 + m * nthr;
-                                if (e >= nu) break;
-                                const int jj = e / nw, ww = e - jj * nw;
-                                const int t4 = (c0 >> 2) + jj;
-                                const uint2 v[3] = {tile[ww * rs + jj], tile[(nw + ww) * rs + jj],
-                                                    tile[(2 * nw + ww) * rs + jj]};
-                                restage_unit(v, q[m], ww * W + 4 * t4, cb.F, so2,
-                                             R1v + (size_t)t4 * lanes + cs * nw + ww,
-                                             R2v + (size_t)t4 * lanes + cs * nw + ww);
-                            }
-                        }
-                        __syncthreads();
-                    }
-                } else {
-                    // direct form (items too small for a tile): consecutive
-                    // threads take consecutive windows; 4 units of loads in flight
-                    const int units = (nw * W) >> 2;
-                    for (int u0 = tid; u0 < units; u0 += 4 * nthr) {
-                        uint2 v[4][3], q[4];
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const int u = min(u0 + m * nthr, units - 1);
-                            const int t4 = u / nw, ww = u - t4 * nw;
-                            const int p = ww * W + 4 * t4;
-                            q[m] = qt[u];
-#pragma unroll
-                            for (int st = 0; st < 3; ++st)
-                                v[m][st] = p < K ? load4(src + st * N + p, aligned) : make_uint2(0u, 0u);
-                        }
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const int u = u0 + m * nthr;
-                            if (u >= units) break;
-                            const int t4 = u / nw, ww = u - t4 * nw;
-                            restage_unit(v[m], q[m], ww * W + 4 * t4, cb.F, so2,
-                                         R1v + (size_t)t4 * lanes + cs * nw + ww,
-                                         R2v + (size_t)t4 * lanes + cs * nw + ww);
-                        }
-                    }
-                }
+                restage_block(a.llr + cb.llr_off, K, cb.F, nw, W, lanes, cs * nw, R1v, R2v,
+                              (uint2 *)lds, R, tid, nthr);
             }
             __syncthreads();  // the tile's last reads come before the clear
             for (int cs = 0; cs < ncb; ++cs) {
@@ -916,10 +943,10 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         c.first = w == 0;
         c.last = w == nw - 1;
         c.E = (short *)(lds + (int64_t)cs * it.lds_slot);
+        c.qt = (const uint2 *)(a.qtab + it.qtab) + w;
+        c.qs = nw;
         c.ck = ck;
         c.mit = s_mit;
-        // decoder 2 addresses E through byte offsets from the slot of block 0
-        short *E0 = (short *)lds;
 
         // trellis termination of both encoders: beta_K (Q layout) in closed
         // form along the forced zero-feedback path from each state
@@ -957,7 +984,6 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             for (int dec = 1; dec <= 2; ++dec) {
                 Win cd = c;
                 cd.R = (const uint4 *)(dec == 1 ? R1 : R2);
-                if (dec == 2) cd.E = E0;
                 uint4 *bA = bnd + (dec - 1) * 2 * lanes;  // alpha boundaries of this decoder
                 uint4 *bB = bA + lanes;                   // beta boundaries
                 if (EXACT) {

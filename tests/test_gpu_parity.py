@@ -384,3 +384,33 @@ def test_uniform_batch_full_size_sampled(dev):
                                              O.params(iters, es, 32, 1), nb)
             assert gok[i] == ook[0] and git[i] == oit[0], i
             assert np.array_equal(gb[i], ob), i
+
+
+@pytest.mark.parametrize("cbs,p", [
+    ([(6144, 0, O.CRC24B)] * 24, O.params(6, 0, 32, 1)),
+    ([(6144, 0, O.CRC24B)] * 9, O.params(4, 1, 31, 1)),     # uneven windows
+    ([(1056, 13, O.CRC24A)] * 30, O.params(5, 1, 4, 2)),    # exact boundaries
+    ([(512, 0, O.CRC_NONE)] * 80 + [(40, 8, O.CRC24B)] * 70, O.params(8, 1, 1, 0)),
+])
+def test_small_grid(dev, cbs, p):
+    """A grid capped far below the item count: every work group restages and
+    decodes many items in turn (claims, scratch and LDS reuse); the outputs
+    equal the oracle's."""
+    T, _, torch = dev
+    D2 = T.Decoder(0)
+    try:
+        D2.set_knobs(grid_cap=3)
+        say(f"[small grid] n={len(cbs)} K={sorted(set(c[0] for c in cbs))} "
+            f"p=({p.max_iters},{p.early_stop},{p.n_windows},{p.win_init}) grid_cap=3")
+        llr, pays, od, n_llr, n_bytes = cb_batch(cbs, "qpsk", [(0.0, 1.0, 2.0)[i % 3]
+                                                               for i in range(len(cbs))], 204)
+        gb, gok, git = gpu_cb_batch((T, D2, torch), od, llr,
+                                    T.params(p.max_iters, p.early_stop, p.n_windows, p.win_init),
+                                    n_bytes)
+        # exact boundaries equal full-length decoding (one window)
+        op = O.params(p.max_iters, p.early_stop, 1, 0) if p.win_init == 2 else p
+        ob, ook, oit = oracle_cb_batch(od, llr, op)
+        assert np.array_equal(gok, ook) and np.array_equal(git, oit)
+        assert np.array_equal(gb, ob)
+    finally:
+        D2.close()
