@@ -552,6 +552,7 @@ def run_stop(args):
             rows.append(row)
             if not crc and db == 8.0 and name == "mi":
                 head = (row, ops, ms)
+    purge = run_purge(D, torch)
     row, ops, ms = head
     return {"metric": "decoded info Gbit/s, mutual-information stop (<= 8 iterations), "
                       "blocks without CRC", "value": row["gbit_s"],
@@ -565,6 +566,46 @@ def run_stop(args):
                          "peak": round(PEAK_INT16_TOPS, 2), "unit": "TOP/s",
                          "frac": round(ops / ms / 1e9 / PEAK_INT16_TOPS, 4), "traffic": None},
             "blocks_wrong": row["blocks_wrong"], "mean_iters": row["mean_iters"],
+            "rows": rows, "purge": purge}
+
+
+def run_purge(D, torch):
+    """The purge of Algorithm 2 at work: 128 transport blocks of 75376 bits
+    (13 x K5824) at 16QAM with Es/N0 spread over the waterfall, MI stop (and
+    MI + CRC stop), with and without purging the siblings of a block that
+    stopped failed: launch time, transport blocks decoded (equal with and
+    without, as the rule requires), blocks purged."""
+    n, tbs = 128, MAX_TB
+    g = wl.rng(8, 77)
+    pays, coded = encode_tbs(D, torch, [tbs] * n, g)
+    llr, lo = channel(coded, [tbs] * n, ["16qam"] * n, list(np.linspace(2.6, 3.8, n)), g)
+    x = torch.from_numpy(llr).cuda()
+    bo = np.arange(n, dtype=np.int64) * ((tbs + 7) // 8)
+    bits = torch.zeros(int(bo[-1]) + (tbs + 7) // 8, dtype=torch.uint8, device="cuda")
+    res = torch.zeros(n * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    rows = []
+    for rule, name, eps in ((T.STOP_MI, "mi", T.MI_EPS_DEFAULT),
+                            (T.STOP_MI | T.STOP_CRC, "mi|crc", T.MI_EPS_DEFAULT),
+                            (T.STOP_MI | T.STOP_CRC, "mi|crc", 33)):
+        out = {}
+        for purge in (False, True):
+            p = T.params(8, rule | (T.STOP_PURGE if purge else 0), 0, 1, eps)
+            ms, _ = time_launches(torch, lambda: D.tb_decode_batch([tbs] * n, lo, bo, x, p, bits, res))
+            r = T.parse_tb_results(res.cpu().numpy())
+            out[purge] = (ms, [q["tb_ok"] for q in r],
+                          sum(1 for q in r for c in range(q["C"]) if q["cb_iters"][c] == 0),
+                          sum(sum(q["cb_iters"][:q["C"]]) for q in r))
+        row = {"rule": name, "mi_eps": eps, "launch_ms": round(out[False][0], 4),
+               "launch_ms_purge": round(out[True][0], 4),
+               "tb_ok": sum(out[False][1]), "tb_ok_purge": sum(out[True][1]),
+               "tb_outcomes_equal": out[False][1] == out[True][1],
+               "blocks_purged": out[True][2],
+               "block_iterations": out[False][3],
+               "block_iterations_purge_unpurged_blocks": out[True][3]}
+        log(f"[purge] {row}")
+        rows.append(row)
+    return {"workload": f"{n} TBs x {tbs} bits (13 x K5824), 16QAM Es/N0 2.6..3.8 dB, <= 8 "
+                        "iterations, library windows, previous-iteration boundaries",
             "rows": rows}
 
 

@@ -81,7 +81,7 @@ typedef enum {
 
 enum { TDEC_CRC_NONE = 0, TDEC_CRC24A = 1, TDEC_CRC24B = 2 };
 
-enum { TDEC_STOP_CRC = 1, TDEC_STOP_MI = 2 }; /* bits of tdec_params.early_stop */
+enum { TDEC_STOP_CRC = 1, TDEC_STOP_MI = 2, TDEC_STOP_PURGE = 4 }; /* bits of tdec_params.early_stop */
 
 /* Decoder parameters. */
 typedef struct {
@@ -101,7 +101,16 @@ typedef struct {
                              T[m] = round(2^15 h(1 / (1 + e^(m/8)))).  With S_i the
                              sum after iteration i, the block stops when
                              S_i <= K mi_eps, or i >= 2 and |S_i - S_(i-1)| <= K mi_eps.
-                           crc_ok reports the CRC at the iteration the block stopped. */
+                           crc_ok reports the CRC at the iteration the block stopped.
+                           TDEC_STOP_PURGE (transport block calls only, with TDEC_STOP_MI:
+                             the paper's Algorithm 2, a transport block fails when any of its
+                             code blocks fails): a block that stops on a rule while its CRC
+                             fails marks its transport block failed, and the block's siblings
+                             still iterating stop at the end of their current iteration
+                             (purged: cb_iters = 0, cb_ok = 0).  Such a transport block has
+                             tb_ok = 0; its payload bits and its other blocks' flags depend
+                             on timing (a sibling may finish before it sees the mark).  Code
+                             block calls ignore the bit. */
     int32_t n_windows;  /* windows per code block, 1..128: every window but the last has
                            W = 8*ceil(K/(8n)) steps (K for n = 1), the last the rest, which
                            must be non-empty; 0 = the library's choice for each K

@@ -345,3 +345,25 @@ def tb_decode_windows(llr, tbs: int, p: Params, nw_per_cb):
         raise ValueError("bad tb_decode arguments")
     return bits, {"tb_ok": res.tb_ok, "max_iters_used": res.max_iters_used, "C": res.C,
                   "cb_ok": list(res.cb_ok[:res.C]), "cb_iters": list(res.cb_iters[:res.C])}
+
+
+def tb_purge_marked(llr, tbs: int, p: Params, nw_per_cb=None):
+    """The paper's Algorithm 2 on top of independent block decoding: a
+    transport block fails as soon as one of its code blocks fails.  With a
+    stopping rule, a block that stops (the rule fires) while its CRC fails is
+    known to have failed, so its transport block is marked failed and the
+    work of its still-iterating siblings can be dropped.  Returns
+    (bits, result, marked): the plain decode of every block with the rule,
+    and whether some block stopped failed.  A block that fails at the last
+    iteration stopped there iff decoding with one more iteration allowed
+    also ends at that iteration (iterations are causal)."""
+    bits, res = tb_decode_windows(llr, tbs, p, nw_per_cb)
+    if not p.early_stop:
+        return bits, res, False
+    marked = any(ok == 0 and it < p.max_iters for ok, it in zip(res["cb_ok"], res["cb_iters"]))
+    if not marked and p.max_iters < 16 and 0 in res["cb_ok"]:
+        p1 = Params(p.max_iters + 1, p.early_stop, p.n_windows, p.win_init, p.mi_eps)
+        _, r1 = tb_decode_windows(llr, tbs, p1, nw_per_cb)
+        marked = any(ok == 0 and it0 == p.max_iters and it1 == p.max_iters
+                     for ok, it0, it1 in zip(res["cb_ok"], res["cb_iters"], r1["cb_iters"]))
+    return bits, res, marked

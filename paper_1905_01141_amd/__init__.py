@@ -226,14 +226,15 @@ def _stream(stream):
 
 
 # ----------------------------------------------------------------------------- helpers
-STOP_CRC, STOP_MI = 1, 2  # bits of Params.early_stop
+STOP_CRC, STOP_MI, STOP_PURGE = 1, 2, 4  # bits of Params.early_stop
 MI_EPS_DEFAULT = 1         # 2^-15 bit per bit: looser thresholds stop max-log-MAP blocks
                            # whose a-posteriori values are large but still wrong
 
 
 def params(max_iters=6, early_stop=0, n_windows=1, win_init=0, mi_eps=MI_EPS_DEFAULT) -> Params:
-    """Decoder parameters (tdec_params).  early_stop: 0, or an OR of STOP_CRC
-    and STOP_MI; mi_eps: the STOP_MI threshold."""
+    """Decoder parameters (tdec_params).  early_stop: 0, or an OR of STOP_CRC,
+    STOP_MI and STOP_PURGE (transport block calls); mi_eps: the STOP_MI
+    threshold."""
     return Params(max_iters, early_stop, n_windows, win_init, mi_eps)
 
 

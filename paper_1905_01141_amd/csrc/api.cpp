@@ -30,6 +30,7 @@ constexpr int kLdsPerCu = 160 * 1024;
 constexpr size_t kQtabEntries = 4u << 20;  // QPP table arena (8 MiB): every size at ~11 window counts
 constexpr size_t kRmEntries = 8u << 20;    // rate matching table arena (16 MiB, >= 450 tables)
 constexpr int kDefaultLdsBudget = 30 * 1024;
+constexpr int kTbFailWords = 1 << 16;  // transport blocks per purge launch
 
 struct PlanSlot {
     std::string key;
@@ -67,6 +68,7 @@ struct tdec_ctx {
     uint8_t *d_encbuf = nullptr;
     size_t encbuf_bytes = 0;
     uint32_t *d_counter = nullptr;  // work distribution counters of the decode kernel (kCtrBytes)
+    uint32_t *d_tbfail = nullptr;   // per transport block failure marks (purge), kTbFailWords
     // QPP LDS-address tables, one per (K, windows) shape, appended on first
     // use and kept for the context's lifetime; the pinned mirror is never
     // rewritten, so its asynchronous uploads need no synchronisation
@@ -408,11 +410,16 @@ tdec_status launch_plan(tdec_ctx *ctx, PlanSlot *ps, const int16_t *d_llr,
     a.win_init = p->win_init;
     a.mi_eps = p->mi_eps;
     a.state_slots = ps->state_slots;
+    // purge (transport block plans): the failure marks start clear
+    const bool purge = (p->early_stop & TDEC_STOP_PURGE) && ps->n_tb > 0 && !fixed;
+    a.tb_fail = purge ? ctx->d_tbfail : nullptr;
     // the plan's scratch and LDS layouts
     if ((p->win_init == 2) != ps->exact || ((p->early_stop & 2) != 0) != ps->mi) return TDEC_EINVAL;
     // the fixed counters start every call at zero (another call may have
     // left them set if it overlapped this one, which the header forbids)
     if (fixed && launch_zero_words((uint32_t *)fixed, kCtrBytes / 4, st)) return TDEC_EDEVICE;
+    if (purge && ps->n_tb > kTbFailWords) return TDEC_ENOMEM;
+    if (purge && launch_zero_words(ctx->d_tbfail, ps->n_tb, st)) return TDEC_EDEVICE;
     int grid = ps->grid;
     if (ctx->launch_reserve > 0) grid = std::max(1, std::min(grid, ps->resident - ctx->launch_reserve));
     if (launch_decode(a, ps->uneven, ps->exact, ps->mi, grid, ps->wg, ps->lds, st))
@@ -471,6 +478,7 @@ tdec_status make_cb_reqs(const tdec_ctx *ctx, int32_t n_cb, const tdec_cb_desc *
         r.cb.F = d.F;
         r.cb.crc = d.crc;
         r.cb.rsv = 0;
+        r.cb.tb = -1;
     }
     return TDEC_OK;
 }
@@ -519,6 +527,7 @@ tdec_status make_tb_reqs(const tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs,
             q.cb.F = (int16_t)(r == 0 ? s[7] : 0);
             q.cb.crc = (int8_t)(s[1] > 1 ? TDEC_CRC24B : TDEC_CRC24A);
             q.cb.rsv = 0;
+            q.cb.tb = t;
             reqs.push_back(q);
             off += 3 * (int64_t)(K + 4);
             hard += hard_words(K);
@@ -542,8 +551,9 @@ tdec_status launch_tb_plan(tdec_ctx *ctx, PlanSlot *ps, char *d_plan, const int1
     if (s != TDEC_OK) return s;
     if (ev_mid && hipEventRecord(ev_mid, st) != hipSuccess) return TDEC_EDEVICE;
     if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ps->asm_words,
-                           ctx->d_hard, ctx->d_ok, ctx->d_it, ctx->d_crc_tab, d_bits, d_res,
-                           ctx->small_asm, st))
+                           ctx->d_hard, ctx->d_ok, ctx->d_it,
+                           (params->early_stop & TDEC_STOP_PURGE) ? ctx->d_tbfail : nullptr,
+                           ctx->d_crc_tab, d_bits, d_res, ctx->small_asm, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }
@@ -691,7 +701,7 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
     c->qtab_cap = kQtabEntries;
     c->rm_cap = kRmEntries;
     const size_t fixed = tab_bytes + 2 * c->flags_cap + c->encbuf_bytes + plan_bytes +
-                         c->qtab_cap * 2 + c->rm_cap * 2;
+                         c->qtab_cap * 2 + c->rm_cap * 2 + (size_t)kTbFailWords * 4;
     if (c->budget < fixed + (16u << 20)) {
         delete c;
         return TDEC_ENOMEM;
@@ -706,6 +716,7 @@ tdec_status tdec_create(int device, size_t hbm_budget_bytes, tdec_ctx **out)
               hipMalloc(&c->d_it, c->flags_cap) == hipSuccess &&
               hipMalloc(&c->d_encbuf, c->encbuf_bytes) == hipSuccess &&
               hipMalloc(&c->d_counter, kCtrBytes) == hipSuccess &&
+              hipMalloc(&c->d_tbfail, (size_t)kTbFailWords * 4) == hipSuccess &&
               hipMemset(c->d_counter, 0, kCtrBytes) == hipSuccess &&
               hipMalloc(&c->d_qtab, c->qtab_cap * 2) == hipSuccess &&
               hipHostMalloc(&c->h_qtab, c->qtab_cap * 2, hipHostMallocDefault) == hipSuccess &&
@@ -755,6 +766,7 @@ void tdec_destroy(tdec_ctx *c)
     (void)hipFree(c->d_it);
     (void)hipFree(c->d_encbuf);
     (void)hipFree(c->d_counter);
+    (void)hipFree(c->d_tbfail);
     if (c->d_qtab) (void)hipFree(c->d_qtab);
     if (c->h_qtab) (void)hipHostFree(c->h_qtab);
     if (c->d_rmtab) (void)hipFree(c->d_rmtab);
@@ -874,7 +886,7 @@ tdec_status tb_decode_batch(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, con
 bool tdec::params_valid(const tdec_params *p)
 {
     return p && p->max_iters >= 1 && p->max_iters <= 16 && p->early_stop >= 0 &&
-           p->early_stop <= 3 && p->n_windows >= 0 && p->n_windows <= 128 && p->win_init >= 0 &&
+           p->early_stop <= 7 && p->n_windows >= 0 && p->n_windows <= 128 && p->win_init >= 0 &&
            p->win_init <= 2 && p->mi_eps >= 0 && p->mi_eps <= 32768;
 }
 

@@ -1129,9 +1129,19 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                     s_done[cs] = 1;
                     s_iters[cs] = iter;
                     s_ok[cs] = pass;
+                    // a block that stops with a failed CRC fails its
+                    // transport block (Algorithm 2): mark it for the siblings
+                    if (!pass && a.tb_fail && cb.tb >= 0) atomicOr(&a.tb_fail[cb.tb], 1u);
                 } else if (iter == a.max_iters) {
                     s_iters[cs] = iter;
                     s_ok[cs] = pass;
+                } else if (a.tb_fail && cb.tb >= 0 &&
+                           __hip_atomic_load(&a.tb_fail[cb.tb], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    // a sibling failed: the rest of this block's work is purged
+                    s_done[cs] = 1;
+                    s_iters[cs] = 0;
+                    s_ok[cs] = 0;
                 }
             }
             __syncthreads();
@@ -1303,6 +1313,7 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, i
                                                                   const uint32_t *hard,
                                                                   const uint8_t *crc_ok,
                                                                   const uint8_t *iters,
+                                                                  const uint32_t *tb_fail,
                                                                   uint8_t *bits, TbRes *res,
                                                                   const uint32_t *x32)
 {
@@ -1429,7 +1440,8 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, i
             // wave-wide maximum (the 64 threads are one wave)
             for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
             if (tid == 0) {
-                o.tb_ok = s_crc == 0;
+                // a transport block marked failed by a purge fails (Algorithm 2)
+                o.tb_ok = s_crc == 0 && !(tb_fail && tb_fail[t]);
                 o.max_iters_used = mx;
                 o.C = tb.C;
                 o.rsv = 0;
@@ -1440,8 +1452,9 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, i
 }
 
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
-                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
-                       uint8_t *bits, void *res, bool small_grid, void *stream)
+                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *tb_fail,
+                       const uint32_t *crc_tab, uint8_t *bits, void *res, bool small_grid,
+                       void *stream)
 {
     if (n_tb <= 0) return 0;
     // one work group of 256 threads per transport block, or kAsmGrid work
@@ -1449,7 +1462,7 @@ int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint3
     const int grid = small_grid ? min(n_tb, kAsmGrid) : n_tb;
     hipLaunchKernelGGL(tb_assemble_kernel, dim3(grid), dim3(small_grid ? 128 : 256),
                        (size_t)max_words * 4, (hipStream_t)stream, items, n_tb, hard, crc_ok, iters,
-                       bits, (TbRes *)res, crc_tab + 2 * kCrcTabN);
+                       tb_fail, bits, (TbRes *)res, crc_tab + 2 * kCrcTabN);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

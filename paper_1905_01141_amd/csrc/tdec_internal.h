@@ -58,6 +58,7 @@ struct DecCb {
     int16_t F;
     int8_t crc;        // 0 none, 1 CRC24A, 2 CRC24B
     int8_t rsv;
+    int32_t tb;        // index of its transport block in the plan (purge marks), -1 = none
 };
 
 // Work distribution counters of the decode kernel: kCtrSets sets of work
@@ -88,6 +89,7 @@ struct DecArgs {
     const uint32_t *mi_tab;  // kMiTabN entropy table entries (mutual-information stop)
     int32_t max_iters, early_stop, win_init, mi_eps;
     int32_t state_slots;  // most blocks of any item (size of the per-slot LDS state)
+    uint32_t *tb_fail;    // per transport block failure marks (purge), null = no purge
 };
 
 // One transport block for the assembly kernel (after the code blocks are decoded).
@@ -225,9 +227,12 @@ constexpr int kAsmGrid = 64;
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
 // small_grid: kAsmGrid work groups of 128 threads (launch lanes) instead of
 // one of 256 threads per transport block.
+// tb_fail: the decode launch's failure marks (purge), a marked block fails
+// without its CRC24A being checked; null = no purge.
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
-                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *crc_tab,
-                       uint8_t *bits, void *res, bool small_grid, void *stream);
+                       const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *tb_fail,
+                       const uint32_t *crc_tab, uint8_t *bits, void *res, bool small_grid,
+                       void *stream);
 int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
                   const uint32_t *crc_tab, void *stream);
 int launch_tb_crc_attach(const uint8_t *payload, int32_t tbs, uint8_t *stream_bits,

@@ -3,7 +3,9 @@ function): the kernel sums the entropy of decoder 2's hard decisions per
 block and stops a block when the sum has converged.  Bits, CRC flags and
 iteration counts equal the oracle's, bit for bit, alone and combined with the
 CRC stop, over windowed, exact-boundary, transport-block and captured-graph
-launches, and at the full 4096 x K6144 batch on sampled blocks."""
+launches, and at the full 4096 x K6144 batch on sampled blocks.  With the
+purge of Algorithm 2 on, transport blocks follow the oracle's model of the
+rule (test_purge_follows_the_model)."""
 import sys
 
 import numpy as np
@@ -166,7 +168,7 @@ def test_mi_stop_full_batch_sampled(dev):
 def test_mi_params_rejected(dev):
     T = dev[0]
     llr, _, od, _, n_bytes = cb_batch([(40, 0, O.CRC24B)], "qpsk", 3.0, 406)
-    for p in (T.params(8, 4, 1, 0), T.params(8, MI, 1, 0, -1), T.params(8, MI, 1, 0, 32769)):
+    for p in (T.params(8, 8, 1, 0), T.params(8, MI, 1, 0, -1), T.params(8, MI, 1, 0, 32769)):
         with pytest.raises(T.TdecError):
             gpu_cbs(dev, od, llr, p, n_bytes)
 
@@ -207,3 +209,55 @@ def test_mi_stop_through_the_serving_loop(dev):
         assert r["tb_ok"] == ores["tb_ok"] and r["max_iters_used"] == ores["max_iters_used"], i
         assert np.array_equal(out[i], ob), (i, tbs)
 
+
+
+def test_purge_follows_the_model(dev):
+    """Purge (Algorithm 2): transport blocks of 13 blocks at low Es/N0, some
+    with one block that carries noise only, MI stop with eps 300.  A block
+    that stops failed marks its transport block; its siblings still running
+    are purged (iters 0, ok 0).  Per the oracle's model: an unmarked
+    transport block equals the oracle in everything; a marked one has
+    tb_ok = 0 and each block either equals the oracle or was purged.  The
+    same launch without the purge equals the oracle throughout."""
+    T, D, torch = dev
+    tbs = 75376
+    n = 24
+    g = np.random.default_rng(1905)
+    esn0 = np.linspace(2.6, 3.6, n)
+    llr, _, lo, bo = tb_batch([tbs] * n, "16qam", esn0, 407)
+    sizes = O.cb_sizes(tbs)
+    noisy = [i for i in range(n) if i % 3 == 0]
+    for i in noisy:  # block 5 of these transport blocks: noise only
+        o = int(lo[i]) + sum(3 * (K + 4) for K, _ in sizes[:5])
+        llr[o:o + 3 * (sizes[5][0] + 4)] = g.integers(-40, 41, 3 * (sizes[5][0] + 4))
+    x = torch.from_numpy(llr).cuda()
+    nb = int(bo[-1]) + (tbs + 7) // 8
+    nws = [D.pick_windows(K) for K, _ in sizes]
+    op = O.params(8, MI, 0, 1, 300)
+    model = [O.tb_purge_marked(llr[lo[i]:lo[i] + O.tb_llr_count(tbs)], tbs, op, nws)
+             for i in range(n)]
+    n_marked = sum(m[2] for m in model)
+    say(f"[purge] {n} x {tbs}: {n_marked} transport blocks marked by the model")
+    assert n_marked >= len(noisy)
+    for purge in (False, True):
+        p = T.params(8, MI | (T.STOP_PURGE if purge else 0), 0, 1, 300)
+        eb = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+        er = torch.zeros(n * T.TB_RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        D.tb_decode_batch([tbs] * n, lo, bo, x, p, eb, er)
+        torch.cuda.synchronize()
+        res, hb = T.parse_tb_results(er.cpu().numpy()), eb.cpu().numpy()
+        purged = 0
+        for i, (ob, ores, marked) in enumerate(model):
+            if not purge or not marked:
+                assert res[i] == ores, (purge, i)
+                assert np.array_equal(hb[bo[i]:bo[i] + ob.size], ob), (purge, i)
+                continue
+            assert res[i]["tb_ok"] == 0, i
+            for r in range(len(sizes)):
+                got = (res[i]["cb_ok"][r], res[i]["cb_iters"][r])
+                want = (ores["cb_ok"][r], ores["cb_iters"][r])
+                assert got == want or got == (0, 0), (i, r, got, want)
+                purged += got == (0, 0) and want != (0, 0)
+        if purge:
+            say(f"[purge] blocks purged: {purged}")
+            assert purged >= 1

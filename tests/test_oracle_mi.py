@@ -143,3 +143,35 @@ def test_bad_params_rejected(orc):
     for p in (orc.params(8, 4, 1, 0), orc.params(8, 2, 1, 0, -1), orc.params(8, 2, 1, 0, 32769)):
         with pytest.raises(Exception):
             orc.cb_decode(llr, 40, 0, orc.CRC_NONE, p)
+
+
+def test_purge_model(orc):
+    """Algorithm 2's rule on top of block decoding: a transport block is
+    marked failed when one of its blocks stops on the MI rule with a failed
+    CRC; blocks that decode, or blocks that fail without the rule firing,
+    leave it unmarked."""
+    tbs = 9000                       # two code blocks
+    sizes = orc.cb_sizes(tbs)
+    assert len(sizes) == 2
+    g = wl.rng(1905, 11)
+    d, _ = orc.tb_encode(wl.random_bits(g, tbs))
+    clean = wl.channel_blocks(d, sizes, "qpsk", 6.0, g)
+    p = orc.params(8, orc.STOP_MI, 1, 0, 300)
+    _, res, marked = orc.tb_purge_marked(clean, tbs, p)
+    assert res["tb_ok"] == 1 and not marked
+    # the second block carries noise only: it fails, and with eps 300 its
+    # a-posteriori sum settles well before the last iteration
+    bad = clean.copy()
+    n0 = 3 * (sizes[0][0] + 4)
+    bad[n0:] = g.integers(-40, 41, bad.size - n0).astype(np.int16)
+    _, res, marked = orc.tb_purge_marked(bad, tbs, p)
+    assert res["cb_ok"][1] == 0 and res["cb_iters"][1] < 8 and marked
+    assert res["tb_ok"] == 0
+    # no stopping rule: nothing stops early, nothing is marked
+    _, res, marked = orc.tb_purge_marked(bad, tbs, orc.params(8, 0, 1, 0, 0))
+    assert res["cb_iters"] == [8, 8] and not marked
+    # a block that fails at the last iteration is marked only if the rule
+    # fired there: eps 0 with a noise block that never settles
+    _, res, marked = orc.tb_purge_marked(bad, tbs, orc.params(2, orc.STOP_MI, 1, 0, 0))
+    _, r3 = orc.tb_decode(bad, tbs, orc.params(3, orc.STOP_MI, 1, 0, 0))
+    assert marked == (res["cb_ok"][1] == 0 and r3["cb_iters"][1] == 2 or res["cb_iters"][1] < 2)

@@ -309,7 +309,7 @@ def test_slot_arena_coalesces_after_churn():
 def test_creation_checks_every_decoder_parameter():
     """A bad stop rule, threshold, boundary mode or window count fails at
     creation, not later at every launch."""
-    for p in (T.params(8, 4, 1, 0), T.params(8, T.STOP_MI, 1, 0, -1), T.params(8, T.STOP_MI, 1, 0, 32769),
+    for p in (T.params(8, 8, 1, 0), T.params(8, T.STOP_MI, 1, 0, -1), T.params(8, T.STOP_MI, 1, 0, 32769),
               T.params(8, 1, 1, 3), T.params(8, 1, 129, 0), T.params(0, 1, 1, 0), T.params(17, 1, 1, 0)):
         with pytest.raises(T.TdecError):
             T.Server.model(T.server_cfg(p), 100_000, 0)
