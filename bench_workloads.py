@@ -708,8 +708,11 @@ def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admis
         while srv.discard() == 65536:
             pass
         srv.reset_stats()
+        # everything the replay reads is built before the clock starts
+        tbs_m = np.ascontiguousarray(pool_tbs[im], np.int32)
+        ptr_m = np.ascontiguousarray(pool_llr_ptr[im], np.uint64)
         t_begin = T.now_ns() + TTI_NS
-        late_m, smax = srv.replay(cm, pool_tbs[im], pool_llr_ptr[im], bp, TTI_NS, t_begin, tag0)
+        late_m, smax = srv.replay(cm, tbs_m, ptr_m, bp, TTI_NS, t_begin, tag0)
         srv.drain(60000)
         t_end = T.now_ns()
         while True:

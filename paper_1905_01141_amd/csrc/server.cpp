@@ -89,6 +89,27 @@ public:
         }
         add(off, n);
     }
+    // Release many extents at once: sorted by offset, adjacent ones are
+    // merged first, so a launch's slots (mostly allocated one after another)
+    // cost a few index operations instead of a few per slot.  `ext` holds
+    // (offset, bytes) pairs and is reordered.
+    void release_many(std::vector<std::pair<int64_t, int64_t>> &ext)
+    {
+        if (ext.empty()) return;
+        for (auto &e : ext) e.second = (e.second + 255) & ~(int64_t)255;
+        std::sort(ext.begin(), ext.end());
+        int64_t off = ext[0].first, n = ext[0].second;
+        for (size_t i = 1; i < ext.size(); ++i) {
+            if (ext[i].first == off + n) {
+                n += ext[i].second;
+            } else {
+                release(off, n);
+                off = ext[i].first;
+                n = ext[i].second;
+            }
+        }
+        release(off, n);
+    }
     int64_t used() const { return used_; }
     int64_t peak() const { return peak_; }
     void reset_peak() { peak_ = used_; }
@@ -196,7 +217,7 @@ struct tdec_server {
     tdec_serve_stats st{};
     int64_t batch_tbs_sum = 0, batch_cbs_sum = 0;
     int64_t pre_sum = 0, coding_sum = 0, post_sum = 0;  // per-launch delays (ns)
-    std::vector<int64_t> lat;
+    std::deque<int64_t> lat;   // chunked: appending never moves what is stored
     std::vector<tdec_launch_rec> ring;  // last kLaunchRing launches
     int64_t ring_n = 0;                 // launches recorded since the last reset
     bool stop = false;
@@ -430,6 +451,8 @@ void retire_locked(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res
                    const int64_t lat3[5], int64_t t1)
 {
     const std::vector<Pending> &b = L.b;
+    std::vector<std::pair<int64_t, int64_t>> ext;
+    ext.reserve(b.size());
     for (size_t i = 0; i < b.size(); ++i) {
         tdec_server_result &r = res[i];
         r.tag = b[i].tag;
@@ -438,7 +461,7 @@ void retire_locked(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res
         r.batch_tbs = (int32_t)b.size();
         r.t_arrive_ns = b[i].t_arrive;
         r.t_done_ns = t1;
-        s->arena.release(b[i].slot_off, b[i].slot_bytes);
+        ext.emplace_back(b[i].slot_off, b[i].slot_bytes);
         if (r.status == TDEC_SERVE_DONE) {
             ++s->st.completed;
             s->st.payload_bits += r.tbs;
@@ -449,6 +472,7 @@ void retire_locked(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res
         }
         s->done.push_back(r);
     }
+    s->arena.release_many(ext);
     s->inflight -= (int64_t)b.size();
     ++s->st.batches;
     s->batch_tbs_sum += (int64_t)b.size();
@@ -591,7 +615,6 @@ tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
     s->arena.init((int64_t)s->cfg.slot_budget_bytes);
     s->m_lat = (double)(cfg->model_lat_ns ? cfg->model_lat_ns : 300000);
     s->m_npk = (double)(cfg->model_ns_per_kbit ? cfg->model_ns_per_kbit : 50);
-    s->lat.reserve(1 << 16);
     s->ring.resize((size_t)kLaunchRing);
     return TDEC_OK;
 }
@@ -714,6 +737,21 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
         std::lock_guard<std::mutex> lk(s->mu);
         const int64_t now = mono_ns();
         const int64_t deadline = t_arrive_ns + (int64_t)s->cfg.deadline_us * 1000;
+        // One extent for the whole call when every block is valid and it
+        // fits: the blocks take consecutive pieces of it, each released on
+        // its own later (and merged back); otherwise one extent per block.
+        int64_t big = -1, big_at = 0;
+        if (n > 1) {
+            int64_t tot = 0;
+            bool valid = true;
+            for (int32_t i = 0; i < n && valid; ++i) {
+                Segm g;
+                valid = seg_of(tbs[i], &g) && h_llr[i];
+                tot += (g.n_llr * 2 + 255) & ~(int64_t)255;
+            }
+            if (valid) big = s->arena.alloc(tot);
+        }
+        std::vector<std::pair<int64_t, int64_t>> unused;  // pieces of refused blocks
         for (int32_t i = 0; i < n; ++i) {
             ++s->st.submitted;
             Segm g;
@@ -723,8 +761,13 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 why = TDEC_SERVE_REJ_INVALID;
             } else {
                 bytes = g.n_llr * 2;
-                off = s->arena.alloc(bytes);
-                if (off < 0) why = TDEC_SERVE_REJ_BUDGET;
+                if (big >= 0) {
+                    off = big + big_at;
+                    big_at += (bytes + 255) & ~(int64_t)255;
+                } else {
+                    off = s->arena.alloc(bytes);
+                    if (off < 0) why = TDEC_SERVE_REJ_BUDGET;
+                }
             }
             if (why == TDEC_SERVE_DONE && (s->cfg.admission & TDEC_ADMIT_DEADLINE)) {
                 // the block joins the next launch after the running one (or
@@ -758,7 +801,7 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 // to the deadline a launch ends, and the prediction is noisy
                 if (busy && pred > limit - (int64_t)s->cfg.deadline_us * 100) {
                     why = TDEC_SERVE_REJ_DEADLINE;
-                    s->arena.release(off, bytes);
+                    unused.emplace_back(off, bytes);
                 }
             }
             if (why != TDEC_SERVE_DONE) {
@@ -786,6 +829,7 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
             adm.push_back(p);
             idx.push_back(i);
         }
+        s->arena.release_many(unused);
     }
     // (2) copies: host sources one asynchronous copy each, device sources
     // batched into gather launches; fail[k] marks blocks whose copy failed
@@ -868,13 +912,14 @@ tdec_status tdec_server_replay(tdec_server *s, int32_t n_ticks, int64_t t_first_
 {
     if (!s || n_ticks < 0 || period_ns <= 0 || (n_ticks && (!counts || !tbs || !d_llr)))
         return TDEC_EINVAL;
-    int64_t total = 0;
+    int32_t most = 1;
     for (int32_t k = 0; k < n_ticks; ++k) {
         if (counts[k] < 0) return TDEC_EINVAL;
-        total += counts[k];
+        most = std::max(most, counts[k]);
     }
-    std::vector<uint64_t> tags((size_t)std::max<int64_t>(total, 1));
-    for (int64_t i = 0; i < total; ++i) tags[(size_t)i] = tag_base + (uint64_t)i;
+    // one tick's tags at a time: nothing proportional to the whole schedule
+    // is built between the caller's clock reading and the first tick
+    std::vector<uint64_t> tags((size_t)most);
     int64_t late = 0, smax = 0, at = 0;
     for (int32_t k = 0; k < n_ticks; ++k) {
         const int64_t tick = t_first_ns + (int64_t)k * period_ns;
@@ -882,8 +927,9 @@ tdec_status tdec_server_replay(tdec_server *s, int32_t n_ticks, int64_t t_first_
         }
         late = std::max(late, mono_ns() - tick);
         if (counts[k]) {
+            for (int32_t j = 0; j < counts[k]; ++j) tags[(size_t)j] = tag_base + (uint64_t)(at + j);
             const int64_t t0 = mono_ns();
-            const int32_t r = submit_impl(s, counts[k], tags.data() + at, tbs + at, d_llr + at,
+            const int32_t r = submit_impl(s, counts[k], tags.data(), tbs + at, d_llr + at,
                                           h_bits ? h_bits + at : nullptr, tick, nullptr, true);
             if (r < 0) return (tdec_status)r;
             smax = std::max(smax, mono_ns() - t0);
@@ -926,7 +972,7 @@ tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out)
     {
         std::lock_guard<std::mutex> lk(s->mu);
         *out = s->st;
-        v = s->lat;
+        v.assign(s->lat.begin(), s->lat.end());
         out->model_lat_ns = (int64_t)s->m_lat;
         out->model_ns_per_kbit = (int64_t)s->m_npk;
         out->slots_in_use_bytes = s->arena.used();
