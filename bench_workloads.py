@@ -1057,10 +1057,13 @@ def run_cells(args):
 
 # ----------------------------------------------------------------------------- default-run checks
 # The cells count claimed for this decoder and the Es/N0 the cells workload
-# calibrated on 2048 TBs per point (TB error rate 0.27 at 10.585 dB); its
-# binary search finds 108-110 cells (2 launch lanes), right at saturation,
-# so the claim keeps a margin.  The uniform bench re-checks it briefly.
-CELLS_CLAIMED = 105
+# calibrated on 2048 TBs per point (TB error rate 0.27 at 10.585 dB).  Its
+# binary search finds 108-110 cells (2 launch lanes) on most devices, right
+# at saturation; at 105 cells (97 % of that) a stall of a few milliseconds
+# has been seen to tip the loop into 2.5 ms launches whose backlog spoils the
+# p99, so the claim keeps a margin of about 8 %.  The uniform bench re-checks
+# it briefly.
+CELLS_CLAIMED = 100
 CELLS_ESN0_DB = 10.585
 
 
