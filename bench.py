@@ -227,8 +227,9 @@ def main():
     ap.add_argument("--rho", type=str, default="0.25,0.5,1,2,4",
                     help="serving: load points (fractions of 40 cells' capacity)")
     ap.add_argument("--ttis", type=int, default=3000, help="serving/cells: measured TTIs")
-    ap.add_argument("--mode", default="continuous", choices=["continuous", "per-tb"],
-                    help="serving: batching form")
+    ap.add_argument("--mode", default="continuous", choices=["continuous", "per-tb", "ring"],
+                    help="serving/cells: batching form (ring: one persistent kernel fed from a "
+                         "work ring)")
     ap.add_argument("--min-w", type=int, default=0,
                     help="mixed/serving/cells: shortest window the autotuner may choose, in steps "
                          "(0: 32 for the mixed TTIs, 64 for serving and cells)")

@@ -679,14 +679,15 @@ class Checker:
 
 
 def serve(T, D, torch, pool_llr_ptr, pool_tbs, lam_fn, n_ttis, warm, mode, admission,
-          deadline_us=3000, budget=8 << 30, seed=0, checker=None, max_inflight=0):
+          deadline_us=3000, budget=8 << 30, seed=0, checker=None, max_inflight=0, ring=False):
     """Drive the serving loop with arrivals from lam_fn(rng) -> pool indices
     per TTI, submitted by the library's native load generator (one batch per
     1 ms tick, no Python between ticks); returns the stats of the measured
     TTIs (with `checker`, their results are checked against the oracle's)."""
     cfg = T.server_cfg(T.params(8, 1, 0, 1) if mode != "cells" else T.params(8, 0, 0, 1),
                        deadline_us=deadline_us, slot_budget_bytes=budget,
-                       mode=T.SERVE_PER_TB if mode == "per-tb" else T.SERVE_CONTINUOUS,
+                       mode=(T.SERVE_PER_TB if mode == "per-tb" else
+                             T.SERVE_RING if ring else T.SERVE_CONTINUOUS),
                        admission=admission, max_inflight=max_inflight)
     rng = np.random.default_rng(seed)
     # the whole schedule, drawn before the clock starts
@@ -849,6 +850,8 @@ def serving_setup(args):
     # 64 steps cost more in throughput than they save in latency
     tune_windows(D, args, [k for t in set(ptbs.tolist()) for k, _ in T.cb_sizes(int(t))], 8,
                  default_min_w=64)
+    if args.mode == "ring":
+        D.set_max_windows(64)  # the ring kernel's limit, so the checker sees its choices
     cpu, checker = pool_checker(args, D, llr_h, lo_h, ptbs, 8, 1, "serving")
     lam1 = SERVING_CELLS * MAX_TB / float(np.mean(ptbs))  # TBs per TTI at rho = 1
     return D, pool, cpu, checker, lam1
@@ -862,7 +865,7 @@ def serving_row(args, D, pool, checker, lam1, rho, ttis):
     s = serve_checked("serving", T, D, torch, ptrs, ptbs,
                       lambda r: r.integers(0, len(ptbs), r.poisson(lam)),
                       ttis, 300, args.mode, T.ADMIT_BUDGET | T.ADMIT_DEADLINE,
-                      checker=checker, max_inflight=args.inflight)
+                      checker=checker, max_inflight=args.inflight, ring=args.mode == "ring")
     row = {"rho": rho, "tb_per_tti": round(lam, 1),
            "offered_gbit_s": round(lam * mean_tbs / 1e6, 3),
            "served_gbit_s": round(s["payload_bits"] / s["wall_s"] / 1e9, 3),
@@ -914,6 +917,8 @@ def cells_decoder(args):
     before any calibration: windows change error rates)."""
     D = T.Decoder(0, 2 << 30)
     tune_windows(D, args, [5824], 8, batch_bits=CELLS_TUNE_CBS * 5824, default_min_w=64)
+    if args.mode == "ring":
+        D.set_max_windows(64)
     return D
 
 
@@ -995,7 +1000,8 @@ def cells_trial(args, D, pool, checker, n_cells, ttis):
     _, ptbs, ptrs, _, _, _, _ = pool
     s = serve_checked("cells", T, D, torch, ptrs, ptbs,
                       lambda r: r.integers(0, len(ptbs), 2 * n_cells), ttis, 200,
-                      "cells", T.ADMIT_BUDGET, checker=checker, max_inflight=args.inflight)
+                      "cells", T.ADMIT_BUDGET, checker=checker, max_inflight=args.inflight,
+                      ring=args.mode == "ring")
     okk = s["lat_p99_ns"] <= 3_000_000 and s["rej_budget"] == 0
     okk = okk and (s.get("parity") is None or
                    (s["parity"]["flag_or_iteration_mismatches"] == 0 and
@@ -1051,7 +1057,7 @@ def run_cells(args):
             "calibration": {"esn0_db": esn0, "tb_error_rate": round(bler, 4),
                             "tbs_per_point": CELLS_CAL_TBS, "points": pts},
             "at_best": cells_summary(s),
-            "cpu_baseline": cpu, "max_inflight": args.inflight,
+            "cpu_baseline": cpu, "max_inflight": args.inflight, "mode": args.mode,
             "pool_h2d_gbit_s": round(8 * pool[4], 1)}
 
 

@@ -160,6 +160,13 @@ void tdec_destroy(tdec_ctx *ctx);
  * tdec_params.n_windows == 0 (always a valid count for K). */
 int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K);
 
+/* Limit the library's window choice (tuned or built in) to at most max_nw
+ * windows per code block, 1..128, or lift the limit (0): a larger choice
+ * becomes the most windows <= max_nw that are valid for K.  The serving
+ * loop's ring mode decodes with at most 64 (tdec_server.h).  EINVAL for a
+ * value out of range. */
+tdec_status tdec_set_max_windows(tdec_ctx *ctx, int32_t max_nw);
+
 /* ---------------------------------------------------------------- decoding */
 
 /* One code block of a batch.

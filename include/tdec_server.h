@@ -43,6 +43,27 @@
  * with the same workspace budget and window choices, so tune the context's
  * windows before creating the server).
  *
+ * Ring mode (TDEC_SERVE_RING): the dispatcher does not launch a decode
+ * kernel per batch.  One persistent decode kernel stays resident while work
+ * arrives, and every batch is appended to a work ring in pinned host memory
+ * as it is taken (up to max_inflight batches in flight): the batch is
+ * planned, its plan uploaded, and its work items (1-64 code blocks of one
+ * size each) published by advancing the ring's tail.  A work group of the
+ * kernel that has finished an item claims the next published one through a
+ * device counter, so blocks that arrive while the kernel runs start as soon
+ * as a work group is free, with no launch and no host round trip between
+ * them and the work already running.  Each item's work group marks it done
+ * in host memory after its outputs; once all items of a batch are done the
+ * completer assembles its transport blocks (a small kernel in slots the ring
+ * kernel leaves free) and hands the results back.  Every wait of the kernel
+ * is bounded: a work group with nothing to claim leaves after ring_idle_us,
+ * or at once when the server is destroyed, and the kernel is launched again
+ * when work arrives after it has ended.  This mode decodes with window
+ * boundaries from the previous iteration or none (win_init 0 or 1), without
+ * the mutual-information stop, and with at most 64 windows per block (the
+ * context's window choices are capped there; n_windows must be 0 or <= 64);
+ * other configurations are rejected with EINVAL.
+ *
  * Modelled executor: tdec_server_create_model runs the same queueing,
  * admission, batching and statistics with no device at all.  Its device runs
  * the launches' work one after another at ns_per_kbit per 1000 code block
@@ -66,7 +87,8 @@ extern "C" {
 
 enum {
     TDEC_SERVE_CONTINUOUS = 0, /* decode everything waiting as one launch whenever a lane is free */
-    TDEC_SERVE_PER_TB = 1      /* one launch per TB in arrival order (the plain form, for comparison) */
+    TDEC_SERVE_PER_TB = 1,     /* one launch per TB in arrival order (the plain form, for comparison) */
+    TDEC_SERVE_RING = 2        /* one persistent decode kernel fed from a work ring (see below) */
 };
 enum { TDEC_ADMIT_BUDGET = 1, TDEC_ADMIT_DEADLINE = 2 };
 enum {
@@ -86,9 +108,13 @@ typedef struct {
     int64_t model_lat_ns;     /* service model prior: duration of a small launch */
     int64_t model_ns_per_kbit;/* service model prior: ns per 1000 code block bits */
     tdec_params params;       /* decoder parameters of every launch */
-    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2); the
-                                 per-TB mode always runs one at a time */
-    int32_t rsv;
+    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2; ring
+                                 mode: batches in flight, 0 = 4); the per-TB
+                                 mode always runs one at a time */
+    int32_t ring_idle_us;     /* ring mode: the ring kernel ends once its work
+                                 groups have found nothing to claim for this
+                                 long (0 = 20000, at most 10^7); the next
+                                 batch launches it again */
 } tdec_server_cfg;
 
 typedef struct {
@@ -117,6 +143,8 @@ typedef struct {
      * post-processing (transport block assembly, copies back, copy-out) */
     int64_t mean_pre_ns, mean_coding_ns, mean_post_ns;
     double mean_batch_tbs, mean_batch_cbs;
+    int64_t ring_launches;     /* ring mode: launches of the ring kernel since creation */
+    int64_t ring_grid;         /* ring mode: work groups of the ring kernel */
 } tdec_serve_stats;
 
 /* One launch of the serving loop, as the paper's performance captor

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtdec.so")
 CRC_NONE, CRC24A, CRC24B = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EDEVICE", -5: "EBUSY"}
 EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tdec_create",
-           "tdec_destroy", "tdec_pick_windows", "cb_decode_batch", "cb_decode_batch_fixed",
+           "tdec_destroy", "tdec_pick_windows", "tdec_set_max_windows", "cb_decode_batch", "cb_decode_batch_fixed",
            "tb_decode", "tb_decode_batch",
            "cb_encode_batch", "tb_encode", "tdec_now_ns", "tdec_server_create",
            "tdec_server_create_model", "tdec_server_submit", "tdec_server_poll",
@@ -32,7 +32,7 @@ EXPORTS = ("tdec_segment", "tdec_tb_llr_count", "tdec_k_table", "tdec_qpp", "tde
            "tdec_probe_launch", "tdec_server_replay", "tdec_default_knobs", "tdec_set_knobs",
            "tdec_get_knobs", "tdec_autotune_batch")
 ORDER_K_DESC, ORDER_K_ASC, ORDER_REQUEST = 0, 1, 2
-SERVE_CONTINUOUS, SERVE_PER_TB = 0, 1
+SERVE_CONTINUOUS, SERVE_PER_TB, SERVE_RING = 0, 1, 2
 ADMIT_BUDGET, ADMIT_DEADLINE = 1, 2
 SERVE_DONE, SERVE_REJ_BUDGET, SERVE_REJ_DEADLINE, SERVE_REJ_INVALID, SERVE_ERROR = 0, 1, 2, 3, 4
 
@@ -71,7 +71,7 @@ class ServerCfg(ct.Structure):
     _fields_ = [("slot_budget_bytes", ct.c_size_t), ("deadline_us", ct.c_int32),
                 ("max_batch_cb", ct.c_int32), ("mode", ct.c_int32), ("admission", ct.c_int32),
                 ("model_lat_ns", ct.c_int64), ("model_ns_per_kbit", ct.c_int64),
-                ("params", Params), ("max_inflight", ct.c_int32), ("rsv", ct.c_int32)]
+                ("params", Params), ("max_inflight", ct.c_int32), ("ring_idle_us", ct.c_int32)]
 
 
 class ServeResult(ct.Structure):
@@ -87,7 +87,8 @@ class ServeStats(ct.Structure):
         "lat_p99_ns", "lat_p999_ns", "lat_max_ns", "lat_mean_ns", "model_lat_ns",
         "model_ns_per_kbit", "slots_in_use_bytes", "slots_peak_bytes", "mean_pre_ns",
         "mean_coding_ns", "mean_post_ns")] + [
-        ("mean_batch_tbs", ct.c_double), ("mean_batch_cbs", ct.c_double)]
+        ("mean_batch_tbs", ct.c_double), ("mean_batch_cbs", ct.c_double),
+        ("ring_launches", ct.c_int64), ("ring_grid", ct.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -154,6 +155,7 @@ def lib():
         L.tdec_destroy.argtypes = [vp]
         L.tdec_destroy.restype = None
         L.tdec_pick_windows.argtypes = [vp, i32]
+        L.tdec_set_max_windows.argtypes = [vp, i32]
         L.cb_decode_batch.argtypes = [vp, i32, vp, vp, P(Params), vp, vp, vp, vp]
         L.cb_decode_batch_fixed.argtypes = [vp, i32, vp, vp, P(Params), vp, vp, vp, vp]
         L.tb_decode.argtypes = [vp, vp, i32, P(Params), vp, vp, vp]
@@ -373,6 +375,10 @@ class Decoder:
     def pick_windows(self, K: int) -> int:
         return int(lib().tdec_pick_windows(self._h, int(K)))
 
+    def set_max_windows(self, max_nw: int):
+        """Limit the window choice to at most max_nw per block (0: no limit)."""
+        _check("tdec_set_max_windows", lib().tdec_set_max_windows(self._h, int(max_nw)))
+
     def cb_decode_batch(self, descs, llr, p: Params, bits=None, crc_ok=None, iters=None,
                         stream=None):
         """llr: int16 CUDA tensor; bits: uint8 CUDA tensor or None; crc_ok /
@@ -585,9 +591,9 @@ def now_ns() -> int:
 
 def server_cfg(params: Params, deadline_us=3000, slot_budget_bytes=0, max_batch_cb=0,
                mode=SERVE_CONTINUOUS, admission=ADMIT_BUDGET, model_lat_ns=0,
-               model_ns_per_kbit=0, max_inflight=0) -> ServerCfg:
+               model_ns_per_kbit=0, max_inflight=0, ring_idle_us=0) -> ServerCfg:
     return ServerCfg(slot_budget_bytes, deadline_us, max_batch_cb, mode, admission,
-                     model_lat_ns, model_ns_per_kbit, params, max_inflight, 0)
+                     model_lat_ns, model_ns_per_kbit, params, max_inflight, ring_idle_us)
 
 
 class Server:

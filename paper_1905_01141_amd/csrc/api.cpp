@@ -94,6 +94,7 @@ struct tdec_ctx {
     int item_order = TDEC_ORDER_K_DESC;  // order of the work items (TDEC_ORDER_*)
     int grid_cap = 0;            // 0: occupancy-derived persistent grid
     int launch_reserve = 0;      // resident slots a launch leaves free (launch lanes)
+    int max_nw = 0;              // most windows per block (0 = no limit; the ring kernel's shape)
     bool small_asm = false;      // transport block assembly in kAsmGrid small work groups
 };
 
@@ -112,18 +113,23 @@ int32_t pick_windows(int32_t K)
     return best;
 }
 
-int32_t ctx_windows(const tdec_ctx *ctx, int32_t K)
-{
-    const int i = k_index(K);
-    if (ctx && i >= 0 && ctx->tuned_nw[i] > 0) return ctx->tuned_nw[i];
-    return pick_windows(K);
-}
-
 bool windows_ok(int32_t K, int32_t nw)
 {
     if (nw < 1 || nw > kMaxWgThreads / 2) return false;
     const int32_t W = win_len(K, nw);
     return W > 0 && W % kSeg == 0 && (K - (nw - 1) * W) % kSeg == 0;
+}
+
+int32_t ctx_windows(const tdec_ctx *ctx, int32_t K)
+{
+    const int i = k_index(K);
+    int32_t nw = ctx && i >= 0 && ctx->tuned_nw[i] > 0 ? ctx->tuned_nw[i] : pick_windows(K);
+    // a window limit takes the most windows it allows (one always does)
+    if (ctx && ctx->max_nw > 0 && nw > ctx->max_nw) {
+        nw = ctx->max_nw;
+        while (nw > 1 && !windows_ok(K, nw)) --nw;
+    }
+    return nw;
 }
 
 struct CbReq {
@@ -192,7 +198,9 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
     const int64_t key = (int64_t)K * 1024 + nw;
     auto f = ctx->qtab_off.find(key);
     if (f != ctx->qtab_off.end()) return f->second;
-    const size_t ne = qtab_entries(K, nw), n = (ne + 7) & ~(size_t)7;
+    // tables start on 128-byte lines: a table added while a persistent
+    // kernel runs shares no cache line with the tables it has read
+    const size_t ne = qtab_entries(K, nw), n = (ne + 63) & ~(size_t)63;
     if (ctx->qtab_used + n > ctx->qtab_cap) return -1;
     const int64_t off = (int64_t)ctx->qtab_used;
     qtab_fill(K, nw, ctx->h_qtab + off);
@@ -202,6 +210,16 @@ int64_t qtab_get(tdec_ctx *ctx, int32_t K, int32_t nw, hipStream_t st)
     ctx->qtab_used += n;
     ctx->qtab_off[key] = off;
     return off;
+}
+
+// Global scratch bytes of one work item of `lanes` windows of W steps:
+// restaged inputs, checkpoints, boundaries, and with exact boundaries the
+// transfer runs (2 directions x 8 states x 32 bytes per lane).
+int64_t item_scratch(int lanes, int W, bool exact)
+{
+    const int64_t need = (int64_t)lanes * W * 6 + (int64_t)(W / kSeg) * lanes * 16 +
+                         (int64_t)4 * lanes * 16 + (exact ? (int64_t)lanes * 512 : 0) + 256;
+    return (need + 255) & ~(int64_t)255;
 }
 
 // Build the decode plan (items + code block list) from a request.
@@ -296,12 +314,7 @@ tdec_status build_decode_plan(tdec_ctx *ctx, std::vector<CbReq> &reqs, PlanSlot 
         uneven = uneven || (int64_t)nw * W != K;
         lds = std::max(lds, n * sb);
         max_n = std::max(max_n, n);
-        const int lanes = n * nw;
-        // restaged inputs, checkpoints, boundaries, and with exact boundaries
-        // the transfer runs (2 directions x 8 states x 32 bytes per lane)
-        const int64_t need = (int64_t)lanes * W * 6 + (int64_t)(W / kSeg) * lanes * 16 +
-                             (int64_t)4 * lanes * 16 + (exact ? (int64_t)lanes * 512 : 0) + 256;
-        stride = std::max(stride, (need + 255) & ~(int64_t)255);
+        stride = std::max(stride, item_scratch(n * nw, W, exact));
     }
     lds += lds_state_bytes(max_n) + (mi ? lds_mi_bytes(max_n) : 0);
     // persistent grid: as many work groups as can be resident
@@ -788,6 +801,95 @@ void tdec::ctx_set_launch_reserve(tdec_ctx *ctx, int n, bool small_asm)
     ctx->small_asm = small_asm;
 }
 
+void tdec::ctx_set_ring_shape(tdec_ctx *ctx, int max_nw, int lds_budget)
+{
+    if (!ctx) return;
+    ctx->max_nw = std::max(0, max_nw);
+    ctx->lds_budget = std::max(1, lds_budget);
+    ++ctx->tune_gen;
+}
+
+tdec_status tdec::ring_plan(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
+                            const int64_t *bits_off, const tdec_params *params, hipStream_t st,
+                            RingPlan *out)
+{
+    if (!ctx || !out || n_tb <= 0 || !tbs || !llr_off || !params_ok(params)) return TDEC_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TDEC_EDEVICE;
+    const std::string key = tb_key(n_tb, tbs, llr_off, bits_off, params, ctx->tune_gen);
+    bool hit;
+    PlanSlot *ps = lookup(ctx, key, &hit);
+    if (!hit) {
+        std::vector<CbReq> reqs;
+        std::vector<TbItem> tbl;
+        tdec_status s = make_tb_reqs(ctx, n_tb, tbs, llr_off, bits_off, params, reqs, tbl);
+        if (s != TDEC_OK) return s;
+        std::vector<char> blob;
+        s = build_decode_plan(ctx, reqs, *ps, blob, &tbl, st, params->win_init == 2,
+                              (params->early_stop & 2) != 0, ctx->scratch_bytes);
+        if (s == TDEC_OK) s = upload(ctx, ps, key, blob, st);
+        if (s != TDEC_OK) {
+            ps->key.clear();
+            return s;
+        }
+    }
+    RingPlan &r = *out;
+    r.items = (const DecItem *)(ps->h_buf + ps->off_items);
+    r.n_items = ps->n_items;
+    r.d_cbs = (const DecCb *)(ps->d_buf + ps->off_cbs);
+    r.n_cb = ps->n_cb;
+    r.d_tbs = (const TbItem *)(ps->d_buf + ps->off_tbs);
+    r.n_tb = ps->n_tb;
+    r.asm_words = ps->asm_words;
+    r.wg = ps->wg;
+    r.max_item_lds = 0;
+    for (int i = 0; i < ps->n_items; ++i)
+        r.max_item_lds = std::max(r.max_item_lds, r.items[i].ncb * r.items[i].lds_slot);
+    r.stride = ps->stride;
+    r.exact = ps->exact;
+    r.mi = ps->mi;
+    r.ready = ps->ev;
+    r.d_qtab = ctx->d_qtab;
+    r.qtab_entries = (int64_t)ctx->qtab_used;
+    r.d_hard = ctx->d_hard;
+    r.hard_words = (int64_t)ctx->hard_words_cap;
+    r.d_ok = ctx->d_ok;
+    r.d_it = ctx->d_it;
+    r.flags = (int64_t)ctx->flags_cap;
+    return TDEC_OK;
+}
+
+tdec_status tdec::ring_assemble(tdec_ctx *ctx, const RingPlan &r, const tdec_params *params,
+                                uint8_t *d_bits, tdec_tb_result *d_res, hipStream_t st)
+{
+    if (!ctx || !d_res || !params_ok(params)) return TDEC_EINVAL;
+    if (launch_tb_assemble(r.d_tbs, r.n_tb, r.asm_words, ctx->d_hard, ctx->d_ok, ctx->d_it, nullptr,
+                           ctx->d_crc_tab, d_bits, d_res, true, st))
+        return TDEC_EDEVICE;
+    return TDEC_OK;
+}
+
+int64_t tdec::ring_max_stride(int max_nw, int lds_budget)
+{
+    // every size, every window count a plan may use, as many blocks per
+    // item as the planner packs (see build_decode_plan)
+    int64_t m = 0;
+    for (int i = 0; i < kNumK; ++i) {
+        const int32_t K = k_of_index(i);
+        for (int nw = 1; nw <= max_nw; ++nw) {
+            if (!windows_ok(K, nw)) continue;
+            const int half = ((nw + 63) / 64) * 64;
+            int cap = std::min(half / nw, kMaxSlotsPerWg);
+            cap = std::min(cap, std::max(1, lds_budget / lds_slot_bytes(K)));
+            m = std::max(m, item_scratch(cap * nw, win_len(K, nw), false));
+        }
+    }
+    return m;
+}
+
+const uint32_t *tdec::ctx_crc_tab(const tdec_ctx *ctx) { return ctx ? ctx->d_crc_tab : nullptr; }
+
+int tdec::ctx_num_cus(const tdec_ctx *ctx) { return ctx ? ctx->num_cus : 0; }
+
 tdec_status tdec::ctx_clone(const tdec_ctx *src, tdec_ctx **out)
 {
     if (!src || !out) return TDEC_EINVAL;
@@ -797,12 +899,21 @@ tdec_status tdec::ctx_clone(const tdec_ctx *src, tdec_ctx **out)
     c->lds_budget = src->lds_budget;
     c->item_order = src->item_order;
     c->grid_cap = src->grid_cap;
+    c->max_nw = src->max_nw;
     for (int i = 0; i < kNumK; ++i) c->tuned_nw[i] = src->tuned_nw[i];
     ++c->tune_gen;
     return TDEC_OK;
 }
 
 extern "C" {
+
+tdec_status tdec_set_max_windows(tdec_ctx *ctx, int32_t max_nw)
+{
+    if (!ctx || max_nw < 0 || max_nw > kMaxWgThreads / 2) return TDEC_EINVAL;
+    ctx->max_nw = max_nw;
+    ++ctx->tune_gen;
+    return TDEC_OK;
+}
 
 int32_t tdec_pick_windows(const tdec_ctx *ctx, int32_t K)
 {

@@ -707,9 +707,26 @@ __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, 
 // 8-byte aligned, else four 2-byte loads.  The channel LLRs are read once per
 // launch, so the loads are non-temporal: they do not displace the restaged
 // inputs and checkpoints that the iterations re-read from the caches.
+// SYS (the ring kernel): system-scope loads instead, which read the LLRs
+// from memory whatever this XCD's cache holds -- the ring kernel runs while
+// the host and other kernels rewrite the LLR slots.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <bool SYS = false>
 __device__ __forceinline__ uint2 load4(const int16_t *p, bool aligned)
 {
+    if constexpr (SYS) {
+        if (aligned) {
+            const unsigned long long v = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_SYSTEM);
+            return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+        }
+        uint32_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            h[j] = __hip_atomic_load((const unsigned short *)(p + j), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_SYSTEM);
+        return make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
     if (aligned) {
         const u32x2_t v = __builtin_nontemporal_load((const u32x2_t *)p);
         return make_uint2(v.x, v.y);
@@ -775,6 +792,7 @@ __device__ __forceinline__ int restage_rows(int tile_words, int nw, int W)
 // consecutive threads on consecutive windows (rows of R uint2 plus one of
 // padding).  Direct form (R = 0): consecutive threads take consecutive
 // windows.  Every thread of the work group calls it (it holds barriers).
+template <bool SYS>
 __device__ void restage_block(const int16_t *src, int K, int F, int nw, int W, int lanes,
                               int lane0, uint4 *R1v, uint2 *R2v, uint2 *tile, int R, int tid,
                               int nthr)
@@ -798,7 +816,7 @@ __device__ void restage_block(const int16_t *src, int K, int F, int nw, int W, i
                         const int ww = e >> lg, j = e & (R - 1);
                         const int p = ww * W + c0 + 4 * j;
                         v[st][m] = make_uint2(0u, 0u);
-                        if (e < nl && j < Rc && p < K) v[st][m] = load4(src + st * N + p, aligned);
+                        if (e < nl && j < Rc && p < K) v[st][m] = load4<SYS>(src + st * N + p, aligned);
                     }
 #pragma unroll
                 for (int st = 0; st < 3; ++st)
@@ -833,7 +851,7 @@ __device__ void restage_block(const int16_t *src, int K, int F, int nw, int W, i
                 const int p = ww * W + 4 * t4;
 #pragma unroll
                 for (int st = 0; st < 3; ++st)
-                    v[m][st] = p < K ? load4(src + st * N + p, aligned) : make_uint2(0u, 0u);
+                    v[m][st] = p < K ? load4<SYS>(src + st * N + p, aligned) : make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -847,8 +865,97 @@ __device__ void restage_block(const int16_t *src, int K, int F, int nw, int W, i
     }
 }
 
-template <bool UNEVEN, bool EXACT, bool MI>
-__global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs a)
+// Ring mode, thread 0: take a ticket and wait until the item of that number
+// is published.  Tickets come from one fetch-and-add (ring_head[0]), so a
+// burst of claims costs one atomic each.  Only the holder of the first
+// unpublished ticket looks at the host's tail (and stop flag) over the bus,
+// and mirrors what it sees into device memory (ring_head[16], ring_head[32])
+// for the others.  The wait is bounded: it ends when the item is published,
+// when the server stops, or after ring_idle_ticks of the wall clock (the
+// ticket is then abandoned: the host, which stops the kernel itself long
+// before that, rewinds the counter before the next launch).  A rewound
+// counter hands out items that are done already: they are skipped.
+// Returns the item's ring index, or -1 when the work group is to leave.
+__device__ long long ring_claim(const RingArgs &a)
+{
+    unsigned long long *seen = a.head + 16;            // own 128-byte line
+    unsigned int *stopm = (unsigned int *)(a.head + 32);
+    for (;;) {
+        const unsigned long long t = __hip_atomic_fetch_add(a.head, 1ull, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        int nap = 0;
+        for (;;) {
+            const unsigned long long m = __hip_atomic_load(seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t < m) break;
+            const bool lead = t == m;
+            if (lead) {
+                const unsigned long long x =
+                    __hip_atomic_load(&a.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (x > m) {
+                    __hip_atomic_fetch_max(seen, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (t < x) break;
+                }
+                if (__hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                    __hip_atomic_store(stopm, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (__hip_atomic_load(stopm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
+            if ((uint64_t)wall_clock64() - t0 > a.idle_ticks) return -1;
+            // back off: 2^nap naps of 8 x 64 clocks, up to about 1 us for
+            // the ticket holder that watches the host, 3.5 us for the others
+            for (int k = 0; k < (1 << nap); ++k) __builtin_amdgcn_s_sleep(8);
+            nap = min(nap + 1, lead ? 2 : 4);
+        }
+        if (__hip_atomic_load(&a.done[t & (unsigned long long)(a.cap - 1)], __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM) != (uint32_t)t + 1u)
+            return (long long)t;
+    }
+}
+
+// Ring mode, whole work group: claim an item and copy its entry (host
+// memory) and its code blocks (device memory) into LDS at `ent`.  Returns
+// the item's ring index, or -1 when the work group is to leave.
+//
+// Everything an item reads that someone else may have rewritten while the
+// kernel runs -- its entry, its plan's code block list (uploaded by the
+// host), the LLRs of its blocks (copied into reused slots) -- is read with
+// system-scope loads, which go to memory past any stale copy in this XCD's
+// cache; the host publishes an item only after all of it is in memory.  The
+// QPP tables are only ever appended, on cache lines of their own, so no
+// cache holds an old copy of a table the kernel has not read yet.
+__device__ long long ring_take(const RingArgs &a, RingEntry *ent, int tid, int nthr)
+{
+    __shared__ long long s_claim;
+    if (tid == 0) s_claim = ring_claim(a);
+    __syncthreads();
+    const long long i = s_claim;
+    if (i < 0) return -1;
+    constexpr int ew = (int)(sizeof(RingEntry) / 4);
+    const uint32_t *src = (const uint32_t *)(a.ent + (i & (a.cap - 1)));
+    if (tid < ew)
+        ((uint32_t *)ent)[tid] = __hip_atomic_load(src + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+    constexpr int cw = (int)(sizeof(DecCb) / 4);
+    const int n = min(max(ent->item.ncb, 0), kMaxSlotsPerWg) * cw;
+    const uint32_t *cs = (const uint32_t *)ent->cbs;
+    uint32_t *dst = (uint32_t *)(ent + 1);
+    for (int q = tid; q < n; q += nthr)
+        dst[q] = __hip_atomic_load(cs + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+    return i;
+}
+
+// Kernel arguments: DecArgs, and for the ring kernel RingArgs after them.
+template <bool RING>
+struct KernArgs : DecArgs {
+};
+template <>
+struct KernArgs<true> : DecArgs {
+    RingArgs ring;
+};
+
+template <bool UNEVEN, bool EXACT, bool MI, bool RING = false>
+__global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(KernArgs<RING> a)
 {
     // dynamic LDS: per-slot state (CRC, done, iterations, ok) for the most
     // blocks an item of this launch holds; with MI the entropy table and the
@@ -888,8 +995,29 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
     uint32_t *ctr_item = a.counter + xc * kCtrStride;
     uint32_t *ctr_done = a.counter + (kCtrSets + xc) * kCtrStride;
     __shared__ int s_next;
-    for (int item_i = blockIdx.x; item_i < a.n_items; item_i = s_next) {
-        const DecItem it = a.items[item_i];
+    // Ring mode: items are claimed from the host's ring instead, and each
+    // claimed item is copied into LDS after the extrinsic arrays.
+    RingEntry *r_ent = nullptr;
+    long long ring_i = -1;
+    if constexpr (RING) {
+        r_ent = (RingEntry *)(lds_all + a.ring.lds);
+        ring_i = ring_take(a.ring, r_ent, tid, nthr);
+    }
+    for (int item_i = blockIdx.x; RING ? ring_i >= 0 : item_i < a.n_items; item_i = RING ? 0 : s_next) {
+        // the item, block i of it, its QPP tables and outputs: from the ring
+        // entry's copy in ring mode, else from the plan and the arguments
+        const DecItem it = [&] {
+            if constexpr (RING) return r_ent->item;
+            else return a.items[item_i];
+        }();
+        const auto cbat = [&](int i) -> DecCb {
+            if constexpr (RING) return ((const DecCb *)(r_ent + 1))[i];
+            else return a.cbs[it.cb0 + i];
+        };
+        const uint16_t *qtab = RING ? r_ent->qtab : a.qtab;
+        uint32_t *o_hard = RING ? r_ent->hard : a.hard;
+        uint8_t *o_ok = RING ? r_ent->crc_ok : a.crc_ok;
+        uint8_t *o_it = RING ? r_ent->iters : a.iters;
         const int K = it.K, nw = it.nw, W = it.W, ncb = it.ncb;
         const int lanes = ncb * nw;
         // global scratch of this item: restaged inputs of both decoders,
@@ -911,8 +1039,8 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
             uint2 *R2v = (uint2 *)R2;
             const int R = restage_rows((ncb * it.lds_slot) / 8, nw, W);
             for (int cs = 0; cs < ncb; ++cs) {
-                const DecCb cb = a.cbs[it.cb0 + cs];
-                restage_block(a.llr + cb.llr_off, K, cb.F, nw, W, lanes, cs * nw, R1v, R2v,
+                const DecCb cb = cbat(cs);
+                restage_block<RING>(a.llr + cb.llr_off, K, cb.F, nw, W, lanes, cs * nw, R1v, R2v,
                               (uint2 *)lds, R, tid, nthr);
             }
             __syncthreads();  // the tile's last reads come before the clear
@@ -932,7 +1060,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         const bool active = wi < lanes;
         const int cs = active ? wi / nw : 0;
         const int w = active ? wi - cs * nw : 0;
-        const DecCb cb = a.cbs[it.cb0 + cs];
+        const DecCb cb = cbat(cs);
         Win c;
         // every window has W steps but the last, which has the rest of K
         c.W = (UNEVEN && w == nw - 1) ? K - (nw - 1) * W : W;
@@ -943,7 +1071,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         c.first = w == 0;
         c.last = w == nw - 1;
         c.E = (short *)(lds + (int64_t)cs * it.lds_slot);
-        c.qt = (const uint2 *)(a.qtab + it.qtab) + w;
+        c.qt = (const uint2 *)(qtab + it.qtab) + w;
         c.qs = nw;
         c.ck = ck;
         c.mit = s_mit;
@@ -954,11 +1082,17 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
         if (active && c.last && bwd_first) {
             const int16_t *src = a.llr + cb.llr_off;
             const int N = K + 4;
+            const auto ld = [&](int q) -> int {
+                if constexpr (RING)
+                    return (short)__hip_atomic_load((const unsigned short *)(src + q), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM);
+                return src[q];
+            };
             for (int d = 0; d < 2; ++d) {
                 const int o = K + 2 * d;
-                const int lx0 = clamp_llr(src[o]), lz0 = clamp_llr(src[N + o]),
-                          lx1 = clamp_llr(src[2 * N + o]), lz1 = clamp_llr(src[o + 1]),
-                          lx2 = clamp_llr(src[N + o + 1]), lz2 = clamp_llr(src[2 * N + o + 1]);
+                const int lx0 = clamp_llr(ld(o)), lz0 = clamp_llr(ld(N + o)),
+                          lx1 = clamp_llr(ld(2 * N + o)), lz1 = clamp_llr(ld(o + 1)),
+                          lx2 = clamp_llr(ld(N + o + 1)), lz2 = clamp_llr(ld(2 * N + o + 1));
                 short v[8];
                 for (int s = 0; s < 8; ++s) {
                     const int s1 = (s >> 2) & 1, s2b = (s >> 1) & 1, s3 = s & 1;
@@ -1034,7 +1168,7 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                             }
                         } else {
                             // beta at the end of windows nw-2 .. 0, from the termination
-                            const int16_t *src = a.llr + a.cbs[it.cb0 + cg].llr_off;
+                            const int16_t *src = a.llr + cbat(cg).llr_off;
                             const int N = K + 4, o = K + 2 * (dec - 1);
                             const int lx0 = clamp_llr(src[o]), lz0 = clamp_llr(src[N + o]),
                                       lx1 = clamp_llr(src[2 * N + o]), lz1 = clamp_llr(src[o + 1]),
@@ -1168,8 +1302,8 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
                     out[bb] = (uint8_t)(byte & (0xFFu << (8 - valid)));
                 }
             }
-            if (cb.hard_off >= 0 && a.hard) {
-                uint32_t *h = a.hard + cb.hard_off;
+            if (cb.hard_off >= 0 && o_hard) {
+                uint32_t *h = o_hard + cb.hard_off;
                 const int hw = (int)hard_words(K);
                 for (int q = w; q < hw; q += nw) {
                     // K is a multiple of 8: a group of 8 is all inside or all past K
@@ -1177,28 +1311,54 @@ __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(DecArgs 
 #pragma unroll
                     for (int k = 0; k < 32; k += 8)
                         v = (v << 8) | (32 * q + k < K ? hard8(c.E, 32 * q + k) : 0u);
-                    h[q] = v;
+                    // ring: written through to memory, so the assembly
+                    // kernel reads them without this XCD's cache written back
+                    if constexpr (RING)
+                        __hip_atomic_store(h + q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    else
+                        h[q] = v;
                 }
             }
             if (w == 0) {
-                a.crc_ok[cb.out_idx] = (uint8_t)s_ok[cs];
-                a.iters[cb.out_idx] = (uint8_t)s_iters[cs];
+                if constexpr (RING) {
+                    __hip_atomic_store(o_ok + cb.out_idx, (uint8_t)s_ok[cs], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_store(o_it + cb.out_idx, (uint8_t)s_iters[cs], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                } else {
+                    o_ok[cb.out_idx] = (uint8_t)s_ok[cs];
+                    o_it[cb.out_idx] = (uint8_t)s_iters[cs];
+                }
             }
         }
-        __syncthreads();
-        if (tid == 0) s_next = xc + nset * (gx + (int)atomicAdd(ctr_item, 1u));
-        __syncthreads();
+        if constexpr (RING) {
+            // every wave's write-through output stores have completed
+            // before the barrier, so they are in memory before the host can
+            // see the item's done mark
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(&a.ring.done[ring_i & (a.ring.cap - 1)], (uint32_t)ring_i + 1u,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            ring_i = ring_take(a.ring, r_ent, tid, nthr);
+        } else {
+            __syncthreads();
+            if (tid == 0) s_next = xc + nset * (gx + (int)atomicAdd(ctr_item, 1u));
+            __syncthreads();
+        }
     }
     // Every claim of this work group has returned (its last one ended the
     // loop) before it counts itself done, so the last of the set resets the
     // set's counters after all of the set's claims.
-    if (tid == 0 && atomicAdd(ctr_done, 1u) == (uint32_t)gx - 1) {
-        atomicExch(ctr_item, 0u);
-        atomicExch(ctr_done, 0u);
+    if constexpr (!RING) {
+        if (tid == 0 && atomicAdd(ctr_done, 1u) == (uint32_t)gx - 1) {
+            atomicExch(ctr_item, 0u);
+            atomicExch(ctr_done, 0u);
+        }
     }
 }
 
-using DecodeKernel = void (*)(DecArgs);
+using DecodeKernel = void (*)(KernArgs<false>);
 
 // The eight instantiations, indexed by uneven + 2 exact + 4 mi.
 static DecodeKernel decode_kernel(bool uneven, bool exact, bool mi)
@@ -1219,8 +1379,22 @@ const void *decode_kernel_address(bool uneven, bool exact, bool mi)
 int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, int wg_threads,
                   int lds_bytes, void *stream)
 {
+    KernArgs<false> k;
+    static_cast<DecArgs &>(k) = a;
     hipLaunchKernelGGL(decode_kernel(uneven, exact, mi), dim3(grid), dim3(wg_threads), lds_bytes,
-                       (hipStream_t)stream, a);
+                       (hipStream_t)stream, k);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+const void *ring_kernel_address() { return (const void *)turbo_decode_kernel<true, false, false, true>; }
+
+int launch_ring_decode(const DecArgs &a, const RingArgs &r, int grid, int lds_bytes, void *stream)
+{
+    KernArgs<true> k;
+    static_cast<DecArgs &>(k) = a;
+    k.ring = r;
+    hipLaunchKernelGGL((turbo_decode_kernel<true, false, false, true>), dim3(grid), dim3(kRingWg),
+                       lds_bytes, (hipStream_t)stream, k);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

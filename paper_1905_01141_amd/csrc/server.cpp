@@ -18,6 +18,7 @@
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
@@ -174,6 +175,15 @@ struct Lane {
     std::vector<int64_t> bo;  // byte offset of each TB's bits in h_bits
     int64_t t0 = 0, t_enq = 0, kb = 0, cbs = 0, model_end = 0;
     uint64_t seq = 0;  // dispatch order
+    // ring mode: the batch's items on the ring ([ring_first, ring_first +
+    // ring_n)), the first not yet seen done, and whether its assembly is
+    // enqueued; t_items: when every item was seen done
+    tdec::RingPlan rp;
+    uint64_t ring_first = 0, ring_chk = 0;
+    int ring_n = 0;
+    bool items_done = true;  // every item seen done (under ring_mu)
+    bool asm_enq = false;
+    int64_t t_items = 0;
 };
 
 }  // namespace
@@ -222,6 +232,29 @@ struct tdec_server {
     int64_t ring_n = 0;                 // launches recorded since the last reset
     bool stop = false;
     std::thread dispatcher, completer;
+    // ring mode: one persistent decode kernel takes the lanes' items from a
+    // work ring in pinned host memory; the lanes plan, upload and assemble
+    // on one side stream
+    bool ring_mode = false;
+    tdec::RingCtl *ring_ctl = nullptr;
+    tdec::RingEntry *ring_ent = nullptr;
+    uint32_t *ring_done = nullptr;
+    tdec::RingCtl *hd_ring_ctl = nullptr;   // device addresses of the three
+    tdec::RingEntry *hd_ring_ent = nullptr;
+    uint32_t *hd_ring_done = nullptr;
+    unsigned long long *d_ring_head = nullptr;  // the kernel's ticket counter and mirrors
+    char *ring_stage = nullptr;                 // pinned: their values for the next launch
+    char *d_ring_scratch = nullptr;
+    int64_t ring_stride = 0;
+    int ring_cap = 0, ring_grid = 0, ring_lds = 0, ring_item_lds = 0;
+    uint64_t ring_idle_ticks = 0;
+    hipStream_t ring_st = nullptr, side_st = nullptr;
+    hipEvent_t ring_ev = nullptr;
+    bool ring_live = false;  // a ring kernel was launched (ring_ev marks its end)
+    uint64_t ring_pub = 0;   // items published
+    int ring_outstanding = 0;  // lanes with items not all done
+    std::atomic<int64_t> ring_launches{0};
+    std::mutex ring_mu;      // publishing and (re)launching the ring kernel
 
     int64_t dur(int64_t kbits) const
     {
@@ -288,11 +321,144 @@ void enqueue_device(tdec_server *s, Lane &L, hipEvent_t after)
     L.ok = ok;
 }
 
-// Has lane L's launch finished?  (A launch whose enqueue failed has.)
-bool lane_finished(const tdec_server *s, const Lane &L, int64_t now)
+// Ring mode (under ring_mu): launch the ring kernel unless one is running.
+// A ring kernel ends once its work groups have found nothing to claim for
+// the idle time (or on stop), so a publication may find it ended, or it may
+// end with items published after its work groups' last look: the caller
+// publishing and the completer (which sees items outstanding) both call this.
+bool ring_launch_locked(tdec_server *s)
+{
+    if (s->ring_live && hipEventQuery(s->ring_ev) == hipErrorNotReady) return true;
+    // No work group of an earlier launch runs any more: the ticket counter
+    // restarts at the oldest published item that is not done (tickets that
+    // work groups abandoned when they left are handed out again; done items
+    // below it are skipped by the kernel), the mirrors at the same point.
+    uint64_t floor = s->ring_pub;
+    for (int i = 0; i < s->n_lanes; ++i) {
+        const Lane &L = s->lanes[i];
+        if (!L.items_done) floor = std::min(floor, L.ring_first);
+    }
+    memset(s->ring_stage, 0, tdec::kRingCtrBytes);
+    ((uint64_t *)s->ring_stage)[0] = floor;
+    ((uint64_t *)s->ring_stage)[16] = floor;
+    if (hipMemcpyAsync(s->d_ring_head, s->ring_stage, tdec::kRingCtrBytes, hipMemcpyHostToDevice,
+                       s->ring_st) != hipSuccess)
+        return false;
+    tdec::DecArgs a{};
+    const uint32_t *tab = tdec::ctx_crc_tab(s->lanes[0].ctx);
+    a.llr = s->d_arena;
+    a.crc_tab = tab;
+    a.mi_tab = tab + tdec::kCrcTabWords;
+    a.scratch = s->d_ring_scratch;
+    a.scratch_stride = s->ring_stride;
+    a.max_iters = s->cfg.params.max_iters;
+    a.early_stop = s->cfg.params.early_stop;
+    a.win_init = s->cfg.params.win_init;
+    a.mi_eps = s->cfg.params.mi_eps;
+    a.state_slots = tdec::kMaxSlotsPerWg;
+    tdec::RingArgs r{};
+    r.ctl = s->hd_ring_ctl;
+    r.ent = s->hd_ring_ent;
+    r.done = s->hd_ring_done;
+    r.head = s->d_ring_head;
+    r.cap = s->ring_cap;
+    r.lds = tdec::lds_state_bytes(tdec::kMaxSlotsPerWg) + s->ring_item_lds;
+    r.idle_ticks = s->ring_idle_ticks;
+    if (tdec::launch_ring_decode(a, r, s->ring_grid, s->ring_lds, s->ring_st) != 0 ||
+        hipEventRecord(s->ring_ev, s->ring_st) != hipSuccess)
+        return false;
+    s->ring_live = true;
+    ++s->ring_launches;
+    return true;
+}
+
+// Ring mode: plan lane L's batch with its context, wait for the batch's
+// slot copies and the plan's upload, then publish its items on the ring.
+// Returns without waiting for any decoding.
+void enqueue_ring(tdec_server *s, Lane &L)
+{
+    const int n = (int)L.b.size();
+    std::vector<int32_t> tbs(n);
+    std::vector<int64_t> lo(n);
+    L.bo.resize(n);
+    uint64_t seq = 0;
+    int64_t bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        tbs[i] = L.b[i].tbs;
+        lo[i] = L.b[i].slot_off / 2;
+        L.bo[i] = bytes;
+        bytes += (L.b[i].tbs + 7) / 8;
+        seq = std::max(seq, L.b[i].copy_seq);
+    }
+    L.asm_enq = false;
+    L.ring_n = 0;
+    // the items are claimed by a kernel that is already running: everything
+    // they read must be in device memory before they are published
+    bool ok = hipEventSynchronize(s->copy_ev[seq % kCopyEvents]) == hipSuccess;
+    ok = ok && tdec::ring_plan(L.ctx, n, tbs.data(), lo.data(), L.bo.data(), &s->cfg.params, L.st,
+                               &L.rp) == TDEC_OK;
+    const tdec::RingPlan &r = L.rp;
+    // the ring kernel's shape: two waves, the LDS and scratch it was sized for
+    ok = ok && r.wg == tdec::kRingWg && r.max_item_lds <= s->ring_item_lds &&
+         r.stride <= s->ring_stride && !r.exact && !r.mi && r.n_items <= s->ring_cap / kMaxLanes;
+    ok = ok && hipEventSynchronize(r.ready) == hipSuccess;
+    if (ok) {
+        std::lock_guard<std::mutex> g(s->ring_mu);
+        L.ring_first = L.ring_chk = s->ring_pub;
+        for (int k = 0; k < r.n_items; ++k) {
+            tdec::RingEntry &e = s->ring_ent[(s->ring_pub + (uint64_t)k) & (uint64_t)(s->ring_cap - 1)];
+            e.item = r.items[k];
+            e.cbs = r.d_cbs + r.items[k].cb0;
+            e.qtab = r.d_qtab;
+            e.hard = r.d_hard;
+            e.crc_ok = r.d_ok;
+            e.iters = r.d_it;
+        }
+        s->ring_pub += (uint64_t)r.n_items;
+        L.ring_n = r.n_items;
+        L.items_done = false;
+        ++s->ring_outstanding;
+        __atomic_store_n(&s->ring_ctl->tail, s->ring_pub, __ATOMIC_RELEASE);
+        ok = ring_launch_locked(s);
+    }
+    L.t_enq = mono_ns();
+    L.ok = ok;
+}
+
+// Has lane L's launch finished?  (A launch whose enqueue failed has.)  In
+// ring mode a lane finishes in two steps: once all its items are marked
+// done, its assembly is enqueued here; then its completion event fires.
+bool lane_finished(tdec_server *s, Lane &L, int64_t now)
 {
     if (s->model) return now >= L.model_end;
     if (!L.ok) return true;
+    if (s->ring_mode && !L.asm_enq) {
+        const uint64_t end = L.ring_first + (uint64_t)L.ring_n;
+        while (L.ring_chk < end &&
+               __atomic_load_n(&s->ring_done[L.ring_chk & (uint64_t)(s->ring_cap - 1)],
+                               __ATOMIC_ACQUIRE) == (uint32_t)(L.ring_chk + 1))
+            ++L.ring_chk;
+        {
+            std::lock_guard<std::mutex> g(s->ring_mu);
+            if (L.ring_chk < end) {
+                // items outstanding: the kernel must be running (it may have
+                // ended with them published after its work groups left)
+                if (!ring_launch_locked(s)) L.ok = false;
+                return !L.ok;
+            }
+            L.items_done = true;
+            --s->ring_outstanding;
+        }
+        L.t_items = mono_ns();
+        bool ok = hipEventRecord(L.ev_m, L.st) == hipSuccess &&
+                  tdec::ring_assemble(L.ctx, L.rp, &s->cfg.params, L.hd_bits, L.hd_res, L.st) ==
+                      TDEC_OK &&
+                  hipEventRecord(L.ev_c, L.st) == hipSuccess &&
+                  hipEventRecord(L.done_ev, L.st) == hipSuccess;
+        L.asm_enq = true;
+        L.ok = ok;
+        return !ok;
+    }
     const hipError_t e = hipEventQuery(L.done_ev);
     return e != hipErrorNotReady;
 }
@@ -319,7 +485,10 @@ void collect(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res, int6
     bool ok = L.ok && hipEventSynchronize(L.done_ev) == hipSuccess;
     float coding_ms = 0.f, post_ms = 0.f, copy_ms = 0.f;
     if (ok) {
-        (void)hipEventElapsedTime(&coding_ms, L.ev_s, L.ev_m);
+        // ring mode: coding runs from publication until every item was
+        // seen done (host clock)
+        if (s->ring_mode) coding_ms = (float)((double)(L.t_items - L.t_enq) * 1e-6);
+        else (void)hipEventElapsedTime(&coding_ms, L.ev_s, L.ev_m);
         (void)hipEventElapsedTime(&post_ms, L.ev_m, L.done_ev);
         (void)hipEventElapsedTime(&copy_ms, L.ev_c, L.done_ev);
     }
@@ -359,9 +528,11 @@ void dispatcher_main(tdec_server *s)
         // launches leave (the hand-over from one launch to the next is
         // hidden) without sharing them with those launches for long, which
         // would delay their older blocks.
+        // In ring mode a batch goes out as soon as a lane is free: its items
+        // join the running kernel, whose work groups take them as they free up.
         const auto ready = [&] {
             if (s->stop || s->queue.empty() || s->free_lane() < 0) return s->stop;
-            return s->lanes_busy == 0 || mono_ns() >= s->gpu_end_pred - s->lead();
+            return s->ring_mode || s->lanes_busy == 0 || mono_ns() >= s->gpu_end_pred - s->lead();
         };
         while (!ready()) {
             if (!s->queue.empty() && s->free_lane() >= 0 && s->lanes_busy > 0)
@@ -392,7 +563,7 @@ void dispatcher_main(tdec_server *s)
             kb += p.kbits;
             cbs += p.C;
             s->queue.pop_front();
-        } while (s->cfg.mode == TDEC_SERVE_CONTINUOUS && !s->queue.empty() &&
+        } while (s->cfg.mode != TDEC_SERVE_PER_TB && !s->queue.empty() &&
                  cbs + s->queue.front().C <= s->cfg.max_batch_cb &&
                  (!feasible || start + s->dur(kb + s->queue.front().kbits) <= dl));
         s->queued_kbits -= kb;
@@ -434,6 +605,8 @@ void dispatcher_main(tdec_server *s)
                                          std::max(s->sim_busy_until, L.t0) +
                                              (int64_t)((double)s->sim_npk * kb / 1000.0));
             L.model_end = s->sim_busy_until;
+        } else if (s->ring_mode) {
+            enqueue_ring(s, L);
         } else {
             tdec::ctx_set_launch_reserve(L.ctx, reserve, L.small_asm);
             enqueue_device(s, L, after);
@@ -517,6 +690,20 @@ void retire_locked(tdec_server *s, Lane &L, std::vector<tdec_server_result> &res
     if (--s->lanes_busy == 0) s->gpu_end_pred = 0;
 }
 
+// Ring mode: end the ring kernel (it has had no work for the idle time):
+// its work groups, all waiting for unpublished tickets, leave once the stop
+// flag is seen, within microseconds.  Under ring_mu, so that nothing is
+// published meanwhile; a later publication launches the kernel again.
+void ring_stop_idle(tdec_server *s)
+{
+    std::lock_guard<std::mutex> g(s->ring_mu);
+    if (!s->ring_live || s->ring_outstanding > 0) return;
+    __atomic_store_n(&s->ring_ctl->stop, 1u, __ATOMIC_RELEASE);
+    (void)hipEventSynchronize(s->ring_ev);
+    s->ring_live = false;
+    __atomic_store_n(&s->ring_ctl->stop, 0u, __ATOMIC_RELEASE);
+}
+
 // The completer: watches the lanes' launches, oldest first, and retires each
 // as soon as it finishes (in whatever order they finish).
 void completer_main(tdec_server *s)
@@ -528,11 +715,20 @@ void completer_main(tdec_server *s)
         cand.clear();
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_retire.wait(lk, [&] {
+            const auto pending = [&] {
                 for (int i = 0; i < s->n_lanes; ++i)
                     if (s->lanes[i].launched) return true;
                 return s->stop && s->lanes_busy == 0;
-            });
+            };
+            if (s->ring_mode && !s->model && !pending()) {
+                // nothing in flight: after the idle time, end the ring kernel
+                if (!s->cv_retire.wait_for(lk, std::chrono::microseconds(s->cfg.ring_idle_us), pending)) {
+                    lk.unlock();
+                    ring_stop_idle(s);
+                    continue;
+                }
+            }
+            s->cv_retire.wait(lk, pending);
             for (int i = 0; i < s->n_lanes; ++i)
                 if (s->lanes[i].launched) cand.push_back(i);
             if (cand.empty()) break;  // stop, nothing in flight
@@ -580,8 +776,14 @@ void free_device(tdec_server *s)
 {
     if (s->model) return;
     (void)hipSetDevice(s->device);
+    if (s->ring_ctl) {
+        // the ring kernel's work groups leave at their next look at the ring
+        __atomic_store_n(&s->ring_ctl->stop, 1u, __ATOMIC_RELEASE);
+        if (s->ring_st) (void)hipStreamSynchronize(s->ring_st);
+    }
     for (int i = 0; i < kMaxLanes; ++i) {
         Lane &L = s->lanes[i];
+        if (L.st == s->side_st) L.st = nullptr;  // shared, destroyed below
         if (L.st) (void)hipStreamSynchronize(L.st);
         if (L.h_bits) (void)hipHostFree(L.h_bits);
         if (L.h_res) (void)hipHostFree(L.h_res);
@@ -592,16 +794,94 @@ void free_device(tdec_server *s)
         else if (L.ctx) tdec::ctx_set_launch_reserve(L.ctx, 0, false);  // the caller's context
         L = Lane{};
     }
+    if (s->side_st) {
+        (void)hipStreamSynchronize(s->side_st);
+        (void)hipStreamDestroy(s->side_st);
+    }
+    if (s->ring_ev) (void)hipEventDestroy(s->ring_ev);
+    if (s->ring_st) (void)hipStreamDestroy(s->ring_st);
+    if (s->ring_ctl) (void)hipHostFree(s->ring_ctl);
+    if (s->ring_ent) (void)hipHostFree(s->ring_ent);
+    if (s->ring_done) (void)hipHostFree(s->ring_done);
+    if (s->ring_stage) (void)hipHostFree(s->ring_stage);
+    if (s->d_ring_head) (void)hipFree(s->d_ring_head);
+    if (s->d_ring_scratch) (void)hipFree(s->d_ring_scratch);
     if (s->d_arena) (void)hipFree(s->d_arena);
     for (auto &e : s->copy_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->copy_st) (void)hipStreamDestroy(s->copy_st);
 }
 
+// Ring mode: the work ring (pinned host memory, fine-grained so that both
+// sides see each other's writes while the kernel runs), the claim counter,
+// the ring kernel's scratch and shape, and the streams.
+bool ring_setup(tdec_server *s)
+{
+    constexpr unsigned kRingFlags = hipHostMallocMapped | hipHostMallocCoherent;
+    s->ring_mode = true;
+    int cap = 1;
+    while (cap < kMaxLanes * s->cfg.max_batch_cb) cap <<= 1;
+    s->ring_cap = cap;
+    // LDS: the per-slot state of 64 blocks, the item's extrinsic arrays, the
+    // item's copy; 26 KB in all (with the kernel's static LDS under 27 KB),
+    // so that six two-wave work groups share a CU's 160 KB
+    s->ring_lds = 26624;
+    s->ring_item_lds = s->ring_lds - tdec::lds_state_bytes(tdec::kMaxSlotsPerWg) - tdec::kRingLdsBytes;
+    s->ring_stride = tdec::ring_max_stride(tdec::kRingWg / 2, s->ring_item_lds);
+    int occ = 0, khz = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tdec::ring_kernel_address(), tdec::kRingWg,
+                                                     s->ring_lds) != hipSuccess ||
+        occ < 1 ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess || khz < 1)
+        return false;
+    // The ring kernel's stream masks out one compute unit per eighth of the
+    // device (which is one per XCD whether the CU numbering runs XCD by XCD
+    // or round-robin over them): the transport block assembly, the gather
+    // and copy launches of the other streams always find room there.  A
+    // stream with a CU mask also gets a hardware queue of its own, so that
+    // no other stream's work queues up behind the resident ring kernel.
+    const int ncu = tdec::ctx_num_cus(s->ctx);
+    // (ncu words: enough whether the runtime counts the mask's size in bits
+    // or in 32-bit words; words past the CU count are ignored)
+    std::vector<uint32_t> mask((size_t)std::max(ncu, 1), 0u);
+    int used = 0;
+    for (int c = 0; c < ncu; ++c) {
+        const int blk = ncu / 8, k = blk > 0 ? c / blk : 8;
+        if (ncu >= 64 && k < 8 && c == k * blk + blk - 1 - k) continue;
+        mask[(size_t)c / 32] |= 1u << (c % 32);
+        ++used;
+    }
+    s->ring_grid = std::max(1, occ * used);
+    // a work group gives up a wait after four idle times and 100 ms more:
+    // the host ends an idle kernel itself long before that, so the bound
+    // only matters if the host stops looking after the ring
+    s->ring_idle_ticks = ((uint64_t)s->cfg.ring_idle_us * 4u + 100000u) * (uint64_t)khz / 1000u;
+    bool ok = hipHostMalloc(&s->ring_ctl, sizeof(tdec::RingCtl), kRingFlags) == hipSuccess &&
+              hipHostMalloc(&s->ring_ent, sizeof(tdec::RingEntry) * (size_t)cap, kRingFlags) == hipSuccess &&
+              hipHostMalloc(&s->ring_done, sizeof(uint32_t) * (size_t)cap, kRingFlags) == hipSuccess &&
+              hipHostMalloc(&s->ring_stage, tdec::kRingCtrBytes, hipHostMallocDefault) == hipSuccess;
+    if (!ok) return false;
+    memset(s->ring_ctl, 0, sizeof(tdec::RingCtl));
+    memset(s->ring_ent, 0, sizeof(tdec::RingEntry) * (size_t)cap);
+    memset(s->ring_done, 0, sizeof(uint32_t) * (size_t)cap);
+    ok = hipHostGetDevicePointer((void **)&s->hd_ring_ctl, s->ring_ctl, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void **)&s->hd_ring_ent, s->ring_ent, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void **)&s->hd_ring_done, s->ring_done, 0) == hipSuccess &&
+         hipMalloc(&s->d_ring_head, tdec::kRingCtrBytes) == hipSuccess &&
+         hipMalloc(&s->d_ring_scratch, (size_t)s->ring_stride * (size_t)s->ring_grid) == hipSuccess &&
+         hipExtStreamCreateWithCUMask(&s->ring_st, (uint32_t)mask.size(), mask.data()) == hipSuccess &&
+         hipStreamCreateWithFlags(&s->side_st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&s->ring_ev, hipEventDisableTiming) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    return ok;
+}
+
 tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
 {
     if (!cfg || cfg->deadline_us <= 0 || cfg->max_batch_cb < 0 ||
-        (cfg->mode != TDEC_SERVE_CONTINUOUS && cfg->mode != TDEC_SERVE_PER_TB) ||
+        (cfg->mode != TDEC_SERVE_CONTINUOUS && cfg->mode != TDEC_SERVE_PER_TB &&
+         cfg->mode != TDEC_SERVE_RING) ||
+        cfg->ring_idle_us < 0 || cfg->ring_idle_us > 10000000 ||
         !tdec::params_valid(&cfg->params) || cfg->model_lat_ns < 0 ||
         cfg->model_ns_per_kbit < 0 || cfg->max_inflight < 0 || cfg->max_inflight > kMaxLanes)
         return TDEC_EINVAL;
@@ -610,7 +890,12 @@ tdec_status create_common(const tdec_server_cfg *cfg, tdec_server *s)
     if (!s->cfg.max_batch_cb) s->cfg.max_batch_cb = 8192;
     s->cfg.max_batch_cb = std::max(s->cfg.max_batch_cb, 64);  // a TB has at most 64 blocks
     // the plain per-TB form runs one launch at a time
-    s->n_lanes = s->cfg.mode == TDEC_SERVE_PER_TB ? 1 : (s->cfg.max_inflight ? s->cfg.max_inflight : 2);
+    s->n_lanes = s->cfg.mode == TDEC_SERVE_PER_TB
+                     ? 1
+                     : (s->cfg.max_inflight ? s->cfg.max_inflight
+                                            : (s->cfg.mode == TDEC_SERVE_RING ? 4 : 2));
+    if (!s->cfg.ring_idle_us) s->cfg.ring_idle_us = 20000;
+    s->ring_mode = s->cfg.mode == TDEC_SERVE_RING;
     s->cfg.max_inflight = s->n_lanes;
     s->arena.init((int64_t)s->cfg.slot_budget_bytes);
     s->m_lat = (double)(cfg->model_lat_ns ? cfg->model_lat_ns : 300000);
@@ -655,29 +940,41 @@ tdec_status tdec_server_create(tdec_ctx *ctx, const tdec_server_cfg *cfg, tdec_s
     // every copy event starts recorded, so that a wait on it never blocks on nothing
     for (auto &e : s->copy_ev) ok = ok && hipEventRecord(e, s->copy_st) == hipSuccess;
     tdec_status cs = TDEC_OK;
+    const bool ring = s->cfg.mode == TDEC_SERVE_RING;
+    if (ring) {
+        // the ring kernel holds 64 windows per work group (two waves)
+        ok = ok && s->cfg.params.win_init != 2 && !(s->cfg.params.early_stop & 2) &&
+             s->cfg.params.n_windows <= tdec::kRingWg / 2;
+        if (!ok) cs = TDEC_EINVAL;
+        ok = ok && ring_setup(s);
+    }
     for (int i = 0; i < s->n_lanes && ok; ++i) {
         Lane &L = s->lanes[i];
-        if (i == 0) {
+        if (i == 0 && !ring) {
             L.ctx = ctx;
         } else {
+            // ring mode plans with contexts of the ring kernel's shape, so
+            // the caller's context is left as it was
             cs = tdec::ctx_clone(ctx, &L.ctx);
             ok = cs == TDEC_OK;
             L.own_ctx = ok;
+            if (ok && ring) tdec::ctx_set_ring_shape(L.ctx, tdec::kRingWg / 2, s->ring_item_lds);
         }
+        if (ring) L.st = s->side_st;
         ok = ok &&
              hipHostMalloc(&L.h_bits, s->bits_cap, kStageFlags) == hipSuccess &&
              hipHostMalloc(&L.h_res, sizeof(tdec_tb_result) * (size_t)s->res_cap,
                            kStageFlags) == hipSuccess &&
              hipHostGetDevicePointer((void **)&L.hd_bits, L.h_bits, 0) == hipSuccess &&
              hipHostGetDevicePointer((void **)&L.hd_res, L.h_res, 0) == hipSuccess &&
-             hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) == hipSuccess &&
+             (ring || hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) == hipSuccess) &&
              hipEventCreate(&L.done_ev) == hipSuccess && hipEventCreate(&L.ev_s) == hipSuccess &&
              hipEventCreate(&L.ev_m) == hipSuccess && hipEventCreate(&L.ev_c) == hipSuccess;
     }
     if (!ok) {
         free_device(s);
         delete s;
-        return cs == TDEC_EDEVICE ? TDEC_EDEVICE : TDEC_ENOMEM;
+        return cs == TDEC_EDEVICE || cs == TDEC_EINVAL ? cs : TDEC_ENOMEM;
     }
     start_threads(s);
     *out = s;
@@ -775,7 +1072,7 @@ static int32_t submit_impl(tdec_server *s, int32_t n, const uint64_t *tags, cons
                 const int64_t start = std::max(now, s->gpu_end_pred);
                 int64_t pred;
                 int64_t limit = deadline;
-                if (s->cfg.mode == TDEC_SERVE_CONTINUOUS) {
+                if (s->cfg.mode != TDEC_SERVE_PER_TB) {
                     const int64_t launches =
                         (s->queued_cbs + g.C + s->cfg.max_batch_cb - 1) / s->cfg.max_batch_cb;
                     pred = start + s->dur(s->queued_kbits + g.kbits) +
@@ -973,6 +1270,8 @@ tdec_status tdec_server_stats(tdec_server *s, tdec_serve_stats *out)
         std::lock_guard<std::mutex> lk(s->mu);
         *out = s->st;
         v.assign(s->lat.begin(), s->lat.end());
+        out->ring_launches = s->ring_launches;
+        out->ring_grid = s->ring_grid;
         out->model_lat_ns = (int64_t)s->m_lat;
         out->model_ns_per_kbit = (int64_t)s->m_npk;
         out->slots_in_use_bytes = s->arena.used();

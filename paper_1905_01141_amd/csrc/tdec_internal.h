@@ -68,6 +68,31 @@ constexpr int kCtrSets = 8;
 constexpr int kCtrStride = 64;  // uint32 words
 constexpr int kCtrBytes = 2 * kCtrSets * kCtrStride * 4;
 
+// Work ring of the serving loop's ring mode.  The host appends work items
+// to a ring in pinned host memory while one persistent decode kernel runs;
+// its work groups claim items through a device counter and mark each item
+// done in host memory once its outputs are written.
+struct RingCtl {
+    uint64_t tail;  // items published (written by the host, release order)
+    uint32_t stop;  // set by the host: work groups leave once nothing is left to claim
+    uint32_t rsv;
+};
+// One ring item: a work item of a plan uploaded by the host, with the device
+// buffers of the context that planned it.
+struct RingEntry {
+    DecItem item;          // its cb0 is unused: cbs points at the item's first block
+    int32_t rsv[2];
+    const DecCb *cbs;      // device: the item's ncb code blocks
+    const uint16_t *qtab;  // device: QPP address tables (item.qtab is an offset here)
+    uint32_t *hard;        // device outputs (hard_off / out_idx of the blocks index these)
+    uint8_t *crc_ok;
+    uint8_t *iters;
+};
+// LDS bytes of the ring kernel's copy of one item: the entry, then up to
+// kMaxSlotsPerWg code blocks.
+constexpr int kRingCtrBytes = 384;
+constexpr int kRingLdsBytes = (int)(sizeof(RingEntry) + kMaxSlotsPerWg * sizeof(DecCb) + 63) & ~63;
+
 struct DecArgs {
     const DecItem *items;
     int32_t n_items;
@@ -90,6 +115,20 @@ struct DecArgs {
     int32_t max_iters, early_stop, win_init, mi_eps;
     int32_t state_slots;  // most blocks of any item (size of the per-slot LDS state)
     uint32_t *tb_fail;    // per transport block failure marks (purge), null = no purge
+};
+
+// The ring kernel's further arguments (its items come from the ring, not
+// DecArgs::items).
+struct RingArgs {
+    const RingCtl *ctl;        // host
+    const RingEntry *ent;      // host, cap entries
+    uint32_t *done;            // host, cap marks: item i writes i + 1 when done
+    unsigned long long *head;  // device, kRingCtrBytes: [0] tickets handed out, [16] the
+                               // host's tail as last seen, [32] (32 bits) its stop flag as seen
+    int32_t cap;               // a power of two
+    int32_t lds;               // LDS byte offset of the item copy (kRingLdsBytes)
+    uint64_t idle_ticks;       // a work group that waits this many wall-clock ticks for
+                               // its item gives up and leaves the kernel
 };
 
 // One transport block for the assembly kernel (after the code blocks are decoded).
@@ -183,6 +222,46 @@ int launch_gather(const GatherArgs &g, void *stream);
 // launch leaves.
 void ctx_set_launch_reserve(tdec_ctx *ctx, int n, bool small_asm);
 
+// Ring mode of the serving loop.  A plan of transport blocks built and
+// uploaded (on `st`) as for tdec_tb_decode_batch, for the ring kernel: its
+// items, whose code block lists start at d_cbs + cb0, are published on the
+// ring by the caller once `ready` has fired (the upload, and that of any QPP
+// table the plan added, are complete then), and its transport blocks are
+// assembled by ring_assemble once every item is done.  The plan stays valid
+// until the context plans again.
+struct RingPlan {
+    const DecItem *items = nullptr;  // host copy
+    int n_items = 0, n_cb = 0, n_tb = 0, asm_words = 0;
+    const DecCb *d_cbs = nullptr;
+    const TbItem *d_tbs = nullptr;
+    int wg = 0;            // threads per work group the plan's window counts need
+    int max_item_lds = 0;  // LDS bytes of the largest item's extrinsic arrays
+    int64_t stride = 0;    // scratch bytes per work group of the largest item
+    bool exact = false, mi = false;
+    hipEvent_t ready = nullptr;
+    // the planning context's device buffers, with their sizes (elements)
+    const uint16_t *d_qtab = nullptr;
+    int64_t qtab_entries = 0;
+    uint32_t *d_hard = nullptr;
+    int64_t hard_words = 0;
+    uint8_t *d_ok = nullptr, *d_it = nullptr;
+    int64_t flags = 0;
+};
+tdec_status ring_plan(tdec_ctx *ctx, int32_t n_tb, const int32_t *tbs, const int64_t *llr_off,
+                      const int64_t *bits_off, const tdec_params *params, hipStream_t st,
+                      RingPlan *out);
+// Transport block assembly of a ring plan whose items are all done, in
+// kAsmGrid small work groups (beside the resident ring kernel).
+tdec_status ring_assemble(tdec_ctx *ctx, const RingPlan &r, const tdec_params *params,
+                          uint8_t *d_bits, tdec_tb_result *d_res, hipStream_t st);
+// Plans of ctx with at most max_nw windows per block (the ring kernel's
+// work groups hold 64 windows) and items of at most lds_budget LDS bytes.
+void ctx_set_ring_shape(tdec_ctx *ctx, int max_nw, int lds_budget);
+// Scratch bytes per work group that covers every item such plans can hold.
+int64_t ring_max_stride(int max_nw, int lds_budget);
+const uint32_t *ctx_crc_tab(const tdec_ctx *ctx);
+int ctx_num_cus(const tdec_ctx *ctx);
+
 // A new context on src's device with src's workspace budget and window
 // choices (the serving loop's further launch lanes, each with a workspace of
 // its own so that their launches can run at the same time).
@@ -207,6 +286,13 @@ tdec_status tb_decode_batch_timed(tdec_ctx *ctx, int32_t n_tb, const int32_t *tb
 const void *decode_kernel_address(bool uneven, bool exact, bool mi);
 int launch_decode(const DecArgs &a, bool uneven, bool exact, bool mi, int grid, int wg_threads,
                   int lds_bytes, void *stream);
+// The ring kernel (uneven windows allowed, window boundaries from the
+// previous iteration, no mutual-information stop), kRingWg threads per work
+// group; it runs until its work groups have found nothing to claim for
+// ring_idle_ticks, or the ring's stop flag is set and nothing is left.
+constexpr int kRingWg = 128;
+const void *ring_kernel_address();
+int launch_ring_decode(const DecArgs &a, const RingArgs &r, int grid, int lds_bytes, void *stream);
 // Fixed scratch of the allocation-free decode entry point (a file-scope
 // device array of kStaticScratchBytes per device: kCtrBytes of claim counters,
 // then per-work-group scratch).  static_scratch_init, called with `device`

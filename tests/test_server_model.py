@@ -391,3 +391,35 @@ def test_replay_submits_each_tick_at_its_time():
             srv2.replay([1, -1], [], [])
         finally:
             srv2.close()
+
+
+def test_ring_mode_takes_arrivals_at_once():
+    """Ring mode (modelled): a batch that arrives while another is in flight
+    is taken at once -- on the device its items join the running ring kernel
+    -- rather than held until shortly before the first one's predicted end;
+    four batches may be in flight by default, and the ring kernel's idle
+    time is range-checked."""
+    cfg = T.server_cfg(T.params(8, 1, 0, 1), deadline_us=1_000_000, model_lat_ns=20_000_000,
+                       mode=T.SERVE_RING)
+    srv = T.Server.model(cfg, 20_000_000, 0)
+    try:
+        _submit(srv, list(range(5)), [6000] * 5)
+        time.sleep(0.004)
+        _submit(srv, list(range(5, 8)), [3000] * 3)
+        time.sleep(0.002)
+        _submit(srv, [8], [3000])
+        srv.drain(10000)
+        res = _collect(srv, 9)
+        recs = sorted(srv.launches(), key=lambda r: r["t_start_ns"])
+    finally:
+        srv.close()
+    assert len(res) == 9 and [r["n_tb"] for r in recs] == [5, 3, 1]
+    # taken within a few ms of arriving, long before the first batch's end
+    assert recs[1]["t_start_ns"] < recs[0]["t_start_ns"] + 10_000_000
+    assert recs[2]["t_start_ns"] < recs[0]["t_start_ns"] + 12_000_000
+    for us in (-1, 10_000_001):
+        with pytest.raises(T.TdecError):
+            T.Server.model(T.server_cfg(T.params(8, 1, 0, 1), mode=T.SERVE_RING, ring_idle_us=us),
+                           100_000, 0)
+    T.Server.model(T.server_cfg(T.params(8, 1, 0, 1), mode=T.SERVE_RING, ring_idle_us=1),
+                   100_000, 0).close()
