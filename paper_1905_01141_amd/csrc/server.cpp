@@ -393,10 +393,11 @@ void enqueue_ring(tdec_server *s, Lane &L)
     L.asm_enq = false;
     L.ring_n = 0;
     // the items are claimed by a kernel that is already running: everything
-    // they read must be in device memory before they are published
-    bool ok = hipEventSynchronize(s->copy_ev[seq % kCopyEvents]) == hipSuccess;
-    ok = ok && tdec::ring_plan(L.ctx, n, tbs.data(), lo.data(), L.bo.data(), &s->cfg.params, L.st,
-                               &L.rp) == TDEC_OK;
+    // they read must be in device memory before they are published (the plan
+    // is built and its upload enqueued while the slot copies still run)
+    bool ok = tdec::ring_plan(L.ctx, n, tbs.data(), lo.data(), L.bo.data(), &s->cfg.params, L.st,
+                              &L.rp) == TDEC_OK;
+    ok = ok && hipEventSynchronize(s->copy_ev[seq % kCopyEvents]) == hipSuccess;
     const tdec::RingPlan &r = L.rp;
     // the ring kernel's shape: two waves, the LDS and scratch it was sized for
     ok = ok && r.wg == tdec::kRingWg && r.max_item_lds <= s->ring_item_lds &&
