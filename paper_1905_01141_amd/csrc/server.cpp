@@ -33,6 +33,9 @@
 #include "tdec_internal.h"
 #include "tdec_server.h"
 
+// the ring kernel copies ring entries and block lists word by word
+static_assert(sizeof(tdec::RingEntry) % 4 == 0 && sizeof(tdec::DecCb) % 4 == 0, "word copies");
+
 namespace {
 
 int64_t mono_ns()
@@ -405,6 +408,17 @@ void enqueue_ring(tdec_server *s, Lane &L)
     ok = ok && hipEventSynchronize(r.ready) == hipSuccess;
     if (ok) {
         std::lock_guard<std::mutex> g(s->ring_mu);
+        // the ring never wraps onto an item that is published but not done:
+        // its entry may still be claimed (in flight there are at most
+        // max_inflight batches of max_batch_cb items, which the ring holds)
+        uint64_t oldest = s->ring_pub;
+        for (int i = 0; i < s->n_lanes; ++i)
+            if (!s->lanes[i].items_done) oldest = std::min(oldest, s->lanes[i].ring_first);
+        if (s->ring_pub + (uint64_t)r.n_items - oldest > (uint64_t)s->ring_cap) {
+            L.t_enq = mono_ns();
+            L.ok = false;
+            return;
+        }
         L.ring_first = L.ring_chk = s->ring_pub;
         for (int k = 0; k < r.n_items; ++k) {
             tdec::RingEntry &e = s->ring_ent[(s->ring_pub + (uint64_t)k) & (uint64_t)(s->ring_cap - 1)];
