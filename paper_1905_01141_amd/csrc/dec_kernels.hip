@@ -699,10 +699,6 @@ __device__ uint32_t crc_shift(uint32_t r, int n, const uint32_t *T)
 
 __device__ __forceinline__ short clamp_llr(int v) { return (short)max(-kLlrMax, min(kLlrMax, v)); }
 
-// At most 168 VGPRs: three waves per SIMD (the hot loops fit without spills;
-// a few spills remain in the phase-1 loop heads).  UNEVEN: some item's last
-// window is shorter than the others, so window lengths are per lane; the
-// even instantiation keeps them uniform (scalar loop bounds).
 // Four consecutive int16 LLRs (8 bytes); one 8-byte load when the address is
 // 8-byte aligned, else four 2-byte loads.  The channel LLRs are read once per
 // launch, so the loads are non-temporal: they do not displace the restaged
@@ -954,6 +950,14 @@ struct KernArgs<true> : DecArgs {
     RingArgs ring;
 };
 
+// At most 168 VGPRs, so that three waves share a SIMD.  The compiler spills
+// 136 of them (548 B of scratch per lane) in the uniform instantiation and
+// 124-199 in the others, all in the code around the phase loops: the
+// innermost loops (a segment of 8 steps in phase 1, two in phase 2) have no
+// scratch access.  UNEVEN: some item's last window is shorter than the
+// others, so window lengths are per lane; the even instantiation keeps them
+// uniform (scalar loop bounds).  RING: items come from the serving loop's
+// work ring (ring_take) and outputs are written through to memory.
 template <bool UNEVEN, bool EXACT, bool MI, bool RING = false>
 __global__ void __launch_bounds__(kMaxWgThreads, 3) turbo_decode_kernel(KernArgs<RING> a)
 {
