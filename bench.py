@@ -169,7 +169,7 @@ def cpu_baseline(llr, sample_cbs: int, threads: int):
                      f"{N_WIN} windows, one block per task; {dt:.2f} s wall, "
                      f"{sum(o[1] for o in out)} CRC pass",
            "by_threads": sweep, "cpu": cpu["model_name"], "cpu_info": cpu,
-           "threads_note": "a one-GPU box grants 16 host CPUs to its GPU; the pool uses "
+           "threads_note": "the host grants 16 CPUs per GPU; the pool uses "
                            "min(16, CPUs this process may run on)"}
     return rec, out
 
