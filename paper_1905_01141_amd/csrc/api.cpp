@@ -566,7 +566,7 @@ tdec_status launch_tb_plan(tdec_ctx *ctx, PlanSlot *ps, char *d_plan, const int1
     if (launch_tb_assemble((const TbItem *)(d_plan + ps->off_tbs), ps->n_tb, ps->asm_words,
                            ctx->d_hard, ctx->d_ok, ctx->d_it,
                            (params->early_stop & TDEC_STOP_PURGE) ? ctx->d_tbfail : nullptr,
-                           ctx->d_crc_tab, d_bits, d_res, ctx->small_asm, st))
+                           ctx->d_crc_tab, d_bits, d_res, ctx->small_asm ? kAsmGrid : 0, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }
@@ -863,7 +863,7 @@ tdec_status tdec::ring_assemble(tdec_ctx *ctx, const RingPlan &r, const tdec_par
 {
     if (!ctx || !d_res || !params_ok(params)) return TDEC_EINVAL;
     if (launch_tb_assemble(r.d_tbs, r.n_tb, r.asm_words, ctx->d_hard, ctx->d_ok, ctx->d_it, nullptr,
-                           ctx->d_crc_tab, d_bits, d_res, true, st))
+                           ctx->d_crc_tab, d_bits, d_res, kRingAsmGrid, st))
         return TDEC_EDEVICE;
     return TDEC_OK;
 }

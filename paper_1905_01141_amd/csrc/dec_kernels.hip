@@ -1631,14 +1631,14 @@ __global__ void __launch_bounds__(256) tb_assemble_kernel(const TbItem *items, i
 
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *tb_fail,
-                       const uint32_t *crc_tab, uint8_t *bits, void *res, bool small_grid,
+                       const uint32_t *crc_tab, uint8_t *bits, void *res, int small_grid,
                        void *stream)
 {
     if (n_tb <= 0) return 0;
-    // one work group of 256 threads per transport block, or kAsmGrid work
+    // one work group of 256 threads per transport block, or small_grid work
     // groups of two waves (each fits the slot of a decode work group)
-    const int grid = small_grid ? min(n_tb, kAsmGrid) : n_tb;
-    hipLaunchKernelGGL(tb_assemble_kernel, dim3(grid), dim3(small_grid ? 128 : 256),
+    const int grid = small_grid > 0 ? min(n_tb, small_grid) : n_tb;
+    hipLaunchKernelGGL(tb_assemble_kernel, dim3(grid), dim3(small_grid > 0 ? 128 : 256),
                        (size_t)max_words * 4, (hipStream_t)stream, items, n_tb, hard, crc_ok, iters,
                        tb_fail, bits, (TbRes *)res, crc_tab + 2 * kCrcTabN);
     return hipGetLastError() == hipSuccess ? 0 : -1;

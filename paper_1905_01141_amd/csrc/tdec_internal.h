@@ -310,14 +310,19 @@ int launch_zero_words(uint32_t *p, int n, void *stream);
 // free), and the assembly of one launch never waits for the decode of the
 // next.
 constexpr int kAsmGrid = 64;
+// The ring kernel leaves one CU per XCD free: eight CUs hold about 14 such
+// work groups each (their LDS is bounded by the largest transport block).
+constexpr int kRingAsmGrid = 112;
 // max_words: the largest (B + 31) / 32 of the transport blocks (LDS per work group)
-// small_grid: kAsmGrid work groups of 128 threads (launch lanes) instead of
-// one of 256 threads per transport block.
+// small_grid > 0: that many work groups of 128 threads (kAsmGrid beside a
+// launch lane's decode, kRingAsmGrid on the CUs the ring kernel leaves
+// free), each taking transport blocks in turn; 0: one work group of 256
+// threads per transport block.
 // tb_fail: the decode launch's failure marks (purge), a marked block fails
 // without its CRC24A being checked; null = no purge.
 int launch_tb_assemble(const TbItem *items, int n_tb, int max_words, const uint32_t *hard,
                        const uint8_t *crc_ok, const uint8_t *iters, const uint32_t *tb_fail,
-                       const uint32_t *crc_tab, uint8_t *bits, void *res, bool small_grid,
+                       const uint32_t *crc_tab, uint8_t *bits, void *res, int small_grid,
                        void *stream);
 int launch_encode(const EncCb *cbs, int n_cb, const uint8_t *src, uint8_t *out,
                   const uint32_t *crc_tab, void *stream);
