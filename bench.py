@@ -11,10 +11,11 @@ The LLRs are resident in device memory before the timed region starts.
 
 Also reported (stderr + extra JSON fields): the same batch as configured
 (at most 8 iterations with CRC24B early stop), the kernel's VALU roofline
-fraction, the CPU oracle's throughput on a bounded sample, and two short
+fraction, the CPU oracle's throughput on a bounded sample, and short
 re-checks of the other workloads' headline figures (--no-checks skips them):
-the serving loop at rho = 1 and the cells count at its calibrated Es/N0,
-1000 TTIs each, every served TB checked against the oracle.
+the serving loop at rho = 1 (launch lanes, then ring mode) and the cells
+count at its calibrated Es/N0, 1000 TTIs each, every served TB checked
+against the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-checks]
        python bench.py --workload {tb,mixed,serving,cells} [options]
@@ -217,7 +218,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-checks", action="store_true",
-                    help="uniform workload: skip the short serving (rho = 1) and cells re-checks")
+                    help="uniform workload: skip the short serving (rho = 1, both forms) and cells "
+                         "re-checks")
     ap.add_argument("--cpu-sample", type=int, default=N_CB)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -354,7 +356,8 @@ def main():
         import bench_workloads as BW
         args.oracle_ref = None if args.no_cpu_baseline else oracle_tb_reference
         args.oracle_threads = oracle_threads()
-        log("[bench] re-checks: serving at rho = 1 and the cells count, 1000 TTIs each")
+        log("[bench] re-checks: serving at rho = 1 (launch lanes and ring mode) and the cells "
+            "count, 1000 TTIs each")
         checks = BW.default_checks(args)
         log(f"[bench] re-checks: {checks}")
 

@@ -1075,16 +1075,27 @@ CELLS_ESN0_DB = 10.585
 
 def default_checks(args, ttis=1000):
     """Short re-checks that the uniform bench adds to its line: the serving
-    loop at rho = 1 and the cells count at its calibrated Es/N0, each for
-    `ttis` TTIs with every served TB checked against the oracle."""
+    loop at rho = 1 (launch lanes, and ring mode on the same pool) and the
+    cells count at its calibrated Es/N0, each for `ttis` TTIs with every
+    served TB checked against the oracle."""
+    import copy
     out = {}
+    keys = ("p50_ms", "p99_ms", "p999_ms", "served_gbit_s", "deadline_miss", "rej_deadline",
+            "completed", "parity")
     D, pool, _, checker, lam1 = serving_setup(args)
     row = serving_row(args, D, pool, checker, lam1, 1.0, ttis)
     out["serving_rho1"] = {"workload": serving_workload_text(lam1), "ttis": ttis,
-                           **{k: row[k] for k in ("p50_ms", "p99_ms", "p999_ms", "served_gbit_s",
-                                                  "deadline_miss", "rej_deadline", "completed",
-                                                  "parity")}}
-    del pool, checker
+                           **{k: row[k] for k in keys}}
+    # ring mode: its window counts are capped at 64, so the oracle reference
+    # is taken again with the capped counts
+    D.set_max_windows(64)
+    _, ptbs, _, _, _, llr_h, lo_h = pool
+    _, checker_r = pool_checker(args, D, llr_h, lo_h, ptbs, 8, 1, "serving ring")
+    args_r = copy.copy(args)
+    args_r.mode = "ring"
+    row = serving_row(args_r, D, pool, checker_r, lam1, 1.0, ttis)
+    out["serving_ring_rho1"] = {"ttis": ttis, **{k: row[k] for k in keys}}
+    del pool, checker, checker_r
     D.close()
     D = cells_decoder(args)
     pool, _, checker = cells_pool(args, D, CELLS_ESN0_DB)
