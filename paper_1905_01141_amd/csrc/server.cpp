@@ -294,15 +294,14 @@ bool seg_of(int32_t tbs, Segm *o)
     return true;
 }
 
-// Enqueue lane L's batch on its stream: wait for the batch's slot copies
-// and (`after`, may be null) for an earlier launch's assembly, then decode +
-// transport block assembly into the lane's mapped staging, events for the
-// delays and the completion.  Returns without waiting.
-void enqueue_device(tdec_server *s, Lane &L, hipEvent_t after)
+// Lane L's batch as the decoder's arrays: payload sizes, LLR offsets in the
+// slot arena, and (into L.bo) the byte offset of each TB's bits in the
+// lane's staging; returns the copy event that covers the batch's slots.
+uint64_t batch_arrays(Lane &L, std::vector<int32_t> &tbs, std::vector<int64_t> &lo)
 {
     const int n = (int)L.b.size();
-    std::vector<int32_t> tbs(n);
-    std::vector<int64_t> lo(n);
+    tbs.resize(n);
+    lo.resize(n);
     L.bo.resize(n);
     uint64_t seq = 0;
     int64_t bytes = 0;
@@ -313,6 +312,19 @@ void enqueue_device(tdec_server *s, Lane &L, hipEvent_t after)
         bytes += (L.b[i].tbs + 7) / 8;
         seq = std::max(seq, L.b[i].copy_seq);
     }
+    return seq;
+}
+
+// Enqueue lane L's batch on its stream: wait for the batch's slot copies
+// and (`after`, may be null) for an earlier launch's assembly, then decode +
+// transport block assembly into the lane's mapped staging, events for the
+// delays and the completion.  Returns without waiting.
+void enqueue_device(tdec_server *s, Lane &L, hipEvent_t after)
+{
+    std::vector<int32_t> tbs;
+    std::vector<int64_t> lo;
+    const uint64_t seq = batch_arrays(L, tbs, lo);
+    const int n = (int)tbs.size();
     bool ok = hipStreamWaitEvent(L.st, s->copy_ev[seq % kCopyEvents], 0) == hipSuccess;
     if (after) ok = ok && hipStreamWaitEvent(L.st, after, 0) == hipSuccess;
     ok = ok && tdec::tb_decode_batch_timed(L.ctx, n, tbs.data(), lo.data(), L.bo.data(),
@@ -380,19 +392,10 @@ bool ring_launch_locked(tdec_server *s)
 // Returns without waiting for any decoding.
 void enqueue_ring(tdec_server *s, Lane &L)
 {
-    const int n = (int)L.b.size();
-    std::vector<int32_t> tbs(n);
-    std::vector<int64_t> lo(n);
-    L.bo.resize(n);
-    uint64_t seq = 0;
-    int64_t bytes = 0;
-    for (int i = 0; i < n; ++i) {
-        tbs[i] = L.b[i].tbs;
-        lo[i] = L.b[i].slot_off / 2;
-        L.bo[i] = bytes;
-        bytes += (L.b[i].tbs + 7) / 8;
-        seq = std::max(seq, L.b[i].copy_seq);
-    }
+    std::vector<int32_t> tbs;
+    std::vector<int64_t> lo;
+    const uint64_t seq = batch_arrays(L, tbs, lo);
+    const int n = (int)tbs.size();
     L.asm_enq = false;
     L.ring_n = 0;
     // the items are claimed by a kernel that is already running: everything
