@@ -221,3 +221,35 @@ def test_ring_slot_churn_matches_oracle(dev):
         srv.close()
     assert s["ring_launches"] == 1 and s["completed"] == len(tbs_list)
     check_oracle(T, D, llr, lo, tbs_list, out, res, O.params(6, 1, 0, 1))
+
+
+def test_ring_every_block_size(dev):
+    """All 188 code block sizes (one transport block of K - 24 bits each, so
+    a single block of size K) in three arrival batches through one ring
+    kernel: every QPP table, window count, LDS size and item packing of the
+    size table, each block equal to the oracle."""
+    T, D, torch = dev
+    tbs_list = [k - 24 for k in T.k_table()]
+    say(f"[ring] every block size: {len(tbs_list)} TBs")
+    esn0 = np.linspace(0.5, 4.0, len(tbs_list))
+    llr, pays, lo, bo = tb_batch(tbs_list, "qpsk", esn0, 25)
+    x = torch.from_numpy(llr).cuda()
+    torch.cuda.synchronize()
+    p = T.params(5, 1, 0, 1)
+    out = [np.zeros((t + 7) // 8, np.uint8) for t in tbs_list]
+    srv = T.Server(D, T.server_cfg(p, deadline_us=10_000_000, mode=T.SERVE_RING,
+                                   ring_idle_us=1_000_000))
+    try:
+        for grp in np.array_split(np.arange(len(tbs_list)), 3):
+            srv.submit(grp.tolist(), [tbs_list[i] for i in grp],
+                       [x.data_ptr() + 2 * int(lo[i]) for i in grp],
+                       [out[i].ctypes.data for i in grp], device=True)
+            time.sleep(0.0002)
+        srv.drain(60000)
+        res = collect(srv, len(tbs_list))
+        s = srv.stats()
+    finally:
+        srv.close()
+    assert s["completed"] == len(tbs_list)
+    assert {T.segment(t)["C"] for t in tbs_list} == {1}
+    check_oracle(T, D, llr, lo, tbs_list, out, res, O.params(5, 1, 0, 1))
